@@ -1,0 +1,443 @@
+/*
+ * CPU oracle -- TEST INFRASTRUCTURE ONLY (see sg_oracle.h).
+ *
+ * Plain reference implementation of the sweep described in the paper:
+ * checkerboard single-spin updates (sec. 3.1), Metropolis and heat bath
+ * (sec. 2.2, Eq. 4), one Parisi-Rapuano number per site update (sec. 3.3,
+ * Eq. 5), compared against integer thresholds derived on the host in double.
+ * Readings of points the paper leaves open are fixed in the project's design
+ * notes; each is restated at the place it is used.
+ */
+#include "sg_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Parisi-Rapuano wheel, Eq. (5).  The paper's "otimes" is read as a    */
+/* bitwise XOR (it describes the last step as an XOR with a third       */
+/* value).  Lags 24, 55, 61; words are 32 bits (sec. 3.3).             */
+/* ------------------------------------------------------------------ */
+
+void or_wheel_load(or_wheel *w, const uint32_t words[61]) {
+  for (int j = 0; j < 61; j++) w->ring[j] = words[j];
+  w->pos = 0; /* ring[pos] is the oldest live word, I(k-61) */
+}
+
+void or_wheel_store(const or_wheel *w, uint32_t words[61]) {
+  for (int j = 0; j < 61; j++) words[j] = w->ring[(w->pos + j) % 61];
+}
+
+/* I(k-m) lives at ring[(pos + 61 - m) % 61] for m = 1..61. */
+static uint32_t back(const or_wheel *w, int m) {
+  int j = w->pos - m;
+  return w->ring[j < 0 ? j + 61 : j];
+}
+
+uint32_t or_wheel_next(or_wheel *w) {
+  uint32_t ik = back(w, 24) + back(w, 55); /* mod 2^32 by unsigned wrap */
+  uint32_t out = ik ^ back(w, 61);
+  w->ring[w->pos] = ik; /* I(k-61) is no longer needed; I(k) takes its place */
+  w->pos = w->pos == 60 ? 0 : w->pos + 1;
+  return out;
+}
+
+void or_pr_stream(const uint32_t words[61], uint64_t n, uint32_t *out) {
+  or_wheel w;
+  or_wheel_load(&w, words);
+  for (uint64_t t = 0; t < n; t++) out[t] = or_wheel_next(&w);
+}
+
+/* ------------------------------------------------------------------ */
+/* Thresholds.  A number r in [0, 2^32) is accepted when r < T, so the   */
+/* acceptance probability is exactly T / 2^32.                          */
+/* ------------------------------------------------------------------ */
+
+static uint64_t scaled_floor(double p, int bits) { return (uint64_t)floor(ldexp(p, bits)); }
+
+void or_tables_metropolis(double beta, uint64_t T[3]) {
+  /* Flipping a spin with n unsatisfied bonds out of 6 changes the energy of
+   * Eq. (2) (x = 1, h = 0) by dE = 12 - 4n; for n >= 3 dE <= 0 and the move is
+   * always accepted, otherwise with probability exp(-beta dE) (sec. 2.2). */
+  for (int n = 0; n < 3; n++) T[n] = scaled_floor(exp(-beta * (double)(12 - 4 * n)), 32);
+}
+
+void or_tables_heatbath(double beta, uint64_t T[7]) {
+  /* Eq. (4) with E(+-1) = -+h, h = sum_j J_ij s_j = 2k - 6. */
+  for (int k = 0; k < 7; k++) {
+    double h = (double)(2 * k - 6);
+    T[k] = scaled_floor(1.0 / (1.0 + exp(-2.0 * beta * h)), 32);
+  }
+}
+
+void or_tables_potts(double beta, uint64_t W[13]) {
+  for (int d = 0; d < 13; d++) W[d] = scaled_floor(exp(-beta * (double)d), 28);
+}
+
+void or_tables_pt(double beta_a, double beta_b, uint64_t F[24]) {
+  double db = fabs(beta_a - beta_b);
+  for (int b = 0; b < 24; b++) F[b] = scaled_floor(exp(-db * ldexp(1.0, b)), 32);
+}
+
+uint64_t or_pt_threshold(const uint64_t F[24], uint64_t absD) {
+  if (absD >> 24) return 0;
+  uint64_t T = (uint64_t)1 << 32;
+  for (int b = 0; b < 24; b++)
+    if ((absD >> b) & 1) T = (uint64_t)(((unsigned __int128)T * F[b]) >> 32);
+  return T;
+}
+
+/* ------------------------------------------------------------------ */
+/* Lattice: periodic L^3, i = x + L (y + L z); J[d][i] joins i, i + e_d. */
+/* ------------------------------------------------------------------ */
+
+static void neighbours_xyz(int32_t L, int64_t x, int64_t y, int64_t z, int64_t nb[6],
+                           int64_t bond[6]) {
+  int64_t N = (int64_t)L * L * L;
+  int64_t i = x + L * (y + L * z);
+  int64_t xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
+  int64_t yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+  int64_t zp = z + 1 == L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
+  nb[0] = xp + L * (y + L * z);
+  nb[1] = xm + L * (y + L * z);
+  nb[2] = x + L * (yp + L * z);
+  nb[3] = x + L * (ym + L * z);
+  nb[4] = x + L * (y + L * zp);
+  nb[5] = x + L * (y + L * zm);
+  bond[0] = 0 * N + i;      /* bond to +x belongs to i          */
+  bond[1] = 0 * N + nb[1];  /* bond to -x belongs to the -x site */
+  bond[2] = 1 * N + i;
+  bond[3] = 1 * N + nb[3];
+  bond[4] = 2 * N + i;
+  bond[5] = 2 * N + nb[5];
+}
+
+static void neighbours(int32_t L, int64_t i, int64_t nb[6], int64_t bond[6]) {
+  neighbours_xyz(L, i % L, (i / L) % L, i / ((int64_t)L * L), nb, bond);
+}
+
+static int32_t ising_update(int32_t algo, int8_t *s, const int8_t *J, int64_t i,
+                            const int64_t nb[6], const int64_t bond[6], uint32_t r,
+                            const uint64_t *T) {
+  int32_t h = 0; /* local field sum_j J_ij s_j */
+  int32_t n = 0; /* unsatisfied bonds: J s_i s_j = -1 */
+  for (int d = 0; d < 6; d++) {
+    int32_t js = J[bond[d]] * s[nb[d]];
+    h += js;
+    if (js * s[i] == -1) n++;
+  }
+  int32_t old = s[i];
+  if (algo == OR_METROPOLIS) {
+    /* flip if dE <= 0 (n >= 3) or r < T[n]; e^0 = 1 at n = 3 */
+    if (n >= 3 || (uint64_t)r < T[n]) {
+      s[i] = (int8_t)(-old);
+      return 2 * old * h; /* = 12 - 4n */
+    }
+    return 0;
+  }
+  /* heat bath: s = +1 with probability T[k] / 2^32, k = (h + 6) / 2 */
+  int32_t k = (h + 6) / 2;
+  int32_t nw = ((uint64_t)r < T[k]) ? 1 : -1;
+  s[i] = (int8_t)nw;
+  return -(nw - old) * h;
+}
+
+static int32_t potts_update(uint8_t *s, const int8_t *J, int64_t i, const int64_t nb[6],
+                            const int64_t bond[6], uint32_t r, const uint64_t W[13]) {
+  int32_t h[4] = {0, 0, 0, 0}; /* h_a = sum_j J_ij delta(a, s_j) */
+  for (int d = 0; d < 6; d++) h[s[nb[d]]] += J[bond[d]];
+  int32_t hmax = h[0];
+  for (int a = 1; a < 4; a++)
+    if (h[a] > hmax) hmax = h[a];
+  /* Boltzmann weight of state a relative to the best one: exp(-beta (hmax - h_a)) */
+  uint64_t w[4], S = 0;
+  for (int a = 0; a < 4; a++) {
+    w[a] = W[hmax - h[a]];
+    S += w[a];
+  }
+  uint64_t t = ((uint64_t)r * S) >> 32; /* uniform on [0, S) up to rounding */
+  uint64_t cum = 0;
+  int32_t nw = 3;
+  for (int a = 0; a < 4; a++) {
+    cum += w[a];
+    if (t < cum) {
+      nw = a;
+      break;
+    }
+  }
+  int32_t old = s[i];
+  s[i] = (uint8_t)nw;
+  return -(h[nw] - h[old]);
+}
+
+int32_t or_ising_update_site(int32_t L, int32_t algo, int8_t *s, const int8_t *J,
+                             int64_t i, uint32_t r, const uint64_t *T) {
+  int64_t nb[6], bond[6];
+  neighbours(L, i, nb, bond);
+  return ising_update(algo, s, J, i, nb, bond, r, T);
+}
+
+int32_t or_potts_update_site(int32_t L, uint8_t *s, const int8_t *J, int64_t i, uint32_t r,
+                             const uint64_t W[13]) {
+  int64_t nb[6], bond[6];
+  neighbours(L, i, nb, bond);
+  return potts_update(s, J, i, nb, bond, r, W);
+}
+
+int64_t or_ising_energy(int32_t L, const int8_t *s, const int8_t *J) {
+  int64_t N = (int64_t)L * L * L, E = 0;
+  for (int64_t i = 0; i < N; i++) {
+    int64_t nb[6], bond[6];
+    neighbours(L, i, nb, bond);
+    for (int d = 0; d < 6; d += 2) E -= (int64_t)J[bond[d]] * s[i] * s[nb[d]];
+  }
+  return E;
+}
+
+int64_t or_potts_energy(int32_t L, const uint8_t *s, const int8_t *J) {
+  int64_t N = (int64_t)L * L * L, E = 0;
+  for (int64_t i = 0; i < N; i++) {
+    int64_t nb[6], bond[6];
+    neighbours(L, i, nb, bond);
+    for (int d = 0; d < 6; d += 2)
+      if (s[i] == s[nb[d]]) E -= J[bond[d]];
+  }
+  return E;
+}
+
+int64_t or_ising_overlap(int32_t L, const int8_t *a, const int8_t *b) {
+  int64_t N = (int64_t)L * L * L, Q = 0;
+  for (int64_t i = 0; i < N; i++) Q += (int64_t)a[i] * b[i];
+  return Q;
+}
+
+int64_t or_potts_overlap(int32_t L, const uint8_t *a, const uint8_t *b) {
+  int64_t N = (int64_t)L * L * L, Q = 0;
+  for (int64_t i = 0; i < N; i++) Q += (a[i] == b[i]);
+  return Q;
+}
+
+int32_t or_wheels_per_copy(int32_t L) {
+  int32_t rho = L < 8 ? L : 8;
+  return L * (L / rho);
+}
+
+/* ------------------------------------------------------------------ */
+/* One sweep of one copy.  Colour p = (x + y + z) mod 2; the even colour */
+/* is updated first (sec. 3.1: all sites of one colour, then the other). */
+/* Wheel w = g L + z serves rows y = g rho .. g rho + rho - 1 of plane z, */
+/* drawing one number per visited site in the order: colour, then row,   */
+/* then increasing x.  Every visit consumes exactly one number.          */
+/* ------------------------------------------------------------------ */
+
+static void copy_sweep(const or_spec *sp, void *spins, const int8_t *J, or_wheel *wheels,
+                       const uint64_t *T, int64_t *E) {
+  int32_t L = sp->L, rho = L < 8 ? L : 8, nG = L / rho;
+  for (int p = 0; p < 2; p++)
+    for (int g = 0; g < nG; g++)
+      for (int z = 0; z < L; z++) {
+        or_wheel *w = &wheels[g * L + z];
+        for (int y = g * rho; y < g * rho + rho; y++)
+          for (int x = 0; x < L; x++) {
+            if (((x + y + z) & 1) != p) continue;
+            uint32_t r = or_wheel_next(w);
+            int64_t i = x + (int64_t)L * (y + (int64_t)L * z);
+            int64_t nb[6], bond[6];
+            neighbours_xyz(L, x, y, z, nb, bond);
+            if (sp->model == OR_ISING)
+              *E += ising_update(sp->algo, (int8_t *)spins, J, i, nb, bond, r, T);
+            else
+              *E += potts_update((uint8_t *)spins, J, i, nb, bond, r, T);
+          }
+      }
+}
+
+static int64_t copy_energy(const or_spec *sp, const void *spins, const int8_t *J) {
+  if (sp->model == OR_ISING) return or_ising_energy(sp->L, (const int8_t *)spins, J);
+  return or_potts_energy(sp->L, (const uint8_t *)spins, J);
+}
+
+static void copy_tables(const or_spec *sp, double beta, uint64_t T[13]) {
+  if (sp->model == OR_POTTS)
+    or_tables_potts(beta, T);
+  else if (sp->algo == OR_METROPOLIS)
+    or_tables_metropolis(beta, T);
+  else
+    or_tables_heatbath(beta, T);
+}
+
+typedef struct {
+  const or_spec *sp;
+  const double *betas;
+  const int8_t *J;
+  uint8_t *spins;
+  or_wheel *wheels;
+  const int32_t *temp_of_slot;
+  int64_t *E;
+  uint64_t nsw;
+  int64_t c_begin, c_end;
+  int32_t err;
+} worker_arg;
+
+#include <pthread.h>
+
+static void *sweep_worker(void *p) {
+  worker_arg *a = (worker_arg *)p;
+  const or_spec *sp = a->sp;
+  int64_t N = (int64_t)sp->L * sp->L * sp->L;
+  int32_t NW = or_wheels_per_copy(sp->L);
+  int64_t RK = (int64_t)sp->n_replicas * sp->n_temps;
+  for (int64_t c = a->c_begin; c < a->c_end; c++) {
+    const int8_t *Jc = a->J + (c / RK) * 3 * N;
+    uint8_t *sc = a->spins + c * N;
+    uint64_t T[13];
+    copy_tables(sp, a->betas[a->temp_of_slot[c]], T);
+    for (uint64_t t = 0; t < a->nsw; t++) {
+      copy_sweep(sp, sc, Jc, a->wheels + c * NW, T, &a->E[c]);
+      if (sp->check_energy && a->E[c] != copy_energy(sp, sc, Jc)) {
+        a->err = OR_ENERGY_MISMATCH;
+        return NULL;
+      }
+    }
+  }
+  return NULL;
+}
+
+static int32_t sweep_all(const or_spec *sp, const double *betas, const int8_t *J, uint8_t *spins,
+                         or_wheel *wheels, const int32_t *temp_of_slot, int64_t *E, uint64_t nsw) {
+  int64_t C = (int64_t)sp->n_samples * sp->n_replicas * sp->n_temps;
+  int nt = sp->n_threads > 0 ? sp->n_threads : 1;
+  if (nt > C) nt = (int)C;
+  worker_arg args[256];
+  pthread_t th[256];
+  if (nt > 256) nt = 256;
+  for (int t = 0; t < nt; t++) {
+    args[t] = (worker_arg){sp, betas, J, spins, wheels, temp_of_slot, E, nsw,
+                           C * t / nt, C * (t + 1) / nt, 0};
+  }
+  for (int t = 1; t < nt; t++) pthread_create(&th[t], NULL, sweep_worker, &args[t]);
+  sweep_worker(&args[0]);
+  for (int t = 1; t < nt; t++) pthread_join(th[t], NULL);
+  for (int t = 0; t < nt; t++)
+    if (args[t].err) return args[t].err;
+  return OR_OK;
+}
+
+/* Parallel tempering (only named in sec. 2.2).  Reading used here: for
+ * every (sample, replica) chain, pairs of neighbouring temperatures
+ * i = 0..K-2 in ascending order; slots keep their configuration and wheels
+ * and exchange temperatures; the swap is accepted with probability
+ * min(1, exp((beta_i - beta_{i+1}) (E_a - E_b))) evaluated as an integer
+ * threshold; one number of the chain's own wheel per pair, always drawn. */
+static void pt_step(const or_spec *sp, const double *betas, or_wheel *ptw, int32_t *sot,
+                    const int64_t *E, uint64_t *acc) {
+  int32_t K = sp->n_temps;
+  int64_t chains = (int64_t)sp->n_samples * sp->n_replicas;
+  for (int64_t ch = 0; ch < chains; ch++) {
+    int32_t *so = sot + ch * K;
+    for (int i = 0; i + 1 < K; i++) {
+      int64_t a = ch * K + so[i], b = ch * K + so[i + 1];
+      int64_t D = E[b] - E[a];
+      double dbeta = betas[i] - betas[i + 1];
+      uint32_t r = or_wheel_next(&ptw[ch]);
+      int accept;
+      if (dbeta * (double)D <= 0.0) {
+        accept = 1;
+      } else {
+        uint64_t F[24];
+        or_tables_pt(betas[i], betas[i + 1], F);
+        uint64_t absD = (uint64_t)(D < 0 ? -D : D);
+        accept = (uint64_t)r < or_pt_threshold(F, absD);
+      }
+      if (accept) {
+        int32_t t = so[i];
+        so[i] = so[i + 1];
+        so[i + 1] = t;
+        if (acc) acc[ch * (K - 1) + i]++;
+      }
+    }
+  }
+}
+
+static void measure(const or_spec *sp, const int8_t *J, const uint8_t *spins, const int32_t *sot,
+                    const int64_t *E, int64_t *E_log, int64_t *Q_log) {
+  (void)J;
+  int64_t N = (int64_t)sp->L * sp->L * sp->L;
+  int32_t S = sp->n_samples, R = sp->n_replicas, K = sp->n_temps;
+  if (E_log)
+    for (int64_t ch = 0; ch < (int64_t)S * R; ch++)
+      for (int k = 0; k < K; k++) E_log[ch * K + k] = E[ch * K + sot[ch * K + k]];
+  if (!Q_log || R < 2) return;
+  for (int s = 0; s < S; s++)
+    for (int k = 0; k < K; k++) {
+      int64_t ca = ((int64_t)s * R + 0) * K + sot[((int64_t)s * R + 0) * K + k];
+      int64_t cb = ((int64_t)s * R + 1) * K + sot[((int64_t)s * R + 1) * K + k];
+      Q_log[(int64_t)s * K + k] =
+          sp->model == OR_ISING
+              ? or_ising_overlap(sp->L, (const int8_t *)spins + ca * N, (const int8_t *)spins + cb * N)
+              : or_potts_overlap(sp->L, spins + ca * N, spins + cb * N);
+    }
+}
+
+static int valid_L(int32_t L) { return L == 2 || L == 4 || (L >= 8 && L % 8 == 0); }
+
+int32_t or_run(const or_spec *sp, const double *betas, const int8_t *J, void *spins_v,
+               uint32_t *wheels_words, uint32_t *ptwheels_words, int32_t *slot_of_temp,
+               uint64_t sweeps_done, uint64_t n_sweeps, int64_t *E_out, int64_t *E_log,
+               int64_t *Q_log, uint64_t *pt_accepts) {
+  if (!sp || !valid_L(sp->L) || sp->n_samples < 1 || sp->n_replicas < 1 || sp->n_temps < 1)
+    return OR_EINVAL;
+  if (sp->model != OR_ISING && sp->model != OR_POTTS) return OR_EINVAL;
+  if (sp->model == OR_POTTS && sp->algo != OR_HEATBATH) return OR_EINVAL;
+  uint8_t *spins = (uint8_t *)spins_v;
+  int64_t N = (int64_t)sp->L * sp->L * sp->L;
+  int32_t NW = or_wheels_per_copy(sp->L);
+  int32_t K = sp->n_temps;
+  int64_t chains = (int64_t)sp->n_samples * sp->n_replicas;
+  int64_t C = chains * K;
+
+  or_wheel *wheels = (or_wheel *)malloc(sizeof(or_wheel) * C * NW);
+  or_wheel *ptw = (or_wheel *)malloc(sizeof(or_wheel) * (chains > 0 ? chains : 1));
+  int32_t *tos = (int32_t *)malloc(sizeof(int32_t) * C);
+  int64_t *E = (int64_t *)malloc(sizeof(int64_t) * C);
+  for (int64_t w = 0; w < C * NW; w++) or_wheel_load(&wheels[w], wheels_words + w * 61);
+  if (sp->pt_every > 0)
+    for (int64_t ch = 0; ch < chains; ch++) or_wheel_load(&ptw[ch], ptwheels_words + ch * 61);
+  for (int64_t c = 0; c < C; c++) E[c] = copy_energy(sp, spins + c * N, J + (c / K / sp->n_replicas) * 3 * N);
+
+  int32_t rc = OR_OK;
+  uint64_t t = 0, n_meas = 0;
+  while (t < n_sweeps) {
+    uint64_t nsw = n_sweeps - t;
+    if (sp->pt_every > 0) {
+      uint64_t until = sp->pt_every - (sweeps_done + t) % sp->pt_every;
+      if (until < nsw) nsw = until;
+    }
+    if (sp->measure_every > 0) {
+      uint64_t until = sp->measure_every - t % sp->measure_every;
+      if (until < nsw) nsw = until;
+    }
+    for (int64_t ch = 0; ch < chains; ch++)
+      for (int k = 0; k < K; k++) tos[ch * K + slot_of_temp[ch * K + k]] = k;
+    rc = sweep_all(sp, betas, J, spins, wheels, tos, E, nsw);
+    if (rc != OR_OK) break;
+    t += nsw;
+    if (sp->pt_every > 0 && (sweeps_done + t) % sp->pt_every == 0)
+      pt_step(sp, betas, ptw, slot_of_temp, E, pt_accepts);
+    if (sp->measure_every > 0 && t % sp->measure_every == 0) {
+      measure(sp, J, spins, slot_of_temp, E, E_log ? E_log + n_meas * C : NULL,
+              Q_log ? Q_log + n_meas * sp->n_samples * K : NULL);
+      n_meas++;
+    }
+  }
+  for (int64_t w = 0; w < C * NW; w++) or_wheel_store(&wheels[w], wheels_words + w * 61);
+  if (sp->pt_every > 0)
+    for (int64_t ch = 0; ch < chains; ch++) or_wheel_store(&ptw[ch], ptwheels_words + ch * 61);
+  if (E_out) memcpy(E_out, E, sizeof(int64_t) * C);
+  free(wheels);
+  free(ptw);
+  free(tos);
+  free(E);
+  return rc;
+}

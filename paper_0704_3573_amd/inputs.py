@@ -1,0 +1,155 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the HIP path.
+
+This module holds no Monte Carlo arithmetic.  It only turns a 64-bit seed
+into the quenched disorder, the initial configurations and the external
+random values that initialise every Parisi-Rapuano wheel (the paper's
+section 3.3 says the wheels are loaded with externally generated random
+values; section 2.1 defines +-1 couplings for the Edwards-Anderson glass).
+
+Generator: SplitMix64 (Steele, Lea and Flood, 2014), used as a counter-based
+stream.  Output u of a stream with key K is mix64(K + (u+1) * GOLDEN), where
+mix64 is the SplitMix64 finaliser.  Stream keys are derived from
+(seed, tag, a, b) by the same finaliser, so every array is a pure function of
+its indices and can be regenerated piecewise.
+
+Encodings (canonical, host side):
+  * site index i = x + L*(y + L*z), periodic cubic lattice of side L;
+  * couplings J: int8 array [3][N], J[d][i] joins i and i + e_d (d = x, y, z);
+    bit b of stream output u gives element 64*u + b, bit 1 -> -1;
+  * Ising spins: int8 +-1, same bit rule;  Potts spins: uint8 0..3, two bits
+    per site (bits 2k, 2k+1 of the stream word, little end first);
+  * wheel seeds: 61 uint32 words per wheel, oldest first, I(-61) .. I(-1),
+    each the high 32 bits of one stream output; bit 0 of I(-1) is forced to 1
+    so the low-bit lagged-Fibonacci sequence is never all even.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+TAG_J = 0x4A  # 'J' couplings
+TAG_S = 0x53  # 'S' initial spins
+TAG_W = 0x57  # 'W' sweep wheels
+TAG_P = 0x50  # 'P' parallel-tempering wheels
+
+
+def mix64(z):
+    """SplitMix64 finaliser on uint64 numpy values (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def stream_key(seed: int, tag: int, a=0, b=0):
+    """Key of the stream (seed, tag, a, b); a and b may be numpy arrays."""
+    with np.errstate(over="ignore"):
+        k = mix64(np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + np.uint64(tag) * GOLDEN)
+        k = mix64(k ^ (np.asarray(a, dtype=np.uint64) + np.uint64(1)) * _M1)
+        k = mix64(k ^ (np.asarray(b, dtype=np.uint64) + np.uint64(1)) * _M2)
+    return k
+
+
+def stream(key, n: int):
+    """n outputs of each stream in `key` (shape key.shape + (n,))."""
+    key = np.asarray(key, dtype=np.uint64)
+    u = np.arange(1, n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return mix64(key[..., None] + u * GOLDEN)
+
+
+def _bits(key, nbits: int):
+    words = stream(key, (nbits + 63) // 64)
+    shifts = np.arange(64, dtype=np.uint64)
+    bits = (words[..., :, None] >> shifts) & np.uint64(1)
+    return bits.reshape(bits.shape[:-2] + (-1,))[..., :nbits].astype(np.uint8)
+
+
+def couplings(seed: int, sample: int, L: int) -> np.ndarray:
+    """int8 [3][L^3] +-1 couplings of one disorder sample (iid, p = 1/2)."""
+    n = L ** 3
+    b = _bits(stream_key(seed, TAG_J, sample), 3 * n)
+    return (1 - 2 * b.astype(np.int8)).reshape(3, n)
+
+
+def ising_spins(seed: int, copies, L: int) -> np.ndarray:
+    """int8 [len(copies)][L^3] iid +-1 initial spins."""
+    copies = np.atleast_1d(np.asarray(copies, dtype=np.uint64))
+    b = _bits(stream_key(seed, TAG_S, copies), L ** 3)
+    return (1 - 2 * b.astype(np.int8))
+
+
+def potts_spins(seed: int, copies, L: int, q: int = 4) -> np.ndarray:
+    """uint8 [len(copies)][L^3] iid initial Potts states in 0..3 (q = 4)."""
+    if q != 4:
+        raise ValueError("only q = 4 has a two-bit encoding")
+    copies = np.atleast_1d(np.asarray(copies, dtype=np.uint64))
+    b = _bits(stream_key(seed, TAG_S, copies), 2 * L ** 3)
+    b = b.reshape(b.shape[:-1] + (L ** 3, 2))
+    return (b[..., 0] | (b[..., 1] << 1)).astype(np.uint8)
+
+
+def _wheel_words(seed: int, tag: int, a, b):
+    w = (stream(stream_key(seed, tag, a, b), 61) >> np.uint64(32)).astype(np.uint32)
+    w[..., 60] |= np.uint32(1)
+    return w
+
+
+def wheel_seeds(seed: int, copies, n_wheels: int) -> np.ndarray:
+    """uint32 [len(copies)][n_wheels][61]: I(-61)..I(-1) of every sweep wheel."""
+    copies = np.atleast_1d(np.asarray(copies, dtype=np.uint64))
+    w = np.arange(n_wheels, dtype=np.uint64)
+    return _wheel_words(seed, TAG_W, copies[:, None], w[None, :])
+
+
+def pt_wheel_seeds(seed: int, chains) -> np.ndarray:
+    """uint32 [len(chains)][61]: seed words of each parallel-tempering wheel."""
+    chains = np.atleast_1d(np.asarray(chains, dtype=np.uint64))
+    return _wheel_words(seed, TAG_P, chains, 0)
+
+
+def rho(L: int) -> int:
+    """Rows of one z-plane served by one wheel: min(8, L)."""
+    return min(8, L)
+
+
+def wheels_per_copy(L: int) -> int:
+    """One wheel per (z, group of rho rows): L * L / rho."""
+    return L * (L // rho(L))
+
+
+def make_instance(model: str, L: int, n_samples: int, n_replicas: int,
+                  n_temps: int, seed: int, sample0: int = 0):
+    """All inputs of one job: couplings, spins, sweep wheels, PT wheels.
+
+    Copy (slot) c = (s * R + r) * K + k for sample s, replica r, slot k.
+    Samples are numbered from `sample0` so that one large campaign can be
+    split into several jobs without changing any sample's inputs.
+    """
+    S, R, K = n_samples, n_replicas, n_temps
+    C = S * R * K
+    J = np.stack([couplings(seed, sample0 + s, L) for s in range(S)])
+    glob = np.arange(C, dtype=np.uint64) + np.uint64(sample0 * R * K)
+    if model == "ising":
+        sp = ising_spins(seed, glob, L)
+    elif model == "potts":
+        sp = potts_spins(seed, glob, L)
+    else:
+        raise ValueError(model)
+    wh = wheel_seeds(seed, glob, wheels_per_copy(L))
+    chains = np.arange(S * R, dtype=np.uint64) + np.uint64(sample0 * R)
+    pw = pt_wheel_seeds(seed, chains)
+    return {"J": np.ascontiguousarray(J), "spins": np.ascontiguousarray(sp),
+            "wheels": np.ascontiguousarray(wh), "ptwheels": np.ascontiguousarray(pw)}
+
+
+def linear_temperatures(K: int, t_min: float = 0.7, t_max: float = 1.6) -> np.ndarray:
+    """Temperatures t_min + (t_max - t_min) * i / (K - 1), i = 0..K-1."""
+    if K == 1:
+        return np.array([t_min])
+    i = np.arange(K, dtype=np.float64)
+    return t_min + (t_max - t_min) * i / (K - 1)
