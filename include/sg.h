@@ -1,0 +1,165 @@
+/*
+ * sg.h -- C-ABI of the MI355X (gfx950) checkerboard spin-glass sweep library
+ * (libsg.so).
+ *
+ * Method: Belletti et al., "Simulating spin systems on IANUS, an FPGA-based
+ * computer" (arXiv 0704.3573).  Single-spin Metropolis and heat-bath dynamics
+ * (sec. 2.2, Eq. 4) of the 3D Edwards-Anderson +-J Ising glass (Eq. 2 with
+ * x = 1, h = 0, sec. 2.1) and of the q = 4 +-J Potts glass
+ * H = -sum J_ij delta(s_i, s_j), updated colour by colour on the bipartite
+ * lattice (sec. 3.1), every site update consuming one Parisi-Rapuano number
+ * (sec. 3.3, Eq. 5) compared with an integer threshold.  Parallel tempering,
+ * which sec. 2.2 names as an add-on, swaps temperatures between slots.
+ *
+ * Conventions (canonical host formats), shared with the project's CPU oracle:
+ *   - cubic periodic lattice of side L, site i = x + L*(y + L*z), N = L^3;
+ *   - colour p = (x + y + z) mod 2, colour 0 is updated first;
+ *   - a job has S samples, R replicas, K temperature slots; copy (slot)
+ *     c = (s*R + r)*K + k, C = S*R*K copies;
+ *   - couplings int8 [S][3][N], J[s][d][i] (+1/-1) joins i and i + e_d;
+ *   - Ising spins int8 +1/-1, Potts spins uint8 0..3, [C][N];
+ *   - sweep wheels uint32 [C][NW][61] with NW = L * L / min(8, L) (one per
+ *     plane z and group of min(8, L) rows, index g*L + z), words I(k-61) ..
+ *     I(k-1) oldest first; parallel-tempering wheels uint32 [S*R][61];
+ *   - slot_of_temp int32 [S*R][K]: slot holding temperature index k;
+ *   - energies and overlaps int64.
+ * Which random number feeds which site: wheel (c, z, g) serves rows
+ * y = g*rho .. g*rho + rho - 1 (rho = min(8, L)) of plane z and draws, in every
+ * sweep, colour 0 then colour 1, rows ascending, x ascending, one number per
+ * visited site.
+ *
+ * Errors: every call returns SG_OK (0) or a negative SG_E_* code; the message
+ * of the last error on the calling thread is returned by sg_last_error().  No
+ * C++ exception crosses this boundary.  Device errors raised asynchronously
+ * surface at the next call that synchronises.
+ *
+ * Ownership: handles are created and released by the library.  Device memory
+ * of a job (its "arena") is owned by the caller: ask sg_job_bytes(), allocate
+ * that many bytes on the device (for example a torch uint8 tensor) and pass
+ * the pointer; it must stay valid until sg_job_destroy().  Host arrays are
+ * owned by the caller and only read (or written) during the call.  Streams
+ * are hipStream_t values passed as void* (NULL = the default stream); all
+ * work is stream ordered, calls marked (sync) wait for it.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_OK 0
+#define SG_E_INVALID (-1)     /* bad argument or specification              */
+#define SG_E_UNSUPPORTED (-2) /* lattice size / model not built             */
+#define SG_E_NOMEM (-3)       /* arena (or budget) too small                */
+#define SG_E_HIP (-4)         /* the HIP runtime reported an error          */
+#define SG_E_STATE (-5)       /* call not valid in the current state        */
+
+#define SG_ISING 0
+#define SG_POTTS 1
+#define SG_METROPOLIS 0
+#define SG_HEATBATH 1
+
+typedef struct sg_ctx sg_ctx;
+typedef struct sg_job sg_job;
+typedef struct sg_batch sg_batch;
+
+typedef struct sg_job_spec {
+  int32_t model;      /* SG_ISING or SG_POTTS                                  */
+  int32_t algo;       /* SG_METROPOLIS or SG_HEATBATH (Potts: heat bath only)   */
+  int32_t q;          /* Potts states, must be 4 (ignored for Ising)            */
+  int32_t L;          /* 2, 4, 8, 16, 24, 32, 40, 48, 56, 64 (Potts: <= 48)     */
+  int32_t n_samples;  /* S >= 1                                                 */
+  int32_t n_replicas; /* R >= 1 (overlaps need R >= 2)                          */
+  int32_t n_temps;    /* K >= 1                                                 */
+  int32_t pt_every;   /* sweeps between parallel-tempering steps, 0 = none      */
+} sg_job_spec;
+
+/* Message of the last error on this thread ("" if none). */
+const char *sg_last_error(void);
+
+/* Number of sweep wheels per copy for side L (0 if L is not supported). */
+int32_t sg_wheels_per_copy(int32_t L);
+
+/* Bind a context to HIP device `device`. */
+int sg_ctx_create(int device, sg_ctx **out);
+int sg_ctx_destroy(sg_ctx *ctx);
+
+/* Device bytes needed by a job with this specification. */
+int sg_job_bytes(const sg_job_spec *spec, uint64_t *bytes);
+
+/*
+ * Create a job in the caller's device arena and upload its state (blocks
+ * until the upload has finished).
+ *   betas         [K] inverse temperatures >= 0, by temperature index;
+ *   J             [S][3][N] int8;  spins [C][N] int8 or uint8;
+ *   wheels        [C][NW][61];      ptwheels [S*R][61] (may be NULL if
+ *                 pt_every == 0);
+ *   slot_of_temp  [S*R][K] or NULL (identity);
+ *   sweeps_done   sweeps already performed by this state (0 for a new job;
+ *                 used to resume from exported state).
+ * SG_E_NOMEM if arena_bytes < sg_job_bytes(); SG_E_UNSUPPORTED for L or a
+ * model that is not built; SG_E_INVALID for inconsistent inputs.
+ */
+int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, const int8_t *J,
+                  const void *spins, const uint32_t *wheels, const uint32_t *ptwheels,
+                  const int32_t *slot_of_temp, uint64_t sweeps_done, void *d_arena,
+                  uint64_t arena_bytes, void *stream, sg_job **out);
+
+/* Replace the K inverse temperatures (rebuilds the integer tables). (sync) */
+int sg_job_set_betas(sg_job *job, const double *betas, void *stream);
+
+/* Run n sweeps of every copy, with parallel-tempering steps after every
+ * multiple of pt_every sweeps (counted since the start of the job). */
+int sg_job_sweep(sg_job *job, uint64_t n_sweeps, void *stream);
+
+/* Energy of every copy by chain and temperature index, E[(s*R + r)*K + k]
+ * (may be NULL), and overlap of replicas 0 and 1 at every temperature,
+ * Q[s*K + k] (may be NULL; needs R >= 2): Ising sum_i s^a_i s^b_i, Potts number
+ * of equal sites. (sync) */
+int sg_job_measure(sg_job *job, int64_t *E, int64_t *Q, void *stream);
+
+/* Energy of every slot (copy order), as left by the last sweep or measure. (sync) */
+int sg_job_energies(sg_job *job, int64_t *E_slot, void *stream);
+
+/* Canonical export of the state. (sync) */
+int sg_job_get_spins(sg_job *job, void *spins_out /* [C][N] */, void *stream);
+int sg_job_get_wheels(sg_job *job, uint32_t *wheels_out /* [C][NW][61] */,
+                      uint32_t *ptwheels_out /* [S*R][61] or NULL */, void *stream);
+int sg_job_get_perm(sg_job *job, int32_t *slot_of_temp_out /* [S*R][K] */, void *stream);
+/* Accepted parallel-tempering swaps per (chain, pair), [S*R][K-1]. (sync) */
+int sg_job_get_pt_accepts(sg_job *job, uint64_t *out, void *stream);
+/* Sweeps performed so far. */
+int sg_job_sweeps_done(const sg_job *job, uint64_t *out);
+
+/* Test hook: the next n (<= 4096) numbers of sweep wheel `wheel` of copy
+ * `copy`, computed on the device; the job's state is not advanced. (sync) */
+int sg_job_debug_rng(sg_job *job, int32_t copy, int32_t wheel, uint32_t n, uint32_t *out,
+                     void *stream);
+
+int sg_job_destroy(sg_job *job);
+
+/*
+ * Batches: many jobs (mixed L, models, temperatures) advanced together by one
+ * fused sweep launch per period, replayed from a captured hipGraph.  Jobs can
+ * be added and removed between runs (continuous batching); a job's results do
+ * not depend on the batch it runs in.
+ */
+int sg_batch_create(sg_ctx *ctx, sg_batch **out);
+int sg_batch_add(sg_batch *b, sg_job *job);
+int sg_batch_remove(sg_batch *b, sg_job *job);
+/* Threads per workgroup of the fused launch (multiple of 64, <= 1024;
+ * 0 = automatic).  Results do not depend on it. */
+int sg_batch_set_block(sg_batch *b, int32_t threads);
+/* Advance every job of the batch by n sweeps (parallel tempering included). */
+int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream);
+/* Threads per workgroup chosen for the current membership. */
+int sg_batch_block(sg_batch *b, int32_t *threads);
+int sg_batch_destroy(sg_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,275 @@
+"""ctypes binding of libsg.so (include/sg.h): argument marshalling only.
+
+PyTorch supplies device memory (a uint8 tensor per job arena) and streams
+(``torch.cuda.Stream.cuda_stream``); every step of the sweep runs in the
+library's HIP kernels.  If the library has not been built this module raises
+on first use: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsg.so")
+
+ISING, POTTS = 0, 1
+METROPOLIS, HEATBATH = 0, 1
+
+SG_OK, SG_E_INVALID, SG_E_UNSUPPORTED, SG_E_NOMEM, SG_E_HIP, SG_E_STATE = 0, -1, -2, -3, -4, -5
+
+# every symbol declared in include/sg.h
+EXPORTS = (
+    "sg_last_error", "sg_wheels_per_copy", "sg_ctx_create", "sg_ctx_destroy", "sg_job_bytes",
+    "sg_job_create", "sg_job_set_betas", "sg_job_sweep", "sg_job_measure", "sg_job_energies",
+    "sg_job_get_spins", "sg_job_get_wheels", "sg_job_get_perm", "sg_job_get_pt_accepts",
+    "sg_job_sweeps_done", "sg_job_debug_rng", "sg_job_destroy", "sg_batch_create",
+    "sg_batch_add", "sg_batch_remove", "sg_batch_set_block", "sg_batch_run", "sg_batch_block",
+    "sg_batch_destroy",
+)
+
+
+class SgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsg error {code}: {msg}")
+        self.code = code
+
+
+class Spec(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in (
+        "model", "algo", "q", "L", "n_samples", "n_replicas", "n_temps", "pt_every")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, i32 = C.c_void_p, C.c_uint64, C.c_int32
+        L.sg_last_error.restype = C.c_char_p
+        L.sg_wheels_per_copy.argtypes = [i32]
+        L.sg_wheels_per_copy.restype = i32
+        L.sg_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.sg_ctx_destroy.argtypes = [vp]
+        L.sg_job_bytes.argtypes = [C.POINTER(Spec), C.POINTER(u64)]
+        L.sg_job_create.argtypes = [vp, C.POINTER(Spec), vp, vp, vp, vp, vp, vp, u64, vp, u64, vp,
+                                    C.POINTER(vp)]
+        L.sg_job_set_betas.argtypes = [vp, vp, vp]
+        L.sg_job_sweep.argtypes = [vp, u64, vp]
+        L.sg_job_measure.argtypes = [vp, vp, vp, vp]
+        L.sg_job_energies.argtypes = [vp, vp, vp]
+        L.sg_job_get_spins.argtypes = [vp, vp, vp]
+        L.sg_job_get_wheels.argtypes = [vp, vp, vp, vp]
+        L.sg_job_get_perm.argtypes = [vp, vp, vp]
+        L.sg_job_get_pt_accepts.argtypes = [vp, vp, vp]
+        L.sg_job_sweeps_done.argtypes = [vp, C.POINTER(u64)]
+        L.sg_job_debug_rng.argtypes = [vp, i32, i32, C.c_uint32, vp, vp]
+        L.sg_job_destroy.argtypes = [vp]
+        L.sg_batch_create.argtypes = [vp, C.POINTER(vp)]
+        L.sg_batch_add.argtypes = [vp, vp]
+        L.sg_batch_remove.argtypes = [vp, vp]
+        L.sg_batch_set_block.argtypes = [vp, i32]
+        L.sg_batch_run.argtypes = [vp, u64, vp]
+        L.sg_batch_block.argtypes = [vp, C.POINTER(i32)]
+        L.sg_batch_destroy.argtypes = [vp]
+        for n in EXPORTS:
+            if n not in ("sg_last_error", "sg_wheels_per_copy"):
+                getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _chk(rc):
+    if rc != SG_OK:
+        raise SgError(rc, lib().sg_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def wheels_per_copy(L: int) -> int:
+    return int(lib().sg_wheels_per_copy(L))
+
+
+def job_bytes(spec: Spec) -> int:
+    n = C.c_uint64()
+    _chk(lib().sg_job_bytes(C.byref(spec), C.byref(n)))
+    return n.value
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _chk(lib().sg_ctx_create(device, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().sg_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Job:
+    """One job: S samples x R replicas x K temperature slots of one (model, L).
+
+    Device state lives in a torch uint8 tensor (the arena) owned by this
+    object.  Arrays follow the canonical formats of include/sg.h.
+    """
+
+    def __init__(self, ctx: Context, model, algo, L, betas, J, spins, wheels, ptwheels=None,
+                 *, n_samples=1, n_replicas=1, pt_every=0, slot_of_temp=None, sweeps_done=0,
+                 stream=None, arena=None):
+        import torch
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        K = betas.shape[0]
+        self.spec = Spec(model, algo, 4, L, n_samples, n_replicas, K, pt_every)
+        self.model, self.algo, self.L = model, algo, L
+        self.S, self.R, self.K = n_samples, n_replicas, K
+        self.C = n_samples * n_replicas * K
+        self.N = L ** 3
+        self.NW = wheels_per_copy(L)
+        self.bytes = job_bytes(self.spec)
+        if arena is None:
+            arena = torch.empty(self.bytes, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        self.arena = arena
+        J = np.ascontiguousarray(J, dtype=np.int8)
+        spins = np.ascontiguousarray(spins, dtype=np.int8 if model == ISING else np.uint8)
+        wheels = np.ascontiguousarray(wheels, dtype=np.uint32)
+        assert J.size == self.S * 3 * self.N and spins.size == self.C * self.N
+        assert wheels.size == self.C * self.NW * 61
+        pw = None if ptwheels is None else np.ascontiguousarray(ptwheels, dtype=np.uint32)
+        if pw is not None:
+            assert pw.size == self.S * self.R * 61
+        sot = None if slot_of_temp is None else np.ascontiguousarray(slot_of_temp, dtype=np.int32)
+        h = C.c_void_p()
+        _chk(lib().sg_job_create(ctx.h, C.byref(self.spec), _ptr(betas), _ptr(J), _ptr(spins),
+                                 _ptr(wheels), _ptr(pw), _ptr(sot), sweeps_done,
+                                 C.c_void_p(arena.data_ptr()), arena.numel(), _stream(stream),
+                                 C.byref(h)))
+        self.h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sg_job_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_betas(self, betas, stream=None):
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        _chk(lib().sg_job_set_betas(self.h, _ptr(b), _stream(stream)))
+
+    def sweep(self, n: int, stream=None):
+        _chk(lib().sg_job_sweep(self.h, n, _stream(stream)))
+
+    def measure(self, stream=None, overlap=True):
+        E = np.zeros(self.C, dtype=np.int64)
+        Q = np.zeros(self.S * self.K, dtype=np.int64) if (overlap and self.R >= 2) else None
+        _chk(lib().sg_job_measure(self.h, _ptr(E), _ptr(Q), _stream(stream)))
+        return E, Q
+
+    def energies(self, stream=None):
+        E = np.zeros(self.C, dtype=np.int64)
+        _chk(lib().sg_job_energies(self.h, _ptr(E), _stream(stream)))
+        return E
+
+    def spins(self, stream=None):
+        out = np.zeros((self.C, self.N), dtype=np.int8 if self.model == ISING else np.uint8)
+        _chk(lib().sg_job_get_spins(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def wheels(self, stream=None):
+        w = np.zeros((self.C, self.NW, 61), dtype=np.uint32)
+        pw = np.zeros((self.S * self.R, 61), dtype=np.uint32)
+        _chk(lib().sg_job_get_wheels(self.h, _ptr(w), _ptr(pw), _stream(stream)))
+        return w, pw
+
+    def perm(self, stream=None):
+        out = np.zeros((self.S * self.R, self.K), dtype=np.int32)
+        _chk(lib().sg_job_get_perm(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def pt_accepts(self, stream=None):
+        out = np.zeros((self.S * self.R, max(self.K - 1, 1)), dtype=np.uint64)
+        _chk(lib().sg_job_get_pt_accepts(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def sweeps_done(self) -> int:
+        n = C.c_uint64()
+        _chk(lib().sg_job_sweeps_done(self.h, C.byref(n)))
+        return n.value
+
+    def debug_rng(self, copy: int, wheel: int, n: int, stream=None):
+        out = np.zeros(n, dtype=np.uint32)
+        _chk(lib().sg_job_debug_rng(self.h, copy, wheel, n, _ptr(out), _stream(stream)))
+        return out
+
+
+class Batch:
+    """Jobs advanced together by one fused launch per period (hipGraph replay)."""
+
+    def __init__(self, ctx: Context, jobs=(), block: int = 0):
+        h = C.c_void_p()
+        _chk(lib().sg_batch_create(ctx.h, C.byref(h)))
+        self.h = h
+        self.jobs = []
+        if block:
+            self.set_block(block)
+        for j in jobs:
+            self.add(j)
+
+    def add(self, job: Job):
+        _chk(lib().sg_batch_add(self.h, job.h))
+        self.jobs.append(job)
+
+    def remove(self, job: Job):
+        _chk(lib().sg_batch_remove(self.h, job.h))
+        self.jobs.remove(job)
+
+    def set_block(self, threads: int):
+        _chk(lib().sg_batch_set_block(self.h, threads))
+
+    def block(self) -> int:
+        n = C.c_int32()
+        _chk(lib().sg_batch_block(self.h, C.byref(n)))
+        return n.value
+
+    def run(self, n: int, stream=None):
+        _chk(lib().sg_batch_run(self.h, n, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

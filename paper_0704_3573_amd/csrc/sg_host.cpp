@@ -1,0 +1,952 @@
+// Host side of libsg: argument checks, integer threshold tables (IEEE double,
+// host only), canonical <-> device layout conversion, launch planning,
+// batches replayed from captured hipGraphs.  The C-ABI is declared in
+// include/sg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sg.h"
+#include "sg_layout.h"
+
+namespace sg {
+hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, int tpb, size_t lds,
+                        int nsweeps, hipStream_t st);
+hipError_t set_max_lds(int bytes);
+hipError_t launch_overlap(const uint32_t *spins, const int32_t *slot_of_temp, int64_t *Q, int model,
+                          int L, int S, int R, int K, int copy_words, hipStream_t st);
+hipError_t launch_pt(const int64_t *E, int32_t *slot_of_temp, int32_t *temp_of_slot, uint32_t *ptw,
+                     const uint64_t *F, const int32_t *sgn, uint64_t *accepts, int chains, int K,
+                     hipStream_t st);
+hipError_t launch_debug_rng(const uint32_t *wheels, uint32_t *out, uint64_t wstride_words,
+                            uint64_t widx, int M, uint64_t k0, int n, hipStream_t st);
+hipError_t launch_advance(uint64_t *const *done, const int32_t *cap, int n, int nsweeps,
+                          hipStream_t st);
+hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st);
+}  // namespace sg
+
+using sg::Geom;
+using sg::Work;
+
+// ---------------------------------------------------------------- errors --
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) return fail(SG_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                     \
+  }                                                   \
+  catch (const std::bad_alloc &) {                    \
+    return fail(SG_E_NOMEM, "host allocation failed"); \
+  }                                                   \
+  catch (...) {                                       \
+    return fail(SG_E_INVALID, "internal error");      \
+  }
+
+static hipStream_t S_(void *s) { return (hipStream_t)s; }
+
+// ---------------------------------------------------------------- tables --
+// Thresholds of a number r in [0, 2^32): accepted when r < T, probability T / 2^32.
+static uint64_t scaled_floor(double p, int bits) { return (uint64_t)std::floor(std::ldexp(p, bits)); }
+
+// Row of THR_WORDS words for one temperature (see sg_layout.h).
+static void threshold_row(int model, int algo, double beta, uint32_t row[sg::THR_WORDS]) {
+  std::memset(row, 0, sizeof(uint32_t) * sg::THR_WORDS);
+  uint64_t T[13];
+  int n = 0;
+  if (model == SG_POTTS) {
+    for (int d = 0; d < 13; d++) T[d] = scaled_floor(std::exp(-beta * (double)d), 28);
+    n = 13;
+  } else if (algo == SG_METROPOLIS) {
+    // flip with n unsatisfied bonds costs dE = 12 - 4n (n = 0..2)
+    for (int k = 0; k < 3; k++) T[k] = scaled_floor(std::exp(-beta * (double)(12 - 4 * k)), 32);
+    n = 3;
+  } else {
+    // heat bath, local field h = 2k - 6: P(+1) = 1 / (1 + exp(-2 beta h))
+    for (int k = 0; k < 7; k++) {
+      const double h = (double)(2 * k - 6);
+      T[k] = scaled_floor(1.0 / (1.0 + std::exp(-2.0 * beta * h)), 32);
+    }
+    n = 7;
+  }
+  uint32_t always = 0;
+  for (int k = 0; k < n; k++) {
+    if (T[k] >= (1ull << 32)) {
+      row[k] = 0xFFFFFFFFu;
+      always |= 1u << k;
+    } else {
+      row[k] = (uint32_t)T[k];
+    }
+  }
+  if (model != SG_POTTS) row[15] = always;
+}
+
+// ------------------------------------------------------------------- ctx --
+struct sg_ctx {
+  int device;
+  int max_lds;
+  int cus;
+};
+
+// ------------------------------------------------------------------- job --
+struct Layout {
+  uint64_t spins, J, wheels, ptw, tos, sot, thr, F, sgn, E, Q, acc, done, dbg, works, total;
+  uint64_t spins_bytes, J_bytes, wheels_bytes;
+};
+
+static uint64_t al(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+static int check_spec(const sg_job_spec *sp) {
+  if (!sp) return fail(SG_E_INVALID, "spec is NULL");
+  if (sp->model != SG_ISING && sp->model != SG_POTTS) return fail(SG_E_INVALID, "bad model %d", sp->model);
+  if (sp->algo != SG_METROPOLIS && sp->algo != SG_HEATBATH) return fail(SG_E_INVALID, "bad algo %d", sp->algo);
+  if (sp->model == SG_POTTS && sp->algo != SG_HEATBATH)
+    return fail(SG_E_UNSUPPORTED, "the Potts glass is built for heat bath only");
+  if (sp->model == SG_POTTS && sp->q != 4) return fail(SG_E_UNSUPPORTED, "Potts q must be 4");
+  if (!sg::supported_L(sp->L)) return fail(SG_E_UNSUPPORTED, "L = %d is not built", sp->L);
+  if (sp->model == SG_POTTS && !sg::potts_supported_L(sp->L))
+    return fail(SG_E_UNSUPPORTED, "Potts L = %d is not built (L <= 48)", sp->L);
+  if (sp->n_samples < 1 || sp->n_replicas < 1 || sp->n_temps < 1)
+    return fail(SG_E_INVALID, "S, R, K must be >= 1");
+  if (sp->pt_every < 0) return fail(SG_E_INVALID, "pt_every must be >= 0");
+  const uint64_t C = (uint64_t)sp->n_samples * sp->n_replicas * sp->n_temps;
+  if (C > (1u << 24)) return fail(SG_E_INVALID, "too many copies");
+  return SG_OK;
+}
+
+static Layout layout(const sg_job_spec *sp) {
+  const Geom g = sg::geom(sp->L);
+  const uint64_t S = sp->n_samples, R = sp->n_replicas, K = sp->n_temps, C = S * R * K;
+  const uint64_t N = (uint64_t)sp->L * sp->L * sp->L;
+  const uint64_t K1 = K > 1 ? K - 1 : 1;
+  Layout l{};
+  uint64_t o = 0;
+  l.spins_bytes = sp->model == SG_ISING ? C * g.CS * 4 : C * N;
+  l.J_bytes = sp->model == SG_ISING ? S * sg::ising_js(sp->L) * 4 : S * N;
+  l.wheels_bytes = (uint64_t)g.M * C * g.NW * 4;
+  l.spins = o; o = al(o + l.spins_bytes);
+  l.J = o; o = al(o + l.J_bytes);
+  l.wheels = o; o = al(o + l.wheels_bytes);
+  l.ptw = o; o = al(o + S * R * 64 * 4);
+  l.tos = o; o = al(o + C * 4);
+  l.sot = o; o = al(o + S * R * K * 4);
+  l.thr = o; o = al(o + K * sg::THR_WORDS * 4);
+  l.F = o; o = al(o + K1 * 24 * 8);
+  l.sgn = o; o = al(o + K1 * 4);
+  l.E = o; o = al(o + C * 8);
+  l.Q = o; o = al(o + S * K * 8);
+  l.acc = o; o = al(o + S * R * K1 * 8);
+  l.done = o; o = al(o + 8);
+  l.dbg = o; o = al(o + 4096 * 4);
+  l.works = o; o = al(o + C * sizeof(Work));
+  l.total = o;
+  return l;
+}
+
+struct sg_job {
+  sg_ctx *ctx;
+  sg_job_spec sp;
+  Geom g;
+  int L, S, R, K, C, chains;
+  uint64_t N;
+  Layout lay;
+  uint8_t *arena;
+  std::vector<double> betas;
+  std::vector<Work> works;  // host copy of the job's own launch plan
+  int tpb;
+  size_t lds;
+  uint64_t sweeps_done;
+
+  template <class T>
+  T *at(uint64_t off) const {
+    return (T *)(arena + off);
+  }
+  uint64_t *done_ptr() const { return at<uint64_t>(lay.done); }
+};
+
+// lanes and LDS bytes of a work item of G copies
+static size_t item_lds(const sg_job *j, int G) {
+  if (j->sp.model == SG_ISING) return (size_t)G * j->g.CS * 4 + (size_t)G * 4;
+  return (size_t)G * j->N + (size_t)G * 16 * 4 + (size_t)G * 4;
+}
+
+static int copies_per_item(const sg_job *j, int tpb) {
+  int G = tpb / j->g.NW;
+  G = std::min(G, j->C);
+  while (G > 1 && item_lds(j, G) > (size_t)j->ctx->max_lds) G--;
+  return G;
+}
+
+static void make_items(const sg_job *j, int G, std::vector<Work> &out) {
+  for (int c0 = 0; c0 < j->C; c0 += G) {
+    Work w{};
+    w.spins = j->at<uint32_t>(j->lay.spins);
+    w.J = j->at<uint32_t>(j->lay.J);
+    w.wheels = j->at<uint32_t>(j->lay.wheels);
+    w.temp_of_slot = j->at<int32_t>(j->lay.tos);
+    w.thr = j->at<uint32_t>(j->lay.thr);
+    w.E = j->at<int64_t>(j->lay.E);
+    w.L = j->L;
+    w.algo = j->sp.algo;
+    w.model = j->sp.model;
+    w.copy0 = c0;
+    w.ncopies = std::min(G, j->C - c0);
+    w.C = j->C;
+    w.RK = j->R * j->K;
+    w.nsweeps_cap = 0x7FFFFFFF;
+    w.spins_bytes = (uint32_t)j->lay.spins_bytes;
+    w.J_bytes = (uint32_t)j->lay.J_bytes;
+    w.wheels_bytes = (uint32_t)j->lay.wheels_bytes;
+    w.done = j->done_ptr();
+    out.push_back(w);
+  }
+}
+
+// --------------------------------------------------------------- packing --
+static void pack_ising_spins(const Geom &g, const int8_t *s, uint32_t *out) {
+  const int L = g.L;
+  std::memset(out, 0, sizeof(uint32_t) * g.CS);
+  for (int p = 0; p < 2; p++)
+    for (int z = 0; z < L; z++)
+      for (int wb = 0; wb < g.NWB; wb++) {
+        uint32_t word = 0;
+        for (int r = 0; r < g.RPB; r++) {
+          const int y = wb * g.RPB + r;
+          const int e = (p + y + z) & 1;
+          for (int j = 0; j < g.H; j++) {
+            const int x = 2 * j + e;
+            const int bit = g.B - 1 - (r * g.H + j);
+            if (s[x + L * (y + L * z)] < 0) word |= 1u << bit;
+          }
+        }
+        out[(p * L + z) * g.WZ + wb] = word;
+      }
+}
+
+static void unpack_ising_spins(const Geom &g, const uint32_t *in, int8_t *s) {
+  const int L = g.L;
+  for (int p = 0; p < 2; p++)
+    for (int z = 0; z < L; z++)
+      for (int wb = 0; wb < g.NWB; wb++) {
+        const uint32_t word = in[(p * L + z) * g.WZ + wb];
+        for (int r = 0; r < g.RPB; r++) {
+          const int y = wb * g.RPB + r;
+          const int e = (p + y + z) & 1;
+          for (int j = 0; j < g.H; j++) {
+            const int x = 2 * j + e;
+            const int bit = g.B - 1 - (r * g.H + j);
+            s[x + L * (y + L * z)] = ((word >> bit) & 1u) ? -1 : 1;
+          }
+        }
+      }
+}
+
+// bond d of site (x, y, z): x+, x-, y+, y-, z+, z-
+static int8_t bond(const int8_t *J, int L, int x, int y, int z, int d) {
+  const uint64_t N = (uint64_t)L * L * L;
+  auto idx = [&](int xx, int yy, int zz) { return (uint64_t)xx + L * ((uint64_t)yy + (uint64_t)L * zz); };
+  switch (d) {
+    case 0: return J[0 * N + idx(x, y, z)];
+    case 1: return J[0 * N + idx((x + L - 1) % L, y, z)];
+    case 2: return J[1 * N + idx(x, y, z)];
+    case 3: return J[1 * N + idx(x, (y + L - 1) % L, z)];
+    case 4: return J[2 * N + idx(x, y, z)];
+    default: return J[2 * N + idx(x, y, (z + L - 1) % L)];
+  }
+}
+
+static void pack_ising_J(const Geom &g, const int8_t *J, uint32_t *out) {
+  const int L = g.L;
+  for (int p = 0; p < 2; p++)
+    for (int wb = 0; wb < g.NWB; wb++)
+      for (int d = 0; d < 6; d++)
+        for (int z = 0; z < L; z++) {
+          uint32_t word = 0;
+          for (int r = 0; r < g.RPB; r++) {
+            const int y = wb * g.RPB + r;
+            const int e = (p + y + z) & 1;
+            for (int j = 0; j < g.H; j++) {
+              const int x = 2 * j + e;
+              const int bit = g.B - 1 - (r * g.H + j);
+              if (bond(J, L, x, y, z, d) < 0) word |= 1u << bit;
+            }
+          }
+          out[((p * g.NWB + wb) * 6 + d) * L + z] = word;
+        }
+}
+
+// Potts: byte per site, order [y][x][z]
+static uint64_t potts_idx(int L, int x, int y, int z) { return ((uint64_t)y * L + x) * L + z; }
+
+static void pack_potts_spins(int L, const uint8_t *s, uint8_t *out) {
+  for (int z = 0; z < L; z++)
+    for (int y = 0; y < L; y++)
+      for (int x = 0; x < L; x++) out[potts_idx(L, x, y, z)] = (uint8_t)(s[x + L * (y + L * z)] << 3);
+}
+
+static void unpack_potts_spins(int L, const uint8_t *in, uint8_t *s) {
+  for (int z = 0; z < L; z++)
+    for (int y = 0; y < L; y++)
+      for (int x = 0; x < L; x++) s[x + L * (y + L * z)] = (uint8_t)(in[potts_idx(L, x, y, z)] >> 3);
+}
+
+static void pack_potts_J(int L, const int8_t *J, uint8_t *out) {
+  for (int z = 0; z < L; z++)
+    for (int y = 0; y < L; y++)
+      for (int x = 0; x < L; x++) {
+        uint8_t pat = 0;
+        for (int d = 0; d < 6; d++)
+          if (bond(J, L, x, y, z, d) < 0) pat |= (uint8_t)(1u << d);
+        out[potts_idx(L, x, y, z)] = pat;
+      }
+}
+
+// wheel words (oldest first) of a state that has drawn k0 numbers -> slots
+static void pack_wheels(const sg_job *j, const uint32_t *wh, uint64_t k0, uint32_t *out) {
+  const uint64_t M = j->g.M, NW = j->g.NW, C = j->C, stride = C * NW;
+  for (uint64_t c = 0; c < C; c++)
+    for (uint64_t w = 0; w < NW; w++) {
+      const uint32_t *src = wh + (c * NW + w) * 61;
+      for (int i = 0; i < 61; i++) {
+        const uint64_t slot = (k0 + M - 61 + i) % M;  // draw index k0 - 61 + i
+        out[slot * stride + c * NW + w] = src[i];
+      }
+    }
+}
+
+static void unpack_wheels(const sg_job *j, const uint32_t *in, uint64_t k0, uint32_t *wh) {
+  const uint64_t M = j->g.M, NW = j->g.NW, C = j->C, stride = C * NW;
+  for (uint64_t c = 0; c < C; c++)
+    for (uint64_t w = 0; w < NW; w++) {
+      uint32_t *dst = wh + (c * NW + w) * 61;
+      for (int i = 0; i < 61; i++) dst[i] = in[((k0 + M - 61 + i) % M) * stride + c * NW + w];
+    }
+}
+
+static void tables_upload_host(const sg_job *j, std::vector<uint32_t> &thr, std::vector<uint64_t> &F,
+                               std::vector<int32_t> &sgn) {
+  const int K = j->K, K1 = K > 1 ? K - 1 : 1;
+  thr.assign((size_t)K * sg::THR_WORDS, 0);
+  for (int k = 0; k < K; k++) threshold_row(j->sp.model, j->sp.algo, j->betas[k], &thr[(size_t)k * sg::THR_WORDS]);
+  F.assign((size_t)K1 * 24, 0);
+  sgn.assign((size_t)K1, 0);
+  for (int i = 0; i + 1 < K; i++) {
+    const double db = j->betas[i] - j->betas[i + 1];
+    sgn[i] = db > 0 ? 1 : (db < 0 ? -1 : 0);
+    for (int b = 0; b < 24; b++)
+      F[(size_t)i * 24 + b] = scaled_floor(std::exp(-std::fabs(db) * std::ldexp(1.0, b)), 32);
+  }
+}
+
+static int upload_tables(sg_job *j, hipStream_t st) {
+  std::vector<uint32_t> thr;
+  std::vector<uint64_t> F;
+  std::vector<int32_t> sgn;
+  tables_upload_host(j, thr, F, sgn);
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.thr), thr.data(), thr.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.F), F.data(), F.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.sgn), sgn.data(), sgn.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SG_OK;
+}
+
+static int check_betas(const double *betas, int K) {
+  if (!betas) return fail(SG_E_INVALID, "betas is NULL");
+  for (int k = 0; k < K; k++)
+    if (!(betas[k] >= 0.0) || std::isinf(betas[k])) return fail(SG_E_INVALID, "beta[%d] must be finite and >= 0", k);
+  return SG_OK;
+}
+
+// ------------------------------------------------------------- C-ABI ------
+extern "C" {
+
+const char *sg_last_error(void) { return g_err.c_str(); }
+
+int32_t sg_wheels_per_copy(int32_t L) { return sg::supported_L(L) ? sg::geom(L).NW : 0; }
+
+int sg_ctx_create(int device, sg_ctx **out) {
+  GUARD_BEGIN
+  if (!out) return fail(SG_E_INVALID, "out is NULL");
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(SG_E_INVALID, "device %d of %d", device, n);
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SG_E_UNSUPPORTED, "device %d is %s, the kernels are built for gfx950", device, prop.gcnArchName);
+  sg_ctx *c = new sg_ctx;
+  c->device = device;
+  c->max_lds = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+  c->cus = prop.multiProcessorCount;
+  if (sg::set_max_lds(c->max_lds) != hipSuccess) {
+    (void)hipGetLastError();
+    c->max_lds = 64 * 1024;
+  }
+  *out = c;
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_ctx_destroy(sg_ctx *ctx) {
+  delete ctx;
+  return SG_OK;
+}
+
+int sg_job_bytes(const sg_job_spec *spec, uint64_t *bytes) {
+  int rc = check_spec(spec);
+  if (rc) return rc;
+  if (!bytes) return fail(SG_E_INVALID, "bytes is NULL");
+  *bytes = layout(spec).total;
+  return SG_OK;
+}
+
+int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, const int8_t *J,
+                  const void *spins, const uint32_t *wheels, const uint32_t *ptwheels,
+                  const int32_t *slot_of_temp, uint64_t sweeps_done, void *d_arena,
+                  uint64_t arena_bytes, void *stream, sg_job **out) {
+  GUARD_BEGIN
+  if (!ctx || !out) return fail(SG_E_INVALID, "ctx or out is NULL");
+  int rc = check_spec(spec);
+  if (rc) return rc;
+  if (!J || !spins || !wheels) return fail(SG_E_INVALID, "J, spins and wheels are required");
+  if (spec->pt_every > 0 && spec->n_temps > 1 && !ptwheels)
+    return fail(SG_E_INVALID, "parallel tempering needs ptwheels");
+  rc = check_betas(betas, spec->n_temps);
+  if (rc) return rc;
+  const Layout lay = layout(spec);
+  if (!d_arena) return fail(SG_E_INVALID, "arena is NULL");
+  if (arena_bytes < lay.total)
+    return fail(SG_E_NOMEM, "arena of %llu bytes, job needs %llu", (unsigned long long)arena_bytes,
+                (unsigned long long)lay.total);
+  if (((uintptr_t)d_arena & 255) != 0) return fail(SG_E_INVALID, "arena must be 256-byte aligned");
+  if (lay.spins_bytes >= (1ull << 32) || lay.wheels_bytes >= (1ull << 32) || lay.J_bytes >= (1ull << 32))
+    return fail(SG_E_UNSUPPORTED, "job too large for one device buffer (split it into several jobs)");
+  const uint64_t N = (uint64_t)spec->L * spec->L * spec->L;
+  // validate host inputs
+  const uint64_t S = spec->n_samples, R = spec->n_replicas, K = spec->n_temps, C = S * R * K;
+  for (uint64_t i = 0; i < S * 3 * N; i++)
+    if (J[i] != 1 && J[i] != -1) return fail(SG_E_INVALID, "couplings must be +1 or -1");
+  if (spec->model == SG_ISING) {
+    const int8_t *s = (const int8_t *)spins;
+    for (uint64_t i = 0; i < C * N; i++)
+      if (s[i] != 1 && s[i] != -1) return fail(SG_E_INVALID, "Ising spins must be +1 or -1");
+  } else {
+    const uint8_t *s = (const uint8_t *)spins;
+    for (uint64_t i = 0; i < C * N; i++)
+      if (s[i] > 3) return fail(SG_E_INVALID, "Potts spins must be in 0..3");
+  }
+  std::vector<int32_t> sot((size_t)S * R * K), tos((size_t)C);
+  for (uint64_t ch = 0; ch < S * R; ch++) {
+    std::vector<int> seen((size_t)K, 0);
+    for (uint64_t k = 0; k < K; k++) {
+      const int32_t v = slot_of_temp ? slot_of_temp[ch * K + k] : (int32_t)k;
+      if (v < 0 || v >= (int32_t)K || seen[v]) return fail(SG_E_INVALID, "slot_of_temp is not a permutation");
+      seen[v] = 1;
+      sot[ch * K + k] = v;
+      tos[ch * K + v] = (int32_t)k;
+    }
+  }
+
+  sg_job *j = new sg_job;
+  j->ctx = ctx;
+  j->sp = *spec;
+  j->g = sg::geom(spec->L);
+  j->L = spec->L;
+  j->S = spec->n_samples;
+  j->R = spec->n_replicas;
+  j->K = spec->n_temps;
+  j->C = (int)C;
+  j->chains = (int)(S * R);
+  j->N = N;
+  j->lay = lay;
+  j->arena = (uint8_t *)d_arena;
+  j->betas.assign(betas, betas + K);
+  j->sweeps_done = sweeps_done;
+  hipStream_t st = S_(stream);
+  HIPCHK(hipSetDevice(ctx->device));
+
+  // pack on the host, upload
+  std::vector<uint8_t> buf;
+  if (spec->model == SG_ISING) {
+    std::vector<uint32_t> sp((size_t)C * j->g.CS);
+    for (uint64_t c = 0; c < C; c++)
+      pack_ising_spins(j->g, (const int8_t *)spins + c * N, &sp[c * j->g.CS]);
+    std::vector<uint32_t> jw((size_t)S * sg::ising_js(j->L));
+    for (uint64_t s = 0; s < S; s++) pack_ising_J(j->g, J + s * 3 * N, &jw[s * sg::ising_js(j->L)]);
+    HIPCHK(hipMemcpy(j->at<void>(lay.spins), sp.data(), lay.spins_bytes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(j->at<void>(lay.J), jw.data(), lay.J_bytes, hipMemcpyHostToDevice));
+  } else {
+    std::vector<uint8_t> sp((size_t)C * N), jp((size_t)S * N);
+    for (uint64_t c = 0; c < C; c++) pack_potts_spins(j->L, (const uint8_t *)spins + c * N, &sp[c * N]);
+    for (uint64_t s = 0; s < S; s++) pack_potts_J(j->L, J + s * 3 * N, &jp[s * N]);
+    HIPCHK(hipMemcpy(j->at<void>(lay.spins), sp.data(), lay.spins_bytes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(j->at<void>(lay.J), jp.data(), lay.J_bytes, hipMemcpyHostToDevice));
+  }
+  {
+    const uint64_t k0 = sweeps_done * (uint64_t)j->g.RHO * j->L;
+    std::vector<uint32_t> wv((size_t)lay.wheels_bytes / 4, 0);
+    pack_wheels(j, wheels, k0, wv.data());
+    HIPCHK(hipMemcpy(j->at<void>(lay.wheels), wv.data(), lay.wheels_bytes, hipMemcpyHostToDevice));
+  }
+  {
+    std::vector<uint32_t> pw((size_t)S * R * 64, 0);
+    if (ptwheels)
+      for (uint64_t ch = 0; ch < S * R; ch++) std::memcpy(&pw[ch * 64], ptwheels + ch * 61, 61 * 4);
+    HIPCHK(hipMemcpy(j->at<void>(lay.ptw), pw.data(), pw.size() * 4, hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMemcpy(j->at<void>(lay.sot), sot.data(), sot.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(j->at<void>(lay.tos), tos.data(), tos.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(j->at<void>(lay.done), &sweeps_done, 8, hipMemcpyHostToDevice));
+  {
+    std::vector<uint8_t> z((size_t)(lay.done - lay.E), 0);  // E, Q, accepts
+    HIPCHK(hipMemcpy(j->at<void>(lay.E), z.data(), z.size(), hipMemcpyHostToDevice));
+  }
+  rc = upload_tables(j, st);
+  if (rc) {
+    delete j;
+    return rc;
+  }
+  // own launch plan
+  int tpb = 512;
+  if (j->g.NW > tpb) tpb = j->g.NW;
+  int G = copies_per_item(j, tpb);
+  if (G < 1 || item_lds(j, 1) > (size_t)ctx->max_lds) {
+    delete j;
+    return fail(SG_E_UNSUPPORTED, "one copy of L = %d needs more LDS than the device offers", spec->L);
+  }
+  make_items(j, G, j->works);
+  j->tpb = ((G * j->g.NW + 63) / 64) * 64;
+  j->lds = item_lds(j, G);
+  HIPCHK(hipMemcpy(j->at<void>(lay.works), j->works.data(), j->works.size() * sizeof(Work), hipMemcpyHostToDevice));
+  HIPCHK(hipDeviceSynchronize());
+  *out = j;
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_job_set_betas(sg_job *job, const double *betas, void *stream) {
+  GUARD_BEGIN
+  if (!job) return fail(SG_E_INVALID, "job is NULL");
+  int rc = check_betas(betas, job->K);
+  if (rc) return rc;
+  job->betas.assign(betas, betas + job->K);
+  return upload_tables(job, S_(stream));
+  GUARD_END
+}
+
+static int run_pt(sg_job *j, hipStream_t st) {
+  HIPCHK(sg::launch_pt(j->at<int64_t>(j->lay.E), j->at<int32_t>(j->lay.sot), j->at<int32_t>(j->lay.tos),
+                       j->at<uint32_t>(j->lay.ptw), j->at<uint64_t>(j->lay.F), j->at<int32_t>(j->lay.sgn),
+                       j->at<uint64_t>(j->lay.acc), j->chains, j->K, st));
+  return SG_OK;
+}
+
+// own-plan sweep launch of `n` sweeps plus the counter update
+static int launch_own(sg_job *j, int n, hipStream_t st) {
+  HIPCHK(sg::launch_sweep(j->sp.model, j->sp.algo, j->at<Work>(j->lay.works), (int)j->works.size(), j->tpb,
+                          j->lds, n, st));
+  return SG_OK;
+}
+
+int sg_job_sweep(sg_job *job, uint64_t n_sweeps, void *stream) {
+  GUARD_BEGIN
+  if (!job) return fail(SG_E_INVALID, "job is NULL");
+  hipStream_t st = S_(stream);
+  uint64_t left = n_sweeps;
+  while (left > 0) {
+    uint64_t chunk = std::min<uint64_t>(left, 1u << 20);
+    const int pe = job->sp.pt_every;
+    if (pe > 0) chunk = std::min<uint64_t>(chunk, pe - job->sweeps_done % pe);
+    int rc = launch_own(job, (int)chunk, st);
+    if (rc) return rc;
+    HIPCHK(sg::launch_add(job->done_ptr(), chunk, st));
+    job->sweeps_done += chunk;
+    left -= chunk;
+    if (pe > 0 && job->sweeps_done % pe == 0 && job->K > 1) {
+      rc = run_pt(job, st);
+      if (rc) return rc;
+    }
+  }
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_job_measure(sg_job *job, int64_t *E, int64_t *Q, void *stream) {
+  GUARD_BEGIN
+  if (!job) return fail(SG_E_INVALID, "job is NULL");
+  hipStream_t st = S_(stream);
+  int rc = launch_own(job, 0, st);  // energy only
+  if (rc) return rc;
+  if (Q) {
+    if (job->R < 2) return fail(SG_E_STATE, "overlaps need at least two replicas");
+    const int cw = job->sp.model == SG_ISING ? job->g.CS : (int)(job->N / 4);
+    HIPCHK(sg::launch_overlap(job->at<uint32_t>(job->lay.spins), job->at<int32_t>(job->lay.sot),
+                              job->at<int64_t>(job->lay.Q), job->sp.model, job->L, job->S, job->R, job->K, cw,
+                              st));
+  }
+  std::vector<int64_t> Es((size_t)job->C);
+  std::vector<int32_t> sot((size_t)job->C);
+  HIPCHK(hipMemcpyAsync(Es.data(), job->at<void>(job->lay.E), Es.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(sot.data(), job->at<void>(job->lay.sot), sot.size() * 4, hipMemcpyDeviceToHost, st));
+  if (Q)
+    HIPCHK(hipMemcpyAsync(Q, job->at<void>(job->lay.Q), (size_t)job->S * job->K * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (E)
+    for (int ch = 0; ch < job->chains; ch++)
+      for (int k = 0; k < job->K; k++)
+        E[(size_t)ch * job->K + k] = Es[(size_t)ch * job->K + sot[(size_t)ch * job->K + k]];
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_job_energies(sg_job *job, int64_t *E_slot, void *stream) {
+  if (!job || !E_slot) return fail(SG_E_INVALID, "NULL argument");
+  hipStream_t st = S_(stream);
+  HIPCHK(hipMemcpyAsync(E_slot, job->at<void>(job->lay.E), (size_t)job->C * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SG_OK;
+}
+
+int sg_job_get_spins(sg_job *job, void *out, void *stream) {
+  GUARD_BEGIN
+  if (!job || !out) return fail(SG_E_INVALID, "NULL argument");
+  hipStream_t st = S_(stream);
+  std::vector<uint8_t> raw((size_t)job->lay.spins_bytes);
+  HIPCHK(hipMemcpyAsync(raw.data(), job->at<void>(job->lay.spins), raw.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int c = 0; c < job->C; c++) {
+    if (job->sp.model == SG_ISING)
+      unpack_ising_spins(job->g, (const uint32_t *)raw.data() + (size_t)c * job->g.CS, (int8_t *)out + (size_t)c * job->N);
+    else
+      unpack_potts_spins(job->L, raw.data() + (size_t)c * job->N, (uint8_t *)out + (size_t)c * job->N);
+  }
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_job_get_wheels(sg_job *job, uint32_t *wheels_out, uint32_t *ptwheels_out, void *stream) {
+  GUARD_BEGIN
+  if (!job) return fail(SG_E_INVALID, "job is NULL");
+  hipStream_t st = S_(stream);
+  if (wheels_out) {
+    std::vector<uint32_t> raw((size_t)job->lay.wheels_bytes / 4);
+    HIPCHK(hipMemcpyAsync(raw.data(), job->at<void>(job->lay.wheels), job->lay.wheels_bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    unpack_wheels(job, raw.data(), job->sweeps_done * (uint64_t)job->g.RHO * job->L, wheels_out);
+  }
+  if (ptwheels_out) {
+    std::vector<uint32_t> raw((size_t)job->chains * 64);
+    HIPCHK(hipMemcpyAsync(raw.data(), job->at<void>(job->lay.ptw), raw.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int ch = 0; ch < job->chains; ch++) {
+      const uint32_t *w = &raw[(size_t)ch * 64];
+      const uint32_t pos = w[61] % 61;
+      for (int i = 0; i < 61; i++) ptwheels_out[(size_t)ch * 61 + i] = w[(pos + i) % 61];
+    }
+  }
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_job_get_perm(sg_job *job, int32_t *out, void *stream) {
+  if (!job || !out) return fail(SG_E_INVALID, "NULL argument");
+  hipStream_t st = S_(stream);
+  HIPCHK(hipMemcpyAsync(out, job->at<void>(job->lay.sot), (size_t)job->chains * job->K * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SG_OK;
+}
+
+int sg_job_get_pt_accepts(sg_job *job, uint64_t *out, void *stream) {
+  if (!job || !out) return fail(SG_E_INVALID, "NULL argument");
+  hipStream_t st = S_(stream);
+  const int K1 = job->K > 1 ? job->K - 1 : 1;
+  HIPCHK(hipMemcpyAsync(out, job->at<void>(job->lay.acc), (size_t)job->chains * K1 * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SG_OK;
+}
+
+int sg_job_sweeps_done(const sg_job *job, uint64_t *out) {
+  if (!job || !out) return fail(SG_E_INVALID, "NULL argument");
+  *out = job->sweeps_done;
+  return SG_OK;
+}
+
+int sg_job_debug_rng(sg_job *job, int32_t copy, int32_t wheel, uint32_t n, uint32_t *out, void *stream) {
+  if (!job || !out) return fail(SG_E_INVALID, "NULL argument");
+  if (copy < 0 || copy >= job->C || wheel < 0 || wheel >= job->g.NW || n > 4096)
+    return fail(SG_E_INVALID, "copy, wheel or n out of range");
+  hipStream_t st = S_(stream);
+  const uint64_t stride = (uint64_t)job->C * job->g.NW;
+  HIPCHK(sg::launch_debug_rng(job->at<uint32_t>(job->lay.wheels), job->at<uint32_t>(job->lay.dbg), stride,
+                              (uint64_t)copy * job->g.NW + wheel, job->g.M,
+                              job->sweeps_done * (uint64_t)job->g.RHO * job->L, (int)n, st));
+  HIPCHK(hipMemcpyAsync(out, job->at<void>(job->lay.dbg), (size_t)n * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SG_OK;
+}
+
+int sg_job_destroy(sg_job *job) {
+  delete job;
+  return SG_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- batch --
+struct GraphKey {
+  int nsw;
+  std::vector<int> pt_jobs;
+  bool operator<(const GraphKey &o) const {
+    if (nsw != o.nsw) return nsw < o.nsw;
+    return pt_jobs < o.pt_jobs;
+  }
+};
+
+struct sg_batch {
+  sg_ctx *ctx;
+  std::vector<sg_job *> jobs;
+  int block_req = 0;  // 0 = automatic
+  // plan
+  bool dirty = true;
+  int tpb = 0;
+  size_t lds = 0;
+  std::vector<Work> items[2][2];  // [model][algo]
+  Work *d_items = nullptr;
+  size_t d_items_cap = 0;
+  uint64_t **d_done = nullptr;
+  int32_t *d_cap = nullptr;
+  size_t d_jobs_cap = 0;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;
+};
+
+static void drop_graphs(sg_batch *b) {
+  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+// idle-lane fraction of a block size for the batch's jobs (lower is better)
+static double idle_fraction(const sg_batch *b, int tpb) {
+  double used = 0, total = 0;
+  for (sg_job *j : b->jobs) {
+    if (j->g.NW > tpb) return 2.0;
+    const int G = copies_per_item(j, tpb);
+    if (G < 1) return 2.0;
+    const double items = std::ceil((double)j->C / G);
+    used += (double)j->C * j->g.NW * j->g.RHO;  // weight by draws per sweep per lane
+    total += items * ((tpb + 63) / 64 * 64) * j->g.RHO;
+  }
+  return total > 0 ? 1.0 - used / total : 0.0;
+}
+
+static int plan(sg_batch *b) {
+  if (!b->dirty) return SG_OK;
+  drop_graphs(b);
+  int tpb = b->block_req;
+  if (tpb <= 0) {
+    double best = 3;
+    for (int t = 64; t <= 1024; t += 64) {
+      const double f = idle_fraction(b, t);
+      if (f < best - 1e-9) {
+        best = f;
+        tpb = t;
+      }
+    }
+    if (tpb <= 0) return fail(SG_E_UNSUPPORTED, "no block size fits the batch");
+  }
+  for (sg_job *j : b->jobs)
+    if (j->g.NW > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
+  for (auto &a : b->items)
+    for (auto &v : a) v.clear();
+  size_t lds = 0, total = 0;
+  for (sg_job *j : b->jobs) {
+    const int G = copies_per_item(j, tpb);
+    lds = std::max(lds, item_lds(j, G));
+    make_items(j, G, b->items[j->sp.model][j->sp.algo]);
+  }
+  for (auto &a : b->items)
+    for (auto &v : a) total += v.size();
+  if (total > b->d_items_cap) {
+    if (b->d_items) HIPCHK(hipFree(b->d_items));
+    b->d_items = nullptr;
+    HIPCHK(hipMalloc(&b->d_items, std::max<size_t>(total, 1) * sizeof(Work)));
+    b->d_items_cap = total;
+  }
+  size_t off = 0;
+  for (auto &a : b->items)
+    for (auto &v : a) {
+      if (!v.empty()) HIPCHK(hipMemcpy(b->d_items + off, v.data(), v.size() * sizeof(Work), hipMemcpyHostToDevice));
+      off += v.size();
+    }
+  if (b->jobs.size() > b->d_jobs_cap) {
+    if (b->d_done) HIPCHK(hipFree(b->d_done));
+    if (b->d_cap) HIPCHK(hipFree(b->d_cap));
+    HIPCHK(hipMalloc(&b->d_done, b->jobs.size() * sizeof(uint64_t *)));
+    HIPCHK(hipMalloc(&b->d_cap, b->jobs.size() * sizeof(int32_t)));
+    b->d_jobs_cap = b->jobs.size();
+  }
+  std::vector<uint64_t *> done;
+  std::vector<int32_t> cap;
+  for (sg_job *j : b->jobs) {
+    done.push_back(j->done_ptr());
+    cap.push_back(0x7FFFFFFF);
+  }
+  if (!done.empty()) {
+    HIPCHK(hipMemcpy(b->d_done, done.data(), done.size() * sizeof(uint64_t *), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_cap, cap.data(), cap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  b->tpb = tpb;
+  b->lds = lds;
+  b->dirty = false;
+  return SG_OK;
+}
+
+// enqueue one period: fused sweep launches, counters, due PT steps
+static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs, hipStream_t st) {
+  size_t off = 0;
+  for (int m = 0; m < 2; m++)
+    for (int a = 0; a < 2; a++) {
+      const auto &v = b->items[m][a];
+      if (!v.empty())
+        HIPCHK(sg::launch_sweep(m, a, b->d_items + off, (int)v.size(), b->tpb, b->lds, nsw, st));
+      off += v.size();
+    }
+  HIPCHK(sg::launch_advance(b->d_done, b->d_cap, (int)b->jobs.size(), nsw, st));
+  for (int ji : pt_jobs) {
+    int rc = run_pt(b->jobs[ji], st);
+    if (rc) return rc;
+  }
+  return SG_OK;
+}
+
+extern "C" {
+
+int sg_batch_create(sg_ctx *ctx, sg_batch **out) {
+  GUARD_BEGIN
+  if (!ctx || !out) return fail(SG_E_INVALID, "NULL argument");
+  sg_batch *b = new sg_batch;
+  b->ctx = ctx;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  *out = b;
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_batch_add(sg_batch *b, sg_job *job) {
+  GUARD_BEGIN
+  if (!b || !job) return fail(SG_E_INVALID, "NULL argument");
+  if (job->ctx != b->ctx) return fail(SG_E_INVALID, "job belongs to another context");
+  if (std::find(b->jobs.begin(), b->jobs.end(), job) != b->jobs.end())
+    return fail(SG_E_STATE, "job is already in the batch");
+  b->jobs.push_back(job);
+  b->dirty = true;
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_batch_remove(sg_batch *b, sg_job *job) {
+  GUARD_BEGIN
+  if (!b || !job) return fail(SG_E_INVALID, "NULL argument");
+  auto it = std::find(b->jobs.begin(), b->jobs.end(), job);
+  if (it == b->jobs.end()) return fail(SG_E_STATE, "job is not in the batch");
+  b->jobs.erase(it);
+  b->dirty = true;
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_batch_set_block(sg_batch *b, int32_t threads) {
+  if (!b) return fail(SG_E_INVALID, "batch is NULL");
+  if (threads != 0 && (threads < 64 || threads > 1024 || threads % 64 != 0))
+    return fail(SG_E_INVALID, "block must be 0 or a multiple of 64 in [64, 1024]");
+  b->block_req = threads;
+  b->dirty = true;
+  return SG_OK;
+}
+
+int sg_batch_block(sg_batch *b, int32_t *threads) {
+  if (!b || !threads) return fail(SG_E_INVALID, "NULL argument");
+  int rc = plan(b);
+  if (rc) return rc;
+  *threads = b->tpb;
+  return SG_OK;
+}
+
+int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
+  GUARD_BEGIN
+  if (!b) return fail(SG_E_INVALID, "batch is NULL");
+  if (b->jobs.empty() || n_sweeps == 0) return SG_OK;
+  int rc = plan(b);
+  if (rc) return rc;
+  hipStream_t st = S_(stream);
+  uint64_t left = n_sweeps;
+  while (left > 0) {
+    uint64_t chunk = std::min<uint64_t>(left, 1u << 20);
+    for (sg_job *j : b->jobs)
+      if (j->sp.pt_every > 0 && j->K > 1)
+        chunk = std::min<uint64_t>(chunk, j->sp.pt_every - j->sweeps_done % j->sp.pt_every);
+    GraphKey key;
+    key.nsw = (int)chunk;
+    for (size_t i = 0; i < b->jobs.size(); i++) {
+      sg_job *j = b->jobs[i];
+      if (j->sp.pt_every > 0 && j->K > 1 && (j->sweeps_done + chunk) % j->sp.pt_every == 0)
+        key.pt_jobs.push_back((int)i);
+    }
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_period(b, key.nsw, key.pt_jobs, b->cap_stream);
+      hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+      if (rc) return rc;
+      if (e != hipSuccess) return fail(SG_E_HIP, "graph capture: %s", hipGetErrorString(e));
+      hipGraphExec_t ge;
+      e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(SG_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+      it = b->graphs.emplace(key, ge).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, st));
+    for (sg_job *j : b->jobs) j->sweeps_done += chunk;
+    left -= chunk;
+  }
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_batch_destroy(sg_batch *b) {
+  if (!b) return SG_OK;
+  drop_graphs(b);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_done) (void)hipFree(b->d_done);
+  if (b->d_cap) (void)hipFree(b->d_cap);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+  return SG_OK;
+}
+
+}  // extern "C"

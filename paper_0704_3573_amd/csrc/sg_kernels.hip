@@ -1,0 +1,799 @@
+// gfx950 kernels of the checkerboard spin-glass sweep.
+//
+// Paper: Belletti et al., "Simulating spin systems on IANUS, an FPGA-based
+// computer".  Update rules of sec. 2.2 (Metropolis; heat bath, Eq. 4), the
+// checkerboard schedule of sec. 3.1, the Parisi-Rapuano generator of sec. 3.3
+// (Eq. 5).  Integer thresholds are computed on the host; no kernel evaluates
+// an exponential.
+//
+// Mapping (one workgroup = G complete copies of one job):
+//  * one lane per Parisi-Rapuano wheel; its live words sit in VGPRs as a ring
+//    of M slots (slot k mod M holds I(k)); a block of B consecutive draws is
+//    compiled for one of V = M / B ring phases, so every register index is
+//    static (the paper's "wheel in logic, not memory", sec. 3.3);
+//  * the B sites served by those draws are one 32-bit word of the bit-packed
+//    lattice; each draw is compared with the site's thresholds and the compare
+//    result (a 64-lane mask) is shifted into per-lane accumulator words with
+//    add-with-carry, so the per-site work is draw + compare + insert;
+//  * the six-neighbour unsatisfied-bond count is computed bit-sliced on whole
+//    words (32 sites per operation) from LDS-resident neighbour words;
+//  * the copies' spins stay in LDS for the whole launch; a workgroup barrier
+//    separates the two colours (sec. 3.1: same-colour sites never interact).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_layout.h"
+
+#define DEV __device__ __forceinline__
+
+namespace sg {
+
+// Global memory goes through buffer resources: an SGPR descriptor plus a
+// 32-bit per-lane byte offset; accesses outside the extent read 0 and are
+// dropped on store.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+DEV rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+DEV uint32_t bload(rsrc_t r, uint32_t voff, uint32_t soff = 0) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+DEV void bstore(rsrc_t r, uint32_t v, uint32_t voff, uint32_t soff = 0) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, 0);
+}
+
+template <int L>
+struct GC {
+  static constexpr Geom g = geom(L);
+  static constexpr int RHO = g.RHO, NG = g.NG, NW = g.NW, H = g.H, RPB = g.RPB, B = g.B,
+                       NBLK = g.NBLK, NWB = g.NWB, WZ = g.WZ, CS = g.CS, M = g.M, V = g.V;
+  static constexpr uint32_t MB = B == 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
+  static constexpr uint32_t seg_bits(int r) {
+    return (H == 32 ? 0xFFFFFFFFu : ((1u << H) - 1u)) << (B - (r + 1) * H);
+  }
+  static constexpr uint32_t lowb() {
+    uint32_t m = 0;
+    for (int r = 0; r < RPB; r++) m |= 1u << (B - (r + 1) * H);
+    return m;
+  }
+  static constexpr uint32_t topb() {
+    uint32_t m = 0;
+    for (int r = 0; r < RPB; r++) m |= 1u << (B - 1 - r * H);
+    return m;
+  }
+  static constexpr uint32_t segs(int parity) {
+    uint32_t m = 0;
+    for (int r = parity; r < RPB; r += 2) m |= seg_bits(r);
+    return m;
+  }
+  static constexpr uint32_t LOWB = lowb(), TOPB = topb(), EVENSEG = segs(0), ODDSEG = segs(1);
+};
+
+DEV uint32_t bfi(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
+
+// Full adder on bit-sliced words: sum and majority carry.
+DEV void fadd(uint32_t a, uint32_t b, uint32_t c, uint32_t &s, uint32_t &cy) {
+  uint32_t t = a ^ b;
+  s = t ^ c;
+  cy = bfi(t, c, a);
+}
+
+// Bit-sliced count of six one-bit inputs: n = n0 + 2 n1 + 4 n2.
+DEV void count6(const uint32_t u[6], uint32_t &n0, uint32_t &n1, uint32_t &n2) {
+  uint32_t s1, c1, s2, c2;
+  fadd(u[0], u[1], u[2], s1, c1);
+  fadd(u[3], u[4], u[5], s2, c2);
+  n0 = s1 ^ s2;
+  uint32_t c3 = s1 & s2;
+  fadd(c1, c2, c3, n1, n2);
+}
+
+// a > b for bit-sliced 3-bit numbers.
+DEV uint32_t gt3(uint32_t a2, uint32_t a1, uint32_t a0, uint32_t b2, uint32_t b1, uint32_t b0) {
+  uint32_t lo = a0 & ~b0;
+  uint32_t mid = (a1 & ~b1) | (~(a1 ^ b1) & lo);
+  return (a2 & ~b2) | (~(a2 ^ b2) & mid);
+}
+
+// Per-lane context of the Ising sweep.
+struct IsingLane {
+  uint32_t *sp;        // LDS base of the lane's copy
+  rsrc_t rJ;           // couplings of the job
+  uint32_t joff;       // byte offset of (sample, z) in the couplings
+  int z, zp, zm, g;
+  uint32_t T[7];       // thresholds (Metropolis: 3, heat bath: 7)
+  uint32_t A;          // "always" bits
+};
+
+// The six other-colour neighbour words of block (p, wb) and its own word.
+template <int L>
+DEV void ising_neighbours(const IsingLane &ln, int p, int blk, uint32_t &S, uint32_t N[6],
+                          uint32_t *&own) {
+  using G = GC<L>;
+  const int q = p ^ 1;
+  const int wb = ln.g * G::NBLK + blk;
+  const int y0 = ln.g * G::RHO + blk * G::RPB;
+  own = ln.sp + (p * L + ln.z) * G::WZ + wb;
+  S = *own;
+  const uint32_t *oc = ln.sp + (q * L + ln.z) * G::WZ;
+  const uint32_t Wc = oc[wb];
+  N[4] = ln.sp[(q * L + ln.zp) * G::WZ + wb];  // z+
+  N[5] = ln.sp[(q * L + ln.zm) * G::WZ + wb];  // z-
+  if constexpr (G::NWB == 1) {
+    // one block covers the whole plane: y neighbours are rows of the same word
+    if constexpr (G::RPB == 1) {
+      N[2] = Wc;
+      N[3] = Wc;
+    } else {
+      N[2] = (Wc << G::H) | (Wc >> (G::B - G::H));
+      N[3] = (Wc >> G::H) | (Wc << (G::B - G::H));
+    }
+  } else {
+    const uint32_t Wn = oc[wb + 1 == G::NWB ? 0 : wb + 1];
+    const uint32_t Wp = oc[wb == 0 ? G::NWB - 1 : wb - 1];
+    if constexpr (G::RPB == 1) {
+      N[2] = Wn;
+      N[3] = Wp;
+    } else {
+      N[2] = (Wc << G::H) | (Wn >> (G::B - G::H));  // row r needs row r + 1
+      N[3] = (Wc >> G::H) | (Wp << (G::B - G::H));  // row r needs row r - 1
+    }
+  }
+  // x neighbours: in a row of parity e = (p + y + z) & 1, site j (x = 2j + e)
+  // has x+1 at other-colour index j + e and x-1 at index j + e - 1 (periodic
+  // within the row).
+  const uint32_t rl = bfi(G::LOWB, Wc >> (G::H - 1), Wc << 1);  // index j+1 into j
+  const uint32_t rr = bfi(G::TOPB, Wc << (G::H - 1), Wc >> 1);  // index j-1 into j
+  const uint32_t em = ((p + y0 + ln.z) & 1) ? G::EVENSEG : G::ODDSEG;
+  N[0] = bfi(em, rl, Wc);
+  N[1] = bfi(em, Wc, rr);
+}
+
+template <int L>
+DEV void ising_couplings(const IsingLane &ln, int p, int blk, uint32_t Jw[6]) {
+  using G = GC<L>;
+  const int wb = ln.g * G::NBLK + blk;
+  const uint32_t off = ln.joff + (uint32_t)((p * G::NWB + wb) * 6 * L) * 4u;
+#pragma unroll
+  for (int d = 0; d < 6; d++) Jw[d] = bload(ln.rJ, off + d * L * 4);
+}
+
+// One Metropolis draw: I(k) = I(k-24) + I(k-55), r = I(k) xor I(k-61) (Eq. 5);
+// c1 = [r < T1], c0 = [r < (c1 ? T0 : T2)]; both 64-lane compare masks are
+// shifted into the per-lane accumulators by add-with-carry (acc = 2 acc + c).
+// ALU instructions only; 7 VALU operations per site.
+DEV void met_step(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T0,
+                  uint32_t T1, uint32_t T2, uint32_t &b1, uint32_t &b0) {
+  uint32_t r, ts;
+  uint64_t m1, m0, j1, j0;
+  asm("v_add_u32 %[n], %[a], %[b]\n\t"
+      "v_xor_b32 %[r], %[n], %[c]\n\t"
+      "v_cmp_lt_u32 %[m1], %[r], %[T1]\n\t"
+      "v_cndmask_b32 %[ts], %[T2], %[T0], %[m1]\n\t"
+      "v_cmp_lt_u32 %[m0], %[r], %[ts]\n\t"
+      "v_addc_co_u32 %[b1], %[j1], %[b1], %[b1], %[m1]\n\t"
+      "v_addc_co_u32 %[b0], %[j0], %[b0], %[b0], %[m0]"
+      : [n] "=&v"(inew), [r] "=&v"(r), [ts] "=&v"(ts), [m1] "=&s"(m1), [m0] "=&s"(m0),
+        [j1] "=&s"(j1), [j0] "=&s"(j0), [b1] "+v"(b1), [b0] "+v"(b0)
+      : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T0] "v"(T0), [T1] "v"(T1), [T2] "v"(T2));
+}
+
+// One heat-bath draw: b = #{k : r < T[k]} over seven nested thresholds, three
+// bits found by binary search and shifted into b2, b1, b0.  11 VALU operations.
+DEV void hb_step(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, const uint32_t T[7],
+                 uint32_t &b2, uint32_t &b1, uint32_t &b0) {
+  uint32_t r, ta, x, y, tb;
+  uint64_t m2, m1, m0, j2, j1, j0;
+  asm("v_add_u32 %[n], %[a], %[b]\n\t"
+      "v_xor_b32 %[r], %[n], %[c]\n\t"
+      "v_cmp_lt_u32 %[m2], %[r], %[T3]\n\t"
+      "v_cndmask_b32 %[ta], %[T5], %[T1], %[m2]\n\t"
+      "v_cndmask_b32 %[x], %[T6], %[T2], %[m2]\n\t"
+      "v_cndmask_b32 %[y], %[T4], %[T0], %[m2]\n\t"
+      "v_cmp_lt_u32 %[m1], %[r], %[ta]\n\t"
+      "v_cndmask_b32 %[tb], %[x], %[y], %[m1]\n\t"
+      "v_cmp_lt_u32 %[m0], %[r], %[tb]\n\t"
+      "v_addc_co_u32 %[b2], %[j2], %[b2], %[b2], %[m2]\n\t"
+      "v_addc_co_u32 %[b1], %[j1], %[b1], %[b1], %[m1]\n\t"
+      "v_addc_co_u32 %[b0], %[j0], %[b0], %[b0], %[m0]"
+      : [n] "=&v"(inew), [r] "=&v"(r), [ta] "=&v"(ta), [x] "=&v"(x), [y] "=&v"(y),
+        [tb] "=&v"(tb), [m2] "=&s"(m2), [m1] "=&s"(m1), [m0] "=&s"(m0), [j2] "=&s"(j2),
+        [j1] "=&s"(j1), [j0] "=&s"(j0), [b2] "+v"(b2), [b1] "+v"(b1), [b0] "+v"(b0)
+      : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T0] "v"(T[0]), [T1] "v"(T[1]),
+        [T2] "v"(T[2]), [T3] "v"(T[3]), [T4] "v"(T[4]), [T5] "v"(T[5]), [T6] "v"(T[6]));
+}
+
+// One block: B draws of the lane's wheel at ring phase VI, one per site.
+template <int L, int ALGO, int VI>
+DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int blk,
+                     bool any_always) {
+  using G = GC<L>;
+  constexpr int M = G::M, B = G::B;
+  uint32_t S, N[6], Jw[6];
+  uint32_t *own;
+  ising_neighbours<L>(ln, p, blk, S, N, own);
+  ising_couplings<L>(ln, p, blk, Jw);
+  // bit-sliced neighbour count, done before the draws to keep few words live
+  uint32_t n0, n1, n2;
+  {
+    uint32_t u[6];
+#pragma unroll
+    for (int d = 0; d < 6; d++) u[d] = ALGO == 0 ? (S ^ N[d] ^ Jw[d]) : (N[d] ^ Jw[d]);
+    count6(u, n0, n1, n2);
+  }
+
+  uint32_t b0 = 0, b1 = 0, b2 = 0;
+#pragma unroll
+  for (int i = 0; i < B; i++) {
+    const int k = VI * B + i;  // static after unrolling
+    if constexpr (ALGO == 0)
+      met_step(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
+               ring[(k + M - 61) % M], ln.T[0], ln.T[1], ln.T[2], b1, b0);
+    else
+      hb_step(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
+              ring[(k + M - 61) % M], ln.T, b2, b1, b0);
+  }
+
+  if constexpr (ALGO == 0) {
+    // Metropolis: n unsatisfied bonds; flip iff n >= 3 or r < T[n], i.e. n + b >= 3.
+    uint32_t acc = n2 | (n1 & (n0 | b0 | b1)) | (b1 & (n0 | b0));
+    if (any_always) {
+      const uint32_t A0 = (ln.A & 1) ? ~0u : 0u, A1 = (ln.A & 2) ? ~0u : 0u,
+                     A2 = (ln.A & 4) ? ~0u : 0u;
+      acc |= A0 | (A1 & (n0 | n1 | n2)) | (A2 & (n1 | n2));
+    }
+    *own = S ^ (acc & G::MB);
+  } else {
+    // Heat bath: m = #{d : J_d s_d = -1}, k = 6 - m; s = +1 iff r < T[k], i.e. b > m.
+    uint32_t plus = gt3(b2, b1, b0, n2, n1, n0);
+    if (any_always && ln.A) {
+      // T[k] = 2^32 for every k >= kmin: force +1 where m <= 6 - kmin
+      const int a = 6 - (__ffs(ln.A) - 1);
+      const uint32_t a2 = (a & 4) ? ~0u : 0u, a1 = (a & 2) ? ~0u : 0u, a0 = (a & 1) ? ~0u : 0u;
+      plus |= ~gt3(n2, n1, n0, a2, a1, a0);
+    }
+    *own = ~plus & G::MB;
+  }
+}
+
+// Number of unsatisfied bonds touching the lane's colour-0 sites (every bond
+// has exactly one colour-0 end, so the per-copy sum is U and E = 2U - 3N).
+template <int L>
+DEV int ising_lane_unsat(const IsingLane &ln) {
+  using G = GC<L>;
+  int U = 0;
+  for (int blk = 0; blk < G::NBLK; blk++) {
+    uint32_t S, N[6], Jw[6], u[6];
+    uint32_t *own;
+    ising_neighbours<L>(ln, 0, blk, S, N, own);
+    ising_couplings<L>(ln, 0, blk, Jw);
+#pragma unroll
+    for (int d = 0; d < 6; d++) u[d] = S ^ N[d] ^ Jw[d];
+    uint32_t n0, n1, n2;
+    count6(u, n0, n1, n2);
+    U += __popc(n0 & G::MB) + 2 * __popc(n1 & G::MB) + 4 * __popc(n2 & G::MB);
+  }
+  return U;
+}
+
+// Ring residency.  Register slot r holds draw j = k0 + r (mod M); its memory
+// slot is j mod M = (r + k0) mod M.  The launch always starts at register
+// phase 0, so only the 61 live words I(k0-61) .. I(k0-1) (registers
+// M-61 .. M-1) are loaded, and after the block of phase VI only the 61 words
+// written last are stored back.
+template <int M>
+DEV void ring_load(uint32_t (&ring)[M], rsrc_t r, uint32_t voff, uint32_t stride, int kmod) {
+#pragma unroll
+  for (int i = M - 61; i < M; i++) {
+    const uint32_t slot = __builtin_amdgcn_readfirstlane((uint32_t)((i + kmod) % M));
+    ring[i] = bload(r, voff, slot * stride);
+  }
+}
+
+template <int M, int LAST>
+DEV void ring_store(const uint32_t (&ring)[M], rsrc_t r, uint32_t voff, uint32_t stride, int kmod) {
+#pragma unroll
+  for (int n = 0; n < 61; n++) {
+    const int i = (LAST - n + M) % M;  // static
+    const uint32_t slot = __builtin_amdgcn_readfirstlane((uint32_t)((i + kmod) % M));
+    bstore(r, ring[i], voff, slot * stride);
+  }
+}
+
+// Sweep driver shared by the kernels: the launch's blocks cycle through the V
+// ring phases in order; a workgroup barrier closes every half-sweep.
+struct Drive {
+  int p, blk, s, nsweeps;
+  bool active;
+  rsrc_t rwh;
+  uint32_t widx, wstride;
+  int kmod;
+};
+
+template <class K, int VI>
+DEV bool drive_chain(K &k, uint32_t (&ring)[K::M], Drive &d) {
+  if (d.active) k.template block<VI>(ring, d.p, d.blk);
+  if (++d.blk == K::NBLK) {
+    d.blk = 0;
+    __syncthreads();
+    d.p ^= 1;
+    if (d.p == 0 && ++d.s == d.nsweeps) {
+      if (d.active) ring_store<K::M, (VI + 1) * K::B - 1>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+      return true;
+    }
+  }
+  if constexpr (VI + 1 < K::V)
+    return drive_chain<K, VI + 1>(k, ring, d);
+  else
+    return false;
+}
+
+template <class K>
+DEV void drive(K &k, Drive &d) {
+  if (d.nsweeps <= 0) return;
+  uint32_t ring[K::M];
+  if (d.active) ring_load<K::M>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+  d.p = 0;
+  d.blk = 0;
+  d.s = 0;
+  while (!drive_chain<K, 0>(k, ring, d)) {
+  }
+}
+
+template <int L, int ALGO>
+struct IsingK {
+  using G = GC<L>;
+  static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK;
+  IsingLane ln;
+  bool any_always;
+  template <int VI>
+  DEV void block(uint32_t (&ring)[M], int p, int blk) {
+    ising_block<L, ALGO, VI>(ring, ln, p, blk, any_always);
+  }
+};
+
+template <int L, int ALGO>
+DEV void ising_run(const Work &w, uint32_t *lds) {
+  using G = GC<L>;
+  const int t = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int lanes = w.ncopies * G::NW;
+  const bool active = t < lanes;
+  int *Ucnt = (int *)(lds + w.ncopies * G::CS);
+  const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
+
+  // stage the copies in LDS
+  const uint32_t sbase = (uint32_t)w.copy0 * G::CS * 4u;
+  for (int i = t; i < w.ncopies * G::CS; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
+  for (int i = t; i < w.ncopies; i += nthr) Ucnt[i] = 0;
+
+  IsingK<L, ALGO> k;
+  IsingLane &ln = k.ln;
+  const int cl = active ? t / G::NW : 0;
+  const int wl = t - cl * G::NW;
+  const int copy = w.copy0 + cl;
+  ln.sp = lds + cl * G::CS;
+  ln.g = wl / L;
+  ln.z = wl - ln.g * L;
+  ln.zp = ln.z + 1 == L ? 0 : ln.z + 1;
+  ln.zm = ln.z == 0 ? L - 1 : ln.z - 1;
+  ln.rJ = make_rsrc(w.J, w.J_bytes);
+  ln.joff = ((uint32_t)(copy / w.RK) * ising_js(L) + ln.z) * 4u;
+  ln.A = 0;
+#pragma unroll
+  for (int q = 0; q < 7; q++) ln.T[q] = 0;
+  if (active) {
+    const uint32_t *tr = w.thr + w.temp_of_slot[copy] * THR_WORDS;
+#pragma unroll
+    for (int q = 0; q < 7; q++) ln.T[q] = tr[q];
+    ln.A = tr[15];
+  }
+  k.any_always = __any(active && ln.A != 0);
+
+  Drive d;
+  d.nsweeps = w.nsweeps_cap;
+  d.active = active;
+  d.rwh = make_rsrc(w.wheels, w.wheels_bytes);
+  d.wstride = (uint32_t)w.C * G::NW * 4u;
+  d.widx = ((uint32_t)copy * G::NW + wl) * 4u;
+  d.kmod = (int)__builtin_amdgcn_readfirstlane((uint32_t)((*w.done * (uint64_t)(G::RHO * L)) % G::M));
+  __syncthreads();
+  drive(k, d);
+
+  // energy of every copy, then write back the spins
+  if (active) atomicAdd(&Ucnt[cl], ising_lane_unsat<L>(ln));
+  __syncthreads();
+  if (w.nsweeps_cap > 0)
+    for (int i = t; i < w.ncopies * G::CS; i += nthr) bstore(rsp, lds[i], i * 4, sbase);
+  const int64_t N3 = (int64_t)L * L * L;
+  for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = 2 * (int64_t)Ucnt[i] - 3 * N3;
+}
+
+// ---------------------------------------------------------------------------
+// q = 4 +-J Potts heat bath.  One lane per wheel; each draw updates one site:
+//   h_a = sum_j J_ij delta(a, sigma_j) is accumulated in four byte fields of one
+//   word (J = +1 counts in the low nibble, J = -1 in the high nibble of byte a),
+//   w_a = W[h_max - h_a] comes from the lane's LDS table, t = (r S) >> 32 and
+//   sigma = #{a < 3 : C_a <= t} with C_a the running sums of w.
+// ---------------------------------------------------------------------------
+DEV uint32_t bload_u8(rsrc_t r, uint32_t voff) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, voff, 0, 0);
+}
+
+template <int L>
+struct PottsK {
+  using G = GC<L>;
+  static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK, H = G::H, RPB = G::RPB,
+                       RHO = G::RHO;
+  uint8_t *sp;         // LDS bytes of the lane's copy, [y][x][z], value 8 sigma
+  const uint32_t *Wl;  // LDS weight table of the lane's temperature
+  rsrc_t rJ;           // coupling patterns of the job
+  uint32_t joff;       // byte offset of the lane's sample
+  int z, zp, zm, g;
+
+  // local fields of site with neighbour states s[6] (8 sigma) and pattern pat
+  static DEV uint32_t fields(const uint32_t s[6], uint32_t pat) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int d = 0; d < 6; d++) acc += 1u << (s[d] + (((pat >> d) & 1u) << 2));
+    const uint32_t lo = acc & 0x0F0F0F0Fu, hi = (acc >> 4) & 0x0F0F0F0Fu;
+    return lo + 0x06060606u - hi;  // byte a = 6 + h_a in 0..12
+  }
+
+  template <int VI>
+  DEV void block(uint32_t (&ring)[M], int p, int blk) {
+    const int y0 = g * RHO + blk * RPB;
+#pragma unroll
+    for (int rr = 0; rr < RPB; rr++) {
+      const int y = y0 + rr;
+      const int e = (p + y + z) & 1;
+      const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+      const int base = (y * L + e) * L + z;          // site j = 0 of the row
+      const int bxw = e ? base - L : base + (L - 1) * L;  // periodic x neighbour
+      const int byp = (yp * L + e) * L + z, bym = (ym * L + e) * L + z;
+      const int bzp = base - z + zp, bzm = base - z + zm;
+#pragma unroll
+      for (int j = 0; j < H; j++) {
+        const int k = VI * B + rr * H + j;  // static
+        ring[k % M] = ring[(k + M - 24) % M] + ring[(k + M - 55) % M];
+        const uint32_t r = ring[k % M] ^ ring[(k + M - 61) % M];
+        const int o = 2 * j * L;
+        uint32_t s[6];
+        s[0] = sp[j == H - 1 ? bxw : base + o + L];
+        s[1] = sp[j == 0 ? bxw : base + o - L];
+        s[2] = sp[byp + o];
+        s[3] = sp[bym + o];
+        s[4] = sp[bzp + o];
+        s[5] = sp[bzm + o];
+        const uint32_t pat = bload_u8(rJ, joff + base + o);
+        const uint32_t c = fields(s, pat);
+        const uint32_t c0 = c & 0xFFu, c1 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c3 = c >> 24;
+        const uint32_t cm = max(max(c0, c1), max(c2, c3));
+        const uint32_t w0 = Wl[cm - c0], w1 = Wl[cm - c1], w2 = Wl[cm - c2], w3 = Wl[cm - c3];
+        const uint32_t S = w0 + w1 + w2 + w3;
+        const uint32_t t = __umulhi(r, S);
+        const uint32_t C0 = w0, C1 = w0 + w1, C2 = C1 + w2;
+        const uint32_t sig = (uint32_t)(t >= C0) + (uint32_t)(t >= C1) + (uint32_t)(t >= C2);
+        sp[base + o] = (uint8_t)(sig << 3);
+      }
+    }
+  }
+
+  // sum over the lane's colour-0 sites of h_{sigma_i} (each bond once)
+  DEV int lane_bond_sum(int) const {
+    int hsum = 0;
+    for (int blk = 0; blk < NBLK; blk++) {
+      const int y0 = g * RHO + blk * RPB;
+      for (int rr = 0; rr < RPB; rr++) {
+        const int y = y0 + rr;
+        const int e = (y + z) & 1;
+        const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+        const int base = (y * L + e) * L + z;
+        const int bxw = e ? base - L : base + (L - 1) * L;
+        const int byp = (yp * L + e) * L + z, bym = (ym * L + e) * L + z;
+        const int bzp = base - z + zp, bzm = base - z + zm;
+        for (int j = 0; j < H; j++) {
+          const int o = 2 * j * L;
+          uint32_t s[6];
+          s[0] = sp[j == H - 1 ? bxw : base + o + L];
+          s[1] = sp[j == 0 ? bxw : base + o - L];
+          s[2] = sp[byp + o];
+          s[3] = sp[bym + o];
+          s[4] = sp[bzp + o];
+          s[5] = sp[bzm + o];
+          const uint32_t c = fields(s, bload_u8(rJ, joff + base + o));
+          hsum += (int)((c >> sp[base + o]) & 0xFFu) - 6;
+        }
+      }
+    }
+    return hsum;
+  }
+};
+
+template <int L>
+DEV void potts_run(const Work &w, uint32_t *lds) {
+  using G = GC<L>;
+  constexpr int N3 = L * L * L;
+  constexpr int CW = N3 / 4;  // words per copy in LDS
+  const int t = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int lanes = w.ncopies * G::NW;
+  const bool active = t < lanes;
+  uint32_t *Wt = lds + w.ncopies * CW;          // [ncopies][16] weight tables
+  int *Hcnt = (int *)(Wt + w.ncopies * 16);     // [ncopies]
+  const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
+  const uint32_t sbase = (uint32_t)w.copy0 * N3;
+  for (int i = t; i < w.ncopies * CW; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
+  for (int i = t; i < w.ncopies * 16; i += nthr) {
+    const int c = w.copy0 + i / 16;
+    Wt[i] = w.thr[w.temp_of_slot[c] * THR_WORDS + (i & 15)];
+  }
+  for (int i = t; i < w.ncopies; i += nthr) Hcnt[i] = 0;
+
+  PottsK<L> k;
+  const int cl = active ? t / G::NW : 0;
+  const int wl = t - cl * G::NW;
+  const int copy = w.copy0 + cl;
+  k.sp = (uint8_t *)(lds + cl * CW);
+  k.Wl = Wt + cl * 16;
+  k.g = wl / L;
+  k.z = wl - k.g * L;
+  k.zp = k.z + 1 == L ? 0 : k.z + 1;
+  k.zm = k.z == 0 ? L - 1 : k.z - 1;
+  k.rJ = make_rsrc(w.J, w.J_bytes);
+  k.joff = (uint32_t)(copy / w.RK) * N3;
+
+  Drive d;
+  d.nsweeps = w.nsweeps_cap;
+  d.active = active;
+  d.rwh = make_rsrc(w.wheels, w.wheels_bytes);
+  d.wstride = (uint32_t)w.C * G::NW * 4u;
+  d.widx = ((uint32_t)copy * G::NW + wl) * 4u;
+  d.kmod = (int)__builtin_amdgcn_readfirstlane((uint32_t)((*w.done * (uint64_t)(G::RHO * L)) % G::M));
+  __syncthreads();
+  drive(k, d);
+
+  if (active) atomicAdd(&Hcnt[cl], k.lane_bond_sum(0));
+  __syncthreads();
+  if (w.nsweeps_cap > 0)
+    for (int i = t; i < w.ncopies * CW; i += nthr) bstore(rsp, lds[i], i * 4, sbase);
+  for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = -(int64_t)Hcnt[i];
+}
+
+__global__ __launch_bounds__(1024) void potts_sweep_kernel(const Work *__restrict__ works,
+                                                          int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  switch (w.L) {
+    case 2: potts_run<2>(w, lds); break;
+    case 4: potts_run<4>(w, lds); break;
+    case 8: potts_run<8>(w, lds); break;
+    case 16: potts_run<16>(w, lds); break;
+    case 24: potts_run<24>(w, lds); break;
+    case 32: potts_run<32>(w, lds); break;
+    case 40: potts_run<40>(w, lds); break;
+    case 48: potts_run<48>(w, lds); break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Overlap between replica 0 and replica 1 at every temperature.
+//   Ising: Q = N - 2 popcount(a xor b) over the packed words (pads are zero);
+//   Potts: C = number of equal site bytes.
+// grid = S * K, one workgroup per (sample, temperature).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void overlap_kernel(const uint32_t *__restrict__ spins,
+                                                      const int32_t *__restrict__ slot_of_temp,
+                                                      int64_t *__restrict__ Q, int model, int L,
+                                                      int R, int K, int copy_words) {
+  __shared__ int part[256];
+  const int sk = blockIdx.x;
+  const int s = sk / K, k = sk - s * K;
+  const int ca = (s * R + 0) * K + slot_of_temp[(s * R + 0) * K + k];
+  const int cb = (s * R + 1) * K + slot_of_temp[(s * R + 1) * K + k];
+  const uint32_t *a = spins + (size_t)ca * copy_words;
+  const uint32_t *b = spins + (size_t)cb * copy_words;
+  int acc = 0;
+  for (int i = threadIdx.x; i < copy_words; i += blockDim.x) {
+    const uint32_t x = a[i] ^ b[i];
+    if (model == 0) {
+      acc += __popc(x);
+    } else {
+      // count equal bytes: a byte of x is zero iff the two sites agree
+      const uint32_t nz = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
+      acc += 4 - __popc(nz & 0x80808080u);
+    }
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t N = (int64_t)L * L * L;
+    Q[sk] = model == 0 ? N - 2 * (int64_t)part[0] : (int64_t)part[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Parallel tempering, one thread per (sample, replica) chain.  Pairs of
+// neighbouring temperatures in ascending order; one number of the chain's own
+// wheel per pair; accept when sign(dbeta) * D <= 0, else when r < T with T the
+// integer product of the factors F[b] over the set bits of |D|.
+// The chain wheel is stored as 61 words + the position of the oldest word.
+// ---------------------------------------------------------------------------
+DEV uint32_t ptw_next(uint32_t *w) {
+  int pos = (int)w[61];
+  auto back = [&](int m) { int j = pos - m; return w[j < 0 ? j + 61 : j]; };
+  const uint32_t ik = back(24) + back(55);
+  const uint32_t out = ik ^ w[pos];
+  w[pos] = ik;
+  w[61] = pos == 60 ? 0 : pos + 1;
+  return out;
+}
+
+__global__ __launch_bounds__(64) void pt_kernel(const int64_t *__restrict__ E,
+                                                int32_t *__restrict__ slot_of_temp,
+                                                int32_t *__restrict__ temp_of_slot,
+                                                uint32_t *__restrict__ ptw,
+                                                const uint64_t *__restrict__ F,
+                                                const int32_t *__restrict__ sgn,
+                                                uint64_t *__restrict__ accepts, int chains, int K) {
+  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= chains) return;
+  int32_t *so = slot_of_temp + (size_t)ch * K;
+  uint32_t *w = ptw + (size_t)ch * 64;
+  const int64_t *Ec = E + (size_t)ch * K;
+  for (int i = 0; i + 1 < K; i++) {
+    const int a = so[i], b = so[i + 1];
+    const int64_t D = Ec[b] - Ec[a];
+    const uint32_t r = ptw_next(w);
+    const int sd = D > 0 ? 1 : (D < 0 ? -1 : 0);
+    bool accept;
+    if (sgn[i] * sd <= 0) {
+      accept = true;
+    } else {
+      const uint64_t aD = (uint64_t)(D < 0 ? -D : D);
+      uint64_t T = 0;
+      if (aD < (1ull << 24)) {
+        T = 1ull << 32;
+        const uint64_t *Fi = F + (size_t)i * 24;
+        for (int bb = 0; bb < 24; bb++)
+          if ((aD >> bb) & 1) {
+            // floor(T * F / 2^32), exact: T <= 2^32, F <= 2^32
+            const uint64_t f = Fi[bb];
+            T = __umul64hi(T, f) << 32 | ((T * f) >> 32);
+          }
+      }
+      accept = (uint64_t)r < T;
+    }
+    if (accept) {
+      so[i] = b;
+      so[i + 1] = a;
+      if (accepts) accepts[(size_t)ch * (K - 1) + i]++;
+    }
+  }
+  for (int i = 0; i < K; i++) temp_of_slot[(size_t)ch * K + so[i]] = i;
+}
+
+// ---------------------------------------------------------------------------
+// Next n outputs of one sweep wheel, state untouched (test hook).
+// ---------------------------------------------------------------------------
+__global__ void debug_rng_kernel(const uint32_t *__restrict__ wheels, uint32_t *__restrict__ out,
+                                 uint64_t wstride_words, uint64_t widx, int M, uint64_t k0, int n) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t w[62];
+  for (int j = 0; j < 61; j++) {
+    const uint64_t kj = k0 + M - 61 + j;  // draw index k0 - 61 + j, shifted to stay >= 0
+    w[j] = wheels[(kj % M) * wstride_words + widx];
+  }
+  w[61] = 0;
+  for (int i = 0; i < n; i++) out[i] = ptw_next(w);
+}
+
+template <int ALGO>
+__global__ __launch_bounds__(1024) void ising_sweep_kernel(const Work *__restrict__ works,
+                                                          int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  switch (w.L) {
+    case 2: ising_run<2, ALGO>(w, lds); break;
+    case 4: ising_run<4, ALGO>(w, lds); break;
+    case 8: ising_run<8, ALGO>(w, lds); break;
+    case 16: ising_run<16, ALGO>(w, lds); break;
+    case 24: ising_run<24, ALGO>(w, lds); break;
+    case 32: ising_run<32, ALGO>(w, lds); break;
+    case 40: ising_run<40, ALGO>(w, lds); break;
+    case 48: ising_run<48, ALGO>(w, lds); break;
+    case 56: ising_run<56, ALGO>(w, lds); break;
+    case 64: ising_run<64, ALGO>(w, lds); break;
+    default: break;
+  }
+}
+
+template __global__ void ising_sweep_kernel<0>(const Work *, int);
+template __global__ void ising_sweep_kernel<1>(const Work *, int);
+
+}  // namespace sg
+
+// ---------------------------------------------------------------------------
+// Launchers used by the host library (same translation unit as the kernels).
+// ---------------------------------------------------------------------------
+namespace sg {
+
+// done[j] += min(cap[j], nsweeps) for every job of a launch (sweep counters
+// live on the device so that a captured graph can be replayed).
+__global__ void advance_kernel(uint64_t *const *__restrict__ done, const int32_t *__restrict__ cap,
+                               int n, int nsweeps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *done[i] += (uint64_t)min(cap[i], nsweeps);
+}
+
+__global__ void add_kernel(uint64_t *p, uint64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p += v;
+}
+
+hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st) {
+  hipLaunchKernelGGL(add_kernel, dim3(1), dim3(64), 0, st, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, int tpb,
+                        size_t lds, int nsweeps, hipStream_t st) {
+  if (nworks <= 0) return hipSuccess;
+  if (model == 1)
+    hipLaunchKernelGGL(potts_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (algo == 0)
+    hipLaunchKernelGGL(ising_sweep_kernel<0>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else
+    hipLaunchKernelGGL(ising_sweep_kernel<1>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  return hipGetLastError();
+}
+
+hipError_t set_max_lds(int bytes) {
+  hipError_t e = hipFuncSetAttribute((const void *)potts_sweep_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)ising_sweep_kernel<0>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)ising_sweep_kernel<1>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_overlap(const uint32_t *spins, const int32_t *slot_of_temp, int64_t *Q, int model,
+                          int L, int S, int R, int K, int copy_words, hipStream_t st) {
+  if (S * K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(overlap_kernel, dim3(S * K), dim3(256), 0, st, spins, slot_of_temp, Q, model,
+                     L, R, K, copy_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_pt(const int64_t *E, int32_t *slot_of_temp, int32_t *temp_of_slot, uint32_t *ptw,
+                     const uint64_t *F, const int32_t *sgn, uint64_t *accepts, int chains, int K,
+                     hipStream_t st) {
+  if (chains <= 0 || K < 2) return hipSuccess;
+  hipLaunchKernelGGL(pt_kernel, dim3((chains + 63) / 64), dim3(64), 0, st, E, slot_of_temp,
+                     temp_of_slot, ptw, F, sgn, accepts, chains, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_rng(const uint32_t *wheels, uint32_t *out, uint64_t wstride_words,
+                            uint64_t widx, int M, uint64_t k0, int n, hipStream_t st) {
+  hipLaunchKernelGGL(debug_rng_kernel, dim3(1), dim3(64), 0, st, wheels, out, wstride_words, widx,
+                     M, k0, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(uint64_t *const *done, const int32_t *cap, int n, int nsweeps,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(advance_kernel, dim3((n + 63) / 64), dim3(64), 0, st, done, cap, n, nsweeps);
+  return hipGetLastError();
+}
+
+}  // namespace sg

@@ -1,0 +1,88 @@
+// Device data layout of the checkerboard sweep: geometry constants shared by
+// the host-side packing code and the gfx950 kernels.  (Internal header; the
+// public boundary is include/sg.h.)
+//
+// Ising copy (bit-packed, 1 bit per spin, bit 1 <-> spin -1):
+//   The rho = min(8, L) rows of one z-plane served by one Parisi-Rapuano wheel
+//   are cut into NBLK blocks of RPB rows.  A block holds B = RPB * L/2 sites of
+//   one colour, exactly the B consecutive draws of the wheel, and is stored in
+//   one 32-bit word, most significant bit first: the k-th site of the block in
+//   draw order (row r, then x = 2j + e) sits at bit B - 1 - k.  Words are
+//   indexed [colour p][plane z][block-row wb] with the wb stride padded to an
+//   odd count WZ (LDS bank spread).  Unused high bits are zero.
+// Ising couplings: six words per (colour, wb, z), one per bond direction
+//   (x+, x-, y+, y-, z+, z-), same bit order, bit 1 <-> J = -1, laid out
+//   [p][wb][d][z] so that the lanes of a wave (consecutive z) read one
+//   contiguous segment.
+// Potts copy: one byte per site holding 8 * sigma, ordered [y][x][z] (z
+//   fastest: the lanes of a wave serve consecutive z planes).  Potts
+//   couplings: one byte per site whose bit d is set when the bond in
+//   direction d (x+, x-, y+, y-, z+, z-) has J = -1, same [y][x][z] order.
+// Wheels: M >= 62 slots per wheel, slot (k mod M) holds I(k); slots are
+//   stored [slot][copy * NW + wheel] (coalesced across lanes).
+#pragma once
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#define SG_HD __host__ __device__
+#else
+#define SG_HD
+#endif
+
+namespace sg {
+
+struct Geom {
+  int L, RHO, NG, NW, H, RPB, B, NBLK, NWB, WZ, CS, M, V;
+};
+
+SG_HD constexpr Geom geom(int L) {
+  Geom g{};
+  g.L = L;
+  g.RHO = L < 8 ? L : 8;             // rows per wheel
+  g.NG = L / g.RHO;                  // row groups per plane
+  g.NW = L * g.NG;                   // wheels per copy
+  g.H = L / 2;                       // sites of one colour per row
+  int r = g.H >= 32 ? 1 : 32 / g.H;  // rows per 32-bit block word
+  g.RPB = r < g.RHO ? r : g.RHO;
+  g.B = g.RPB * g.H;                 // sites (and draws) per block
+  g.NBLK = g.RHO / g.RPB;            // blocks per half-sweep per wheel
+  g.NWB = g.L / g.RPB;               // block words per (colour, plane)
+  g.WZ = g.NWB | 1;                  // padded stride
+  g.CS = 2 * g.L * g.WZ;             // words per Ising copy
+  g.M = ((62 + g.B - 1) / g.B) * g.B;  // ring slots, a multiple of B
+  g.V = g.M / g.B;                   // distinct block phases of the ring
+  return g;
+}
+
+SG_HD constexpr bool supported_L(int L) {
+  return L == 2 || L == 4 || L == 8 || L == 16 || L == 24 || L == 32 || L == 40 || L == 48 ||
+         L == 56 || L == 64;
+}
+
+SG_HD constexpr bool potts_supported_L(int L) { return supported_L(L) && L <= 48; }
+
+// Words of Ising couplings per sample.
+SG_HD constexpr int ising_js(int L) { return 2 * geom(L).NWB * 6 * L; }
+
+// Per-temperature threshold row: 16 words.  Ising Metropolis uses [0..2],
+// heat bath [0..6], Potts [0..12]; a threshold equal to 2^32 is stored as
+// 0xFFFFFFFF with bit n of word 15 set ("always").
+constexpr int THR_WORDS = 16;
+
+// One work item of a sweep launch: G complete copies of one job, served by
+// G * NW lanes of one workgroup.
+struct Work {
+  uint32_t *spins;               // job spins (device layout), all copies
+  const uint32_t *J;             // job couplings, all samples
+  uint32_t *wheels;              // job wheel slots
+  const int32_t *temp_of_slot;   // [C]
+  const uint32_t *thr;           // [K][THR_WORDS]
+  int64_t *E;                    // [C] energy per slot (written at the end)
+  int32_t L, algo, model, copy0, ncopies, C, RK;
+  int32_t nsweeps_cap;           // the item runs min(launch sweeps, cap) sweeps
+  uint32_t spins_bytes, J_bytes, wheels_bytes;  // extents (buffer range checks)
+  uint32_t pad;
+  const uint64_t *done;          // sweeps already performed by the job (device)
+};
+
+}  // namespace sg

@@ -1,0 +1,49 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every symbol that
+include/sg.h declares, and validates specifications (no GPU calls)."""
+import os
+import re
+
+import pytest
+
+from paper_0704_3573_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "sg.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int32_t|const char \*)\s*(sg_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTS) == names
+
+
+def test_wheels_per_copy():
+    for L, nw in ((2, 2), (4, 4), (8, 8), (16, 32), (24, 72), (32, 128), (48, 288), (64, 512)):
+        assert B.wheels_per_copy(L) == nw
+    assert B.wheels_per_copy(12) == 0 and B.wheels_per_copy(72) == 0
+
+
+def test_job_bytes_and_validation():
+    n = B.job_bytes(B.Spec(B.ISING, B.METROPOLIS, 4, 64, 1, 2, 1, 0))
+    # two copies of 64^3 bit-packed spins, shared couplings, 512 wheels x 64 slots each
+    assert 2 * 64 ** 3 // 8 + 512 * 64 * 4 * 2 < n < 1_000_000
+    for spec, code in (
+        (B.Spec(B.ISING, B.METROPOLIS, 4, 12, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.POTTS, B.METROPOLIS, 4, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.POTTS, B.HEATBATH, 3, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.POTTS, B.HEATBATH, 4, 64, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.ISING, B.METROPOLIS, 4, 8, 0, 1, 1, 0), B.SG_E_INVALID),
+        (B.Spec(B.ISING, 7, 4, 8, 1, 1, 1, 0), B.SG_E_INVALID),
+        (B.Spec(B.ISING, B.METROPOLIS, 4, 8, 1, 1, 1, -1), B.SG_E_INVALID),
+    ):
+        with pytest.raises(B.SgError) as e:
+            B.job_bytes(spec)
+        assert e.value.code == code
+        assert B.lib().sg_last_error().decode()
