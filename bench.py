@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark: spin updates per nanosecond on one MI355X, batched and plain.
+
+Headline (value): the batched parallel-tempering workload -- 256 disorder
+samples of the 3D Edwards-Anderson +-J glass (64 each at L = 16, 24, 32, 48)
+x 2 replicas x 32 temperatures (T = 0.7 .. 1.6 linear), Metropolis
+checkerboard sweeps with a parallel-tempering step every 10 sweeps, all of
+them advanced by one fused sweep launch per period replayed from a captured
+hipGraph.  One step = one period: 10 sweeps of all 16384 copies (6.6e9
+site updates) + the swap step.  Beside it, the plain single-lattice form
+(L = 64, two replicas, T = 1.1, 100 sweeps + energy/overlap measurement per
+step) and the CPU oracle timed on the host cores on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# int32 vector lanes: 256 CUs x 4 SIMD x 16 lanes per clock at 2.4 GHz
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+# algorithmic integer operations per Metropolis site update: Eq. (5) draw
+# (one add, one xor), one compare with the site's threshold, and one word
+# operation for the bit-sliced six-bond count and flip (36 word operations
+# per 32 sites)
+ALG_OPS_PER_UPDATE = 4
+C3_LS = (16, 24, 32, 48)
+C3_SAMPLES_PER_L, C3_R, C3_K, C3_PT = 64, 2, 32, 10
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def c3_alg_bytes_per_update():
+    # spins read + written once per launch of 10 sweeps is far below this;
+    # per update the method touches its own bit and the six couplings, which
+    # 64 copies of a sample share: 2 bits / 8 + 3 bits / (8 * 64)
+    return 0.25 + 0.375 / (C3_R * C3_K)
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_0704_3573_amd", "csrc", "sg_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "ising_sweep_c3_counters.txt")
+    if not os.path.exists(p):
+        return None
+    vals = {}
+    for line in open(p):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_c3(ctx, B, inputs):
+    jobs = []
+    sample0 = 0
+    betas = 1.0 / inputs.linear_temperatures(C3_K, 0.7, 1.6)
+    for L in C3_LS:
+        t = time.perf_counter()
+        inst = inputs.make_instance("ising", L, C3_SAMPLES_PER_L, C3_R, C3_K, seed=3000,
+                                    sample0=sample0)
+        jobs.append(B.Job(ctx, B.ISING, B.METROPOLIS, L, betas, inst["J"], inst["spins"],
+                          inst["wheels"], inst["ptwheels"], n_samples=C3_SAMPLES_PER_L,
+                          n_replicas=C3_R, pt_every=C3_PT))
+        del inst
+        sample0 += C3_SAMPLES_PER_L
+        log(f"[bench] job L={L}: {C3_SAMPLES_PER_L * C3_R * C3_K} copies ready in "
+            f"{time.perf_counter() - t:.1f}s")
+    return jobs
+
+
+def cpu_baseline(budget_s=15.0):
+    """The oracle on a bounded sample of the batched workload: one sample of
+    each L with its 64 copies, whole parallel-tempering periods."""
+    import numpy as np
+
+    import oracle
+    from paper_0704_3573_amd import inputs
+    threads = max(1, min(16, os.cpu_count() or 1))
+    betas = 1.0 / inputs.linear_temperatures(C3_K, 0.7, 1.6)
+    insts = [inputs.make_instance("ising", L, 1, C3_R, C3_K, seed=3000, sample0=i * 64)
+             for i, L in enumerate(C3_LS)]
+    updates, elapsed, periods = 0, 0.0, 0
+    while elapsed < budget_s and periods < 50:
+        for L, inst in zip(C3_LS, insts):
+            t = time.perf_counter()
+            out = oracle.run(oracle.ISING, oracle.METROPOLIS, L, betas, inst["J"], inst["spins"],
+                             inst["wheels"], inst["ptwheels"], n_samples=1, n_replicas=C3_R,
+                             n_sweeps=C3_PT, pt_every=C3_PT, n_threads=threads)
+            elapsed += time.perf_counter() - t
+            updates += C3_PT * C3_R * C3_K * L ** 3
+            inst["spins"], inst["wheels"], inst["ptwheels"] = (out["spins"], out["wheels"],
+                                                               out["ptwheels"])
+        periods += 1
+    del np
+    return {"value": updates / (elapsed * 1e9), "unit": "spin updates/ns", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one sample per L in {list(C3_LS)} with its {C3_R * C3_K} copies "
+                      f"(2 replicas x 32 temperatures), {periods} parallel-tempering period(s) "
+                      f"of {C3_PT} sweeps each, {updates:.3g} updates in {elapsed:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed batched steps (10 sweeps each)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--plain-steps", type=int, default=5,
+                    help="timed plain steps (100 sweeps + measurement each)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no "
+              "multi-GPU path; independent samples would be sharded one job set per GPU.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0704_3573_amd import binding as B
+    from paper_0704_3573_amd import inputs
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    stream = torch.cuda.current_stream()
+
+    # ------------------------------------------------ batched (headline) --
+    jobs = build_c3(ctx, B, inputs)
+    batch = B.Batch(ctx, jobs)
+    tpb = batch.block()
+    sites = sum(j.C * j.N for j in jobs)
+    log(f"[bench] batched: {len(jobs)} jobs, {sum(j.C for j in jobs)} copies, {sites} sites, "
+        f"block {tpb} threads")
+    for _ in range(args.warmup):
+        batch.run(C3_PT, stream)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run(C3_PT, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    updates_per_step = C3_PT * sites
+    value = updates_per_step / (ms_per_step * 1e6)
+    log(f"[bench] batched: {ms_per_step:.3f} ms/step, {value:.1f} updates/ns")
+
+    # live kernel timing: HIP events recorded inside the replayed graph around
+    # the fused sweep launch (same stream, same graph)
+    batch.set_timing(True)
+    batch.run(C3_PT, stream)
+    batch.sweep_ms()
+    kms = []
+    for _ in range(max(5, min(args.steps, 50))):
+        batch.run(C3_PT, stream)
+        kms.append(batch.sweep_ms())
+    batch.set_timing(False)
+    kernel_ms = float(np.mean(kms))
+    achieved = updates_per_step * ALG_OPS_PER_UPDATE / (kernel_ms * 1e-3) / 1e12
+    traffic = measured_traffic()
+    log(f"[bench] sweep kernel: {kernel_ms:.3f} ms per launch ({C3_PT} sweeps), "
+        f"{achieved:.2f} TOP/s algorithmic")
+    E = [j.energies() for j in jobs]
+    e_per_site = float(np.mean(np.concatenate([e / j.N for e, j in zip(E, jobs)])))
+    del batch, jobs
+
+    # --------------------------------------------------------- plain form --
+    L2 = 64
+    inst = inputs.make_instance("ising", L2, 1, 2, 1, seed=2)
+    job = B.Job(ctx, B.ISING, B.METROPOLIS, L2, [1 / 1.1], inst["J"], inst["spins"],
+                inst["wheels"], n_samples=1, n_replicas=2)
+    job.sweep(100, stream)
+    job.measure(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.plain_steps):
+        job.sweep(100, stream)
+        job.measure(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plain_ms = (t1 - t0) * 1e3 / args.plain_steps
+    plain_value = 100 * 2 * L2 ** 3 / (plain_ms * 1e6)
+    log(f"[bench] plain: {plain_ms:.1f} ms per 100 sweeps + measurement, "
+        f"{plain_value:.2f} updates/ns")
+    del job
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(args.cpu_budget)
+        log(f"[bench] CPU oracle: {cpu['value']:.4f} updates/ns on {cpu['cores']} threads")
+
+    line = {
+        "metric": "spin updates/ns on 1 MI355X (plain vs batched), bit-exact; % HBM roofline",
+        "value": round(value, 3),
+        "unit": "spin updates/ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded +-J couplings, spins and wheel seeds)",
+        "config": {
+            "workload": "batched parallel tempering: 256 EA +-J samples (64 each at L=16,24,32,48)"
+                        " x 2 replicas x 32 temperatures T=0.7..1.6, Metropolis, PT every 10 "
+                        "sweeps; step = 10 sweeps + PT step",
+            "copies": 16384, "sites": sites, "updates_per_step": updates_per_step,
+            "block_threads": tpb, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "TOP/s",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "traffic": traffic,
+            "kernel": "ising_sweep_kernel<Metropolis>",
+            "kernel_ms_per_launch": round(kernel_ms, 4),
+            "alg_ops_per_update": ALG_OPS_PER_UPDATE,
+            "hbm_alg_bytes_per_update": round(c3_alg_bytes_per_update(), 4),
+            "hbm_frac_alg": round(value * c3_alg_bytes_per_update() / HBM_PEAK_GBS, 5),
+        },
+        "plain": {
+            "value": round(plain_value, 3),
+            "unit": "spin updates/ns",
+            "workload": "EA +-J L=64, 2 replicas, T=1.1, Metropolis; step = 100 sweeps + E,Q",
+            "ms_per_step": round(plain_ms, 3),
+        },
+        "speedup_batched_over_plain": round(value / plain_value, 2),
+        "cpu_baseline": cpu,
+        "context": {"paper_fpga_ea_updates_per_ns": {"Virtex4-LX160": 31.25,
+                                                     "Virtex4-LX200": 62.5},
+                    "mean_energy_per_site": round(e_per_site, 4)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,12 @@ int sg_batch_set_block(sg_batch *b, int32_t threads);
 int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream);
 /* Threads per workgroup chosen for the current membership. */
 int sg_batch_block(sg_batch *b, int32_t *threads);
+/* Timing mode: periods are enqueued directly on the caller's stream (not
+ * replayed from the graph) with HIP events around the fused sweep launch;
+ * sg_batch_sweep_ms() returns that launch's duration in the last period,
+ * waiting for it. (sync) */
+int sg_batch_set_timing(sg_batch *b, int32_t enable);
+int sg_batch_sweep_ms(sg_batch *b, float *ms);
 int sg_batch_destroy(sg_batch *b);
 
 #ifdef __cplusplus

@@ -27,7 +27,7 @@ EXPORTS = (
     "sg_job_get_spins", "sg_job_get_wheels", "sg_job_get_perm", "sg_job_get_pt_accepts",
     "sg_job_sweeps_done", "sg_job_debug_rng", "sg_job_destroy", "sg_batch_create",
     "sg_batch_add", "sg_batch_remove", "sg_batch_set_block", "sg_batch_run", "sg_batch_block",
-    "sg_batch_destroy",
+    "sg_batch_set_timing", "sg_batch_sweep_ms", "sg_batch_destroy",
 )
 
 
@@ -78,6 +78,8 @@ def lib():
         L.sg_batch_set_block.argtypes = [vp, i32]
         L.sg_batch_run.argtypes = [vp, u64, vp]
         L.sg_batch_block.argtypes = [vp, C.POINTER(i32)]
+        L.sg_batch_set_timing.argtypes = [vp, i32]
+        L.sg_batch_sweep_ms.argtypes = [vp, C.POINTER(C.c_float)]
         L.sg_batch_destroy.argtypes = [vp]
         for n in EXPORTS:
             if n not in ("sg_last_error", "sg_wheels_per_copy"):
@@ -262,6 +264,14 @@ class Batch:
 
     def run(self, n: int, stream=None):
         _chk(lib().sg_batch_run(self.h, n, _stream(stream)))
+
+    def set_timing(self, on: bool):
+        _chk(lib().sg_batch_set_timing(self.h, int(on)))
+
+    def sweep_ms(self) -> float:
+        ms = C.c_float()
+        _chk(lib().sg_batch_sweep_ms(self.h, C.byref(ms)))
+        return ms.value
 
     def close(self):
         if getattr(self, "h", None):

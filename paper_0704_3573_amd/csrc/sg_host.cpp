@@ -741,6 +741,8 @@ struct sg_batch {
   size_t d_jobs_cap = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the fused sweep launch
 };
 
 static void drop_graphs(sg_batch *b) {
@@ -827,6 +829,8 @@ static int plan(sg_batch *b) {
 // enqueue one period: fused sweep launches, counters, due PT steps
 static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs, hipStream_t st) {
   size_t off = 0;
+  const bool timed = b->timing && st != b->cap_stream;
+  if (timed) HIPCHK(hipEventRecord(b->ev0, st));
   for (int m = 0; m < 2; m++)
     for (int a = 0; a < 2; a++) {
       const auto &v = b->items[m][a];
@@ -834,6 +838,7 @@ static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs,
         HIPCHK(sg::launch_sweep(m, a, b->d_items + off, (int)v.size(), b->tpb, b->lds, nsw, st));
       off += v.size();
     }
+  if (timed) HIPCHK(hipEventRecord(b->ev1, st));
   HIPCHK(sg::launch_advance(b->d_done, b->d_cap, (int)b->jobs.size(), nsw, st));
   for (int ji : pt_jobs) {
     int rc = run_pt(b->jobs[ji], st);
@@ -916,6 +921,15 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
       if (j->sp.pt_every > 0 && j->K > 1 && (j->sweeps_done + chunk) % j->sp.pt_every == 0)
         key.pt_jobs.push_back((int)i);
     }
+    if (b->timing) {
+      // timing mode: the same period enqueued directly on the caller's stream,
+      // with events around the fused sweep launch
+      rc = enqueue_period(b, key.nsw, key.pt_jobs, st);
+      if (rc) return rc;
+      for (sg_job *j : b->jobs) j->sweeps_done += chunk;
+      left -= chunk;
+      continue;
+    }
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
       hipGraph_t g;
@@ -938,9 +952,32 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
   GUARD_END
 }
 
+int sg_batch_set_timing(sg_batch *b, int32_t enable) {
+  GUARD_BEGIN
+  if (!b) return fail(SG_E_INVALID, "batch is NULL");
+  if (enable && !b->ev0) {
+    HIPCHK(hipEventCreate(&b->ev0));
+    HIPCHK(hipEventCreate(&b->ev1));
+  }
+  b->timing = enable != 0;
+  b->dirty = true;
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_batch_sweep_ms(sg_batch *b, float *ms) {
+  if (!b || !ms) return fail(SG_E_INVALID, "NULL argument");
+  if (!b->timing) return fail(SG_E_STATE, "timing is off");
+  HIPCHK(hipEventSynchronize(b->ev1));
+  HIPCHK(hipEventElapsedTime(ms, b->ev0, b->ev1));
+  return SG_OK;
+}
+
 int sg_batch_destroy(sg_batch *b) {
   if (!b) return SG_OK;
   drop_graphs(b);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_done) (void)hipFree(b->d_done);
   if (b->d_cap) (void)hipFree(b->d_cap);

@@ -63,10 +63,10 @@ def stream(key, n: int):
 
 
 def _bits(key, nbits: int):
-    words = stream(key, (nbits + 63) // 64)
-    shifts = np.arange(64, dtype=np.uint64)
-    bits = (words[..., :, None] >> shifts) & np.uint64(1)
-    return bits.reshape(bits.shape[:-2] + (-1,))[..., :nbits].astype(np.uint8)
+    """Bits of the streams in `key`, bit b of output u at position 64 u + b."""
+    words = stream(key, (nbits + 63) // 64).astype("<u8")
+    bits = np.unpackbits(words.view(np.uint8), axis=-1, bitorder="little")
+    return bits[..., :nbits]
 
 
 def couplings(seed: int, sample: int, L: int) -> np.ndarray:

@@ -1,0 +1,114 @@
+"""GPU parity of the batched form: jobs of mixed L advanced by one fused
+launch per period (hipGraph replay) must reproduce the oracle and their own
+stand-alone runs bit for bit, for every block size, and when jobs join or
+leave the batch between runs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0704_3573_amd import inputs
+from tests._gpu import assert_same_state, instance, make_job, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_0704_3573_amd import binding as B
+    return B.Context(0)
+
+
+def small_jobs(ctx, pe=3):
+    specs = [("ising", oracle.METROPOLIS, 8, 2, 2, 4), ("ising", oracle.METROPOLIS, 16, 1, 2, 3),
+             ("ising", oracle.HEATBATH, 24, 1, 1, 2), ("potts", oracle.HEATBATH, 16, 2, 2, 1),
+             ("ising", oracle.METROPOLIS, 48, 1, 2, 2)]
+    out = []
+    for n, (model, algo, L, S, R, K) in enumerate(specs):
+        betas = 1.0 / np.linspace(0.8, 1.5, K)
+        inst = instance(model, L, S, R, K, seed=700 + n)
+        job = make_job(ctx, model, algo, L, betas, inst, S=S, R=R, pt_every=pe if K > 1 else 0)
+        out.append((model, algo, L, S, R, K, betas, inst, job))
+    return out
+
+
+def test_mixed_batch_matches_oracle_and_alone(ctx):
+    from paper_0704_3573_amd import binding as B
+    pe = 3
+    jobs = small_jobs(ctx, pe)
+    alone = small_jobs(ctx, pe)
+    batch = B.Batch(ctx, [j[-1] for j in jobs])
+    batch.run(4)
+    batch.run(5)
+    for (model, algo, L, S, R, K, betas, inst, job), a in zip(jobs, alone):
+        a[-1].sweep(9)
+        ref = run_oracle(model, algo, L, betas, inst, S=S, R=R, n=9, pt_every=pe if K > 1 else 0)
+        assert_same_state(job, ref, f"batched {model} L={L}")
+        assert np.array_equal(job.spins(), a[-1].spins())
+        assert np.array_equal(job.wheels()[0], a[-1].wheels()[0])
+
+
+@pytest.mark.parametrize("block", [64 * k for k in (8, 9, 12, 16)])
+def test_batch_block_size_does_not_change_results(ctx, block):
+    from paper_0704_3573_amd import binding as B
+    jobs = small_jobs(ctx)
+    batch = B.Batch(ctx, [j[-1] for j in jobs], block=block)
+    assert batch.block() == block
+    batch.run(6)
+    for model, algo, L, S, R, K, betas, inst, job in jobs:
+        ref = run_oracle(model, algo, L, betas, inst, S=S, R=R, n=6, pt_every=3 if K > 1 else 0)
+        assert_same_state(job, ref, f"block={block} {model} L={L}")
+
+
+def test_continuous_batching_join_and_leave(ctx):
+    from paper_0704_3573_amd import binding as B
+    jobs = small_jobs(ctx)
+    batch = B.Batch(ctx, [jobs[0][-1], jobs[1][-1]])
+    batch.run(3)
+    batch.add(jobs[2][-1])
+    batch.add(jobs[3][-1])
+    batch.run(4)
+    batch.remove(jobs[0][-1])
+    batch.add(jobs[4][-1])
+    batch.run(2)
+    want = [7, 9, 6, 6, 2]
+    for (model, algo, L, S, R, K, betas, inst, job), n in zip(jobs, want):
+        assert job.sweeps_done() == n
+        ref = run_oracle(model, algo, L, betas, inst, S=S, R=R, n=n, pt_every=3 if K > 1 else 0)
+        assert_same_state(job, ref, f"continuous {model} L={L}")
+
+
+def test_full_size_batched_pt_workload_sampled_chains(ctx):
+    """The benchmark's batched workload at full size (256 samples at L = 16,
+    24, 32, 48, 2 replicas x 32 temperatures, PT every 10 sweeps) in the
+    launch configuration the benchmark times; one sample per L (all 64 of its
+    copies) is re-run by the oracle."""
+    from paper_0704_3573_amd import binding as B
+    betas = 1.0 / inputs.linear_temperatures(32, 0.7, 1.6)
+    jobs, insts = [], []
+    for i, L in enumerate((16, 24, 32, 48)):
+        inst = inputs.make_instance("ising", L, 64, 2, 32, seed=3000, sample0=64 * i)
+        jobs.append(B.Job(ctx, B.ISING, B.METROPOLIS, L, betas, inst["J"], inst["spins"],
+                          inst["wheels"], inst["ptwheels"], n_samples=64, n_replicas=2,
+                          pt_every=10))
+        # keep the inputs of sample 5 of this job only
+        s = 5
+        insts.append({"J": inst["J"][s:s + 1].copy(), "spins": inst["spins"][s * 64:(s + 1) * 64].copy(),
+                      "wheels": inst["wheels"][s * 64:(s + 1) * 64].copy(),
+                      "ptwheels": inst["ptwheels"][s * 2:(s + 1) * 2].copy()})
+        del inst
+    batch = B.Batch(ctx, jobs)
+    assert batch.block() % 64 == 0 and batch.block() >= 288
+    batch.run(20)
+    for L, job, inst in zip((16, 24, 32, 48), jobs, insts):
+        ref = oracle.run(oracle.ISING, oracle.METROPOLIS, L, betas, inst["J"], inst["spins"],
+                         inst["wheels"], inst["ptwheels"], n_samples=1, n_replicas=2, n_sweeps=20,
+                         pt_every=10, n_threads=8)
+        sp = job.spins()[5 * 64:6 * 64]
+        assert np.array_equal(sp, ref["spins"]), f"L={L}"
+        assert np.array_equal(job.energies()[5 * 64:6 * 64], ref["E"]), f"L={L}"
+        assert np.array_equal(job.perm()[10:12], ref["slot_of_temp"]), f"L={L}"
+        wh, pw = job.wheels()
+        assert np.array_equal(wh[5 * 64:6 * 64], ref["wheels"]), f"L={L}"
+        assert np.array_equal(pw[10:12], ref["ptwheels"]), f"L={L}"
