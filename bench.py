@@ -130,6 +130,10 @@ def main():
                     help="timed plain steps (100 sweeps + measurement each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched form (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no "
@@ -144,6 +148,15 @@ def main():
     from paper_0704_3573_amd import inputs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calibration} MiB x 5")
+        return
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
 
@@ -186,6 +199,9 @@ def main():
     E = [j.energies() for j in jobs]
     e_per_site = float(np.mean(np.concatenate([e / j.N for e, j in zip(E, jobs)])))
     del batch, jobs
+    if args.batched_only:
+        log(f"[bench] batched only: {value:.1f} updates/ns")
+        return
 
     # --------------------------------------------------------- plain form --
     L2 = 64

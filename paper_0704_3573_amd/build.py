@@ -10,6 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CLANGXX = os.environ.get("CLANGXX", "/opt/rocm/llvm/bin/clang++")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # keep the compiler from forming packed fp32 instructions
@@ -21,8 +22,11 @@ def build(verbose: bool = False) -> str:
     jobs = []
     for src, dev in (("sg_kernels.hip", True), ("sg_host.cpp", False)):
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
-        cmd = [HIPCC] + COMMON + (DEVICE + ["-x", "hip"] if dev else ["-D__HIP_PLATFORM_AMD__"]) + \
-              ["-c", os.path.join(CSRC, src), "-o", obj]
+        if dev:
+            cmd = [HIPCC] + COMMON + DEVICE + ["-x", "hip"]
+        else:  # host-only C++ against the HIP runtime API
+            cmd = [CLANGXX] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
+        cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
         jobs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
         objs.append(obj)
     for p in jobs:

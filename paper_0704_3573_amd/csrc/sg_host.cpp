@@ -2,7 +2,7 @@
 // host only), canonical <-> device layout conversion, launch planning,
 // batches replayed from captured hipGraphs.  The C-ABI is declared in
 // include/sg.h.
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <cmath>
@@ -31,9 +31,11 @@ hipError_t launch_debug_rng(const uint32_t *wheels, uint32_t *out, uint64_t wstr
 hipError_t launch_advance(uint64_t *const *done, const int32_t *cap, int n, int nsweeps,
                           hipStream_t st);
 hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st);
+hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st);
 }  // namespace sg
 
 using sg::Geom;
+using sg::PtWork;
 using sg::Work;
 
 // ---------------------------------------------------------------- errors --
@@ -112,7 +114,7 @@ struct sg_ctx {
 
 // ------------------------------------------------------------------- job --
 struct Layout {
-  uint64_t spins, J, wheels, ptw, tos, sot, thr, F, sgn, E, Q, acc, done, dbg, works, total;
+  uint64_t spins, J, wheels, ptw, tos, sot, thr, F, sgn, E, Q, acc, done, dbg, works, ptworks, total;
   uint64_t spins_bytes, J_bytes, wheels_bytes;
 };
 
@@ -161,6 +163,7 @@ static Layout layout(const sg_job_spec *sp) {
   l.done = o; o = al(o + 8);
   l.dbg = o; o = al(o + 4096 * 4);
   l.works = o; o = al(o + C * sizeof(Work));
+  l.ptworks = o; o = al(o + ((S * R + 63) / 64) * sizeof(PtWork));
   l.total = o;
   return l;
 }
@@ -220,6 +223,25 @@ static void make_items(const sg_job *j, int G, std::vector<Work> &out) {
     w.J_bytes = (uint32_t)j->lay.J_bytes;
     w.wheels_bytes = (uint32_t)j->lay.wheels_bytes;
     w.done = j->done_ptr();
+    out.push_back(w);
+  }
+}
+
+static const int PT_FUSED_KMAX = 64;
+
+static void make_pt_works(const sg_job *j, std::vector<PtWork> &out) {
+  for (int c0 = 0; c0 < j->chains; c0 += 64) {
+    PtWork w{};
+    w.E = j->at<int64_t>(j->lay.E);
+    w.slot_of_temp = j->at<int32_t>(j->lay.sot);
+    w.temp_of_slot = j->at<int32_t>(j->lay.tos);
+    w.ptw = j->at<uint32_t>(j->lay.ptw);
+    w.F = j->at<uint64_t>(j->lay.F);
+    w.sgn = j->at<int32_t>(j->lay.sgn);
+    w.accepts = j->at<uint64_t>(j->lay.acc);
+    w.chain0 = c0;
+    w.nchains = std::min(64, j->chains - c0);
+    w.K = j->K;
     out.push_back(w);
   }
 }
@@ -541,6 +563,11 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   j->tpb = ((G * j->g.NW + 63) / 64) * 64;
   j->lds = item_lds(j, G);
   HIPCHK(hipMemcpy(j->at<void>(lay.works), j->works.data(), j->works.size() * sizeof(Work), hipMemcpyHostToDevice));
+  {
+    std::vector<PtWork> pw;
+    make_pt_works(j, pw);
+    HIPCHK(hipMemcpy(j->at<void>(lay.ptworks), pw.data(), pw.size() * sizeof(PtWork), hipMemcpyHostToDevice));
+  }
   HIPCHK(hipDeviceSynchronize());
   *out = j;
   return SG_OK;
@@ -558,6 +585,10 @@ int sg_job_set_betas(sg_job *job, const double *betas, void *stream) {
 }
 
 static int run_pt(sg_job *j, hipStream_t st) {
+  if (j->K <= PT_FUSED_KMAX) {
+    HIPCHK(sg::launch_pt_fused(j->at<PtWork>(j->lay.ptworks), (j->chains + 63) / 64, j->K, st));
+    return SG_OK;
+  }
   HIPCHK(sg::launch_pt(j->at<int64_t>(j->lay.E), j->at<int32_t>(j->lay.sot), j->at<int32_t>(j->lay.tos),
                        j->at<uint32_t>(j->lay.ptw), j->at<uint64_t>(j->lay.F), j->at<int32_t>(j->lay.sgn),
                        j->at<uint64_t>(j->lay.acc), j->chains, j->K, st));
@@ -725,6 +756,11 @@ struct GraphKey {
   }
 };
 
+struct PtTable {
+  PtWork *d;
+  int n, kmax;
+};
+
 struct sg_batch {
   sg_ctx *ctx;
   std::vector<sg_job *> jobs;
@@ -740,6 +776,8 @@ struct sg_batch {
   int32_t *d_cap = nullptr;
   size_t d_jobs_cap = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
+  std::vector<void *> graph_bufs;  // device buffers referenced by captured graphs
+  std::map<std::vector<int>, PtTable> pt_cache;
   hipStream_t cap_stream = nullptr;
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the fused sweep launch
@@ -748,6 +786,9 @@ struct sg_batch {
 static void drop_graphs(sg_batch *b) {
   for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
   b->graphs.clear();
+  for (void *p : b->graph_bufs) (void)hipFree(p);
+  b->graph_bufs.clear();
+  b->pt_cache.clear();
 }
 
 // idle-lane fraction of a block size for the batch's jobs (lower is better)
@@ -789,6 +830,12 @@ static int plan(sg_batch *b) {
     lds = std::max(lds, item_lds(j, G));
     make_items(j, G, b->items[j->sp.model][j->sp.algo]);
   }
+  // longest items first: the launch tail is then made of short items
+  for (auto &a : b->items)
+    for (auto &v : a)
+      std::stable_sort(v.begin(), v.end(), [](const Work &x, const Work &y) {
+        return (uint64_t)x.ncopies * x.L * x.L * x.L > (uint64_t)y.ncopies * y.L * y.L * y.L;
+      });
   for (auto &a : b->items)
     for (auto &v : a) total += v.size();
   if (total > b->d_items_cap) {
@@ -840,10 +887,37 @@ static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs,
     }
   if (timed) HIPCHK(hipEventRecord(b->ev1, st));
   HIPCHK(sg::launch_advance(b->d_done, b->d_cap, (int)b->jobs.size(), nsw, st));
+  // parallel tempering of every due job in one fused launch (buffers prepared
+  // before any capture starts)
+  for (int ji : pt_jobs)
+    if (b->jobs[ji]->K > PT_FUSED_KMAX) {
+      int rc = run_pt(b->jobs[ji], st);
+      if (rc) return rc;
+    }
+  auto it = b->pt_cache.find(pt_jobs);
+  if (it != b->pt_cache.end() && it->second.n > 0)
+    HIPCHK(sg::launch_pt_fused(it->second.d, it->second.n, it->second.kmax, st));
+  return SG_OK;
+}
+
+// device table of the fused PT launch for a set of due jobs
+static int prepare_pt(sg_batch *b, const std::vector<int> &pt_jobs) {
+  if (b->pt_cache.count(pt_jobs)) return SG_OK;
+  std::vector<PtWork> pw;
+  int kmax = 2;
   for (int ji : pt_jobs) {
-    int rc = run_pt(b->jobs[ji], st);
-    if (rc) return rc;
+    sg_job *j = b->jobs[ji];
+    if (j->K > PT_FUSED_KMAX) continue;
+    kmax = std::max(kmax, j->K);
+    make_pt_works(j, pw);
   }
+  PtTable t{nullptr, (int)pw.size(), kmax};
+  if (!pw.empty()) {
+    HIPCHK(hipMalloc(&t.d, pw.size() * sizeof(PtWork)));
+    b->graph_bufs.push_back(t.d);
+    HIPCHK(hipMemcpy(t.d, pw.data(), pw.size() * sizeof(PtWork), hipMemcpyHostToDevice));
+  }
+  b->pt_cache.emplace(pt_jobs, t);
   return SG_OK;
 }
 
@@ -921,6 +995,8 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
       if (j->sp.pt_every > 0 && j->K > 1 && (j->sweeps_done + chunk) % j->sp.pt_every == 0)
         key.pt_jobs.push_back((int)i);
     }
+    rc = prepare_pt(b, key.pt_jobs);
+    if (rc) return rc;
     if (b->timing) {
       // timing mode: the same period enqueued directly on the caller's stream,
       // with events around the fused sweep launch

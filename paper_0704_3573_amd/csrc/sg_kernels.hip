@@ -679,6 +679,65 @@ __global__ __launch_bounds__(64) void pt_kernel(const int64_t *__restrict__ E,
   for (int i = 0; i < K; i++) temp_of_slot[(size_t)ch * K + so[i]] = i;
 }
 
+// Fused variant: one workgroup per 64 chains of one job, every job of a
+// batch in one launch.  Wheels, energies, permutations and the factor table
+// are staged in LDS, so the 31 sequential swap decisions of a chain run on
+// LDS latency instead of global memory latency.  Same decisions as pt_kernel.
+__global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__ works, int kmax) {
+  extern __shared__ uint32_t lds[];
+  const PtWork w = works[blockIdx.x];
+  const int t = threadIdx.x;
+  const int K = w.K;
+  uint32_t *ring = lds + t * 62;                                 // 61 words + position
+  int32_t *Es = (int32_t *)(lds + 64 * 62) + t * kmax;           // energy by slot
+  int32_t *so = (int32_t *)(lds + 64 * 62 + 64 * kmax) + t * kmax;  // slot by temperature
+  uint64_t *Fl = (uint64_t *)(lds + 64 * 62 + 128 * kmax);       // [K-1][24]
+  for (int i = t; i < (K - 1) * 24; i += 64) Fl[i] = w.F[i];
+  __syncthreads();
+  if (t >= w.nchains) return;
+  const int ch = w.chain0 + t;
+  const uint32_t *gw = w.ptw + (size_t)ch * 64;
+  for (int j = 0; j < 62; j++) ring[j] = gw[j];
+  for (int k = 0; k < K; k++) {
+    Es[k] = (int32_t)w.E[(size_t)ch * K + k];  // |E| <= 3 L^3 fits 32 bits
+    so[k] = w.slot_of_temp[(size_t)ch * K + k];
+  }
+  for (int i = 0; i + 1 < K; i++) {
+    const int a = so[i], b = so[i + 1];
+    const int32_t D = Es[b] - Es[a];
+    const uint32_t r = ptw_next(ring);
+    const int sd = D > 0 ? 1 : (D < 0 ? -1 : 0);
+    bool accept;
+    if (w.sgn[i] * sd <= 0) {
+      accept = true;
+    } else {
+      const uint32_t aD = (uint32_t)(D < 0 ? -D : D);
+      uint64_t T = 0;
+      if (aD < (1u << 24)) {
+        T = 1ull << 32;
+        const uint64_t *Fi = Fl + i * 24;
+        for (uint32_t m = aD; m; m &= m - 1) {
+          const int bb = __ffs(m) - 1;
+          const uint64_t f = Fi[bb];
+          T = __umul64hi(T, f) << 32 | ((T * f) >> 32);
+        }
+      }
+      accept = (uint64_t)r < T;
+    }
+    if (accept) {
+      so[i] = b;
+      so[i + 1] = a;
+      if (w.accepts) w.accepts[(size_t)ch * (K - 1) + i]++;
+    }
+  }
+  uint32_t *gwo = w.ptw + (size_t)ch * 64;
+  for (int j = 0; j < 62; j++) gwo[j] = ring[j];
+  for (int k = 0; k < K; k++) {
+    w.slot_of_temp[(size_t)ch * K + k] = so[k];
+    w.temp_of_slot[(size_t)ch * K + so[k]] = k;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Next n outputs of one sweep wheel, state untouched (test hook).
 // ---------------------------------------------------------------------------
@@ -779,6 +838,13 @@ hipError_t launch_pt(const int64_t *E, int32_t *slot_of_temp, int32_t *temp_of_s
   if (chains <= 0 || K < 2) return hipSuccess;
   hipLaunchKernelGGL(pt_kernel, dim3((chains + 63) / 64), dim3(64), 0, st, E, slot_of_temp,
                      temp_of_slot, ptw, F, sgn, accepts, chains, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st) {
+  if (nworks <= 0) return hipSuccess;
+  const size_t lds = (size_t)(64 * 62 + 128 * kmax) * 4 + (size_t)(kmax > 1 ? kmax - 1 : 1) * 24 * 8;
+  hipLaunchKernelGGL(pt_fused_kernel, dim3(nworks), dim3(64), lds, st, works, kmax);
   return hipGetLastError();
 }
 

@@ -85,4 +85,16 @@ struct Work {
   const uint64_t *done;          // sweeps already performed by the job (device)
 };
 
+// Parallel-tempering work of one workgroup: up to 64 chains of one job.
+struct PtWork {
+  const int64_t *E;          // [C] energy per slot
+  int32_t *slot_of_temp;     // [chains][K]
+  int32_t *temp_of_slot;     // [C]
+  uint32_t *ptw;             // [chains][64]: 61 ring words + position
+  const uint64_t *F;         // [K-1][24]
+  const int32_t *sgn;        // [K-1]
+  uint64_t *accepts;         // [chains][K-1]
+  int32_t chain0, nchains, K, pad;
+};
+
 }  // namespace sg
