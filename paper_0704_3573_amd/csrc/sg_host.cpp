@@ -191,8 +191,9 @@ struct sg_job {
 
 // lanes and LDS bytes of a work item of G copies
 static size_t item_lds(const sg_job *j, int G) {
-  if (j->sp.model == SG_ISING) return (size_t)G * j->g.CS * 4 + (size_t)G * 4;
-  return (size_t)G * j->N + (size_t)G * 16 * 4 + (size_t)G * 4;
+  // copies, per-copy tables and counters, and one dummy word
+  if (j->sp.model == SG_ISING) return (size_t)G * j->g.CS * 4 + (size_t)G * 4 + 4;
+  return (size_t)G * j->N + (size_t)G * 16 * 4 + (size_t)G * 4 + 4;
 }
 
 static int copies_per_item(const sg_job *j, int tpb) {

@@ -98,6 +98,7 @@ DEV uint32_t gt3(uint32_t a2, uint32_t a1, uint32_t a0, uint32_t b2, uint32_t b1
 // Per-lane context of the Ising sweep.
 struct IsingLane {
   uint32_t *sp;        // LDS base of the lane's copy
+  uint32_t *dummy;     // LDS word that lanes without a wheel write to
   rsrc_t rJ;           // couplings of the job
   uint32_t joff;       // byte offset of (sample, z) in the couplings
   int z, zp, zm, g;
@@ -115,6 +116,7 @@ DEV void ising_neighbours(const IsingLane &ln, int p, int blk, uint32_t &S, uint
   const int y0 = ln.g * G::RHO + blk * G::RPB;
   own = ln.sp + (p * L + ln.z) * G::WZ + wb;
   S = *own;
+  own = ln.dummy ? ln.dummy : own;
   const uint32_t *oc = ln.sp + (q * L + ln.z) * G::WZ;
   const uint32_t Wc = oc[wb];
   N[4] = ln.sp[(q * L + ln.zp) * G::WZ + wb];  // z+
@@ -166,7 +168,7 @@ DEV void met_step(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint
                   uint32_t T1, uint32_t T2, uint32_t &b1, uint32_t &b0) {
   uint32_t r, ts;
   uint64_t m1, m0, j1, j0;
-  asm("v_add_u32 %[n], %[a], %[b]\n\t"
+  asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
       "v_xor_b32 %[r], %[n], %[c]\n\t"
       "v_cmp_lt_u32 %[m1], %[r], %[T1]\n\t"
       "v_cndmask_b32 %[ts], %[T2], %[T0], %[m1]\n\t"
@@ -184,7 +186,7 @@ DEV void hb_step(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, const
                  uint32_t &b2, uint32_t &b1, uint32_t &b0) {
   uint32_t r, ta, x, y, tb;
   uint64_t m2, m1, m0, j2, j1, j0;
-  asm("v_add_u32 %[n], %[a], %[b]\n\t"
+  asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
       "v_xor_b32 %[r], %[n], %[c]\n\t"
       "v_cmp_lt_u32 %[m2], %[r], %[T3]\n\t"
       "v_cndmask_b32 %[ta], %[T5], %[T1], %[m2]\n\t"
@@ -204,6 +206,8 @@ DEV void hb_step(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, const
 }
 
 // One block: B draws of the lane's wheel at ring phase VI, one per site.
+// The block's LDS and coupling loads are issued first; the B ALU-only draw
+// steps then cover their latency before the bit-sliced logic consumes them.
 template <int L, int ALGO, int VI>
 DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int blk,
                      bool any_always) {
@@ -211,16 +215,9 @@ DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int
   constexpr int M = G::M, B = G::B;
   uint32_t S, N[6], Jw[6];
   uint32_t *own;
-  ising_neighbours<L>(ln, p, blk, S, N, own);
   ising_couplings<L>(ln, p, blk, Jw);
-  // bit-sliced neighbour count, done before the draws to keep few words live
-  uint32_t n0, n1, n2;
-  {
-    uint32_t u[6];
-#pragma unroll
-    for (int d = 0; d < 6; d++) u[d] = ALGO == 0 ? (S ^ N[d] ^ Jw[d]) : (N[d] ^ Jw[d]);
-    count6(u, n0, n1, n2);
-  }
+  ising_neighbours<L>(ln, p, blk, S, N, own);
+  __builtin_amdgcn_sched_barrier(0);
 
   uint32_t b0 = 0, b1 = 0, b2 = 0;
 #pragma unroll
@@ -233,7 +230,16 @@ DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int
       hb_step(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
               ring[(k + M - 61) % M], ln.T, b2, b1, b0);
   }
+  __builtin_amdgcn_sched_barrier(0);
 
+  // bit-sliced neighbour count
+  uint32_t n0, n1, n2;
+  {
+    uint32_t u[6];
+#pragma unroll
+    for (int d = 0; d < 6; d++) u[d] = ALGO == 0 ? (S ^ N[d] ^ Jw[d]) : (N[d] ^ Jw[d]);
+    count6(u, n0, n1, n2);
+  }
   if constexpr (ALGO == 0) {
     // Metropolis: n unsatisfied bonds; flip iff n >= 3 or r < T[n], i.e. n + b >= 3.
     uint32_t acc = n2 | (n1 & (n0 | b0 | b1)) | (b1 & (n0 | b0));
@@ -312,7 +318,10 @@ struct Drive {
 
 template <class K, int VI>
 DEV bool drive_chain(K &k, uint32_t (&ring)[K::M], Drive &d) {
-  if (d.active) k.template block<VI>(ring, d.p, d.blk);
+  // every lane of a wave that holds at least one wheel runs the block (lanes
+  // without a wheel compute on copy 0 and store to a dummy word), so the ring
+  // registers never flow around a divergent branch
+  k.template block<VI>(ring, d.p, d.blk);
   if (++d.blk == K::NBLK) {
     d.blk = 0;
     __syncthreads();
@@ -328,15 +337,37 @@ DEV bool drive_chain(K &k, uint32_t (&ring)[K::M], Drive &d) {
     return false;
 }
 
+// When V divides NBLK every half-sweep starts at ring phase 0: the half-sweep
+// is NBLK / V repetitions of the V phases and the launch has a single exit.
+template <class K, int VI>
+DEV void drive_cycle(K &k, uint32_t (&ring)[K::M], int p, int blk0) {
+  k.template block<VI>(ring, p, blk0 + VI);
+  if constexpr (VI + 1 < K::V) drive_cycle<K, VI + 1>(k, ring, p, blk0);
+}
+
 template <class K>
 DEV void drive(K &k, Drive &d) {
   if (d.nsweeps <= 0) return;
+  if (!__any(d.active)) {
+    // a wave without wheels only keeps the workgroup barriers in step
+    for (int i = 0; i < 2 * d.nsweeps; i++) __syncthreads();
+    return;
+  }
   uint32_t ring[K::M];
   if (d.active) ring_load<K::M>(ring, d.rwh, d.widx, d.wstride, d.kmod);
-  d.p = 0;
-  d.blk = 0;
-  d.s = 0;
-  while (!drive_chain<K, 0>(k, ring, d)) {
+  if constexpr (K::NBLK % K::V == 0) {
+    for (int s = 0; s < d.nsweeps; s++)
+      for (int p = 0; p < 2; p++) {
+        for (int b0 = 0; b0 < K::NBLK; b0 += K::V) drive_cycle<K, 0>(k, ring, p, b0);
+        __syncthreads();
+      }
+    if (d.active) ring_store<K::M, K::M - 1>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+  } else {
+    d.p = 0;
+    d.blk = 0;
+    d.s = 0;
+    while (!drive_chain<K, 0>(k, ring, d)) {
+    }
   }
 }
 
@@ -360,6 +391,7 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   const int lanes = w.ncopies * G::NW;
   const bool active = t < lanes;
   int *Ucnt = (int *)(lds + w.ncopies * G::CS);
+  uint32_t *dummy = lds + w.ncopies * G::CS + w.ncopies;
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
 
   // stage the copies in LDS
@@ -373,6 +405,7 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   const int wl = t - cl * G::NW;
   const int copy = w.copy0 + cl;
   ln.sp = lds + cl * G::CS;
+  ln.dummy = active ? nullptr : dummy;
   ln.g = wl / L;
   ln.z = wl - ln.g * L;
   ln.zp = ln.z + 1 == L ? 0 : ln.z + 1;
@@ -426,6 +459,7 @@ struct PottsK {
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK, H = G::H, RPB = G::RPB,
                        RHO = G::RHO;
   uint8_t *sp;         // LDS bytes of the lane's copy, [y][x][z], value 8 sigma
+  uint8_t *dummy;      // LDS byte that lanes without a wheel write to
   const uint32_t *Wl;  // LDS weight table of the lane's temperature
   rsrc_t rJ;           // coupling patterns of the job
   uint32_t joff;       // byte offset of the lane's sample
@@ -474,7 +508,7 @@ struct PottsK {
         const uint32_t t = __umulhi(r, S);
         const uint32_t C0 = w0, C1 = w0 + w1, C2 = C1 + w2;
         const uint32_t sig = (uint32_t)(t >= C0) + (uint32_t)(t >= C1) + (uint32_t)(t >= C2);
-        sp[base + o] = (uint8_t)(sig << 3);
+        *(dummy ? dummy : sp + base + o) = (uint8_t)(sig << 3);
       }
     }
   }
@@ -521,6 +555,7 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   const bool active = t < lanes;
   uint32_t *Wt = lds + w.ncopies * CW;          // [ncopies][16] weight tables
   int *Hcnt = (int *)(Wt + w.ncopies * 16);     // [ncopies]
+  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
   const uint32_t sbase = (uint32_t)w.copy0 * N3;
   for (int i = t; i < w.ncopies * CW; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
@@ -536,6 +571,7 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   const int copy = w.copy0 + cl;
   k.sp = (uint8_t *)(lds + cl * CW);
   k.Wl = Wt + cl * 16;
+  k.dummy = active ? nullptr : dummy;
   k.g = wl / L;
   k.z = wl - k.g * L;
   k.zp = k.z + 1 == L ? 0 : k.z + 1;

@@ -49,8 +49,11 @@ SG_HD constexpr Geom geom(int L) {
   g.NWB = g.L / g.RPB;               // block words per (colour, plane)
   g.WZ = g.NWB | 1;                  // padded stride
   g.CS = 2 * g.L * g.WZ;             // words per Ising copy
-  g.M = ((62 + g.B - 1) / g.B) * g.B;  // ring slots, a multiple of B
-  g.V = g.M / g.B;                   // distinct block phases of the ring
+  // ring slots: a multiple of B, at least 62, with an even number V of block
+  // phases (an even cycle lets the register allocator keep every slot in place)
+  g.V = (62 + g.B - 1) / g.B;
+  g.V += g.V & 1;
+  g.M = g.V * g.B;
   return g;
 }
 
