@@ -153,6 +153,12 @@ int sg_batch_remove(sg_batch *b, sg_job *job);
 /* Threads per workgroup of the fused launch (multiple of 64, <= 1024;
  * 0 = automatic).  Results do not depend on it. */
 int sg_batch_set_block(sg_batch *b, int32_t threads);
+/* Remaining sweep budget of a job in the batch: a run of n sweeps advances
+ * the job by min(n, budget) and lowers the budget by that much
+ * (UINT64_MAX = unlimited, the default).  For jobs without parallel tempering.
+ * This lets jobs of different lengths share one launch and stop exactly. */
+int sg_batch_set_budget(sg_batch *b, sg_job *job, uint64_t sweeps);
+int sg_batch_get_budget(sg_batch *b, sg_job *job, uint64_t *sweeps);
 /* Advance every job of the batch by n sweeps (parallel tempering included). */
 int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream);
 /* Threads per workgroup chosen for the current membership. */

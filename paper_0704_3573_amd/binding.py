@@ -27,7 +27,8 @@ EXPORTS = (
     "sg_job_get_spins", "sg_job_get_wheels", "sg_job_get_perm", "sg_job_get_pt_accepts",
     "sg_job_sweeps_done", "sg_job_debug_rng", "sg_job_destroy", "sg_batch_create",
     "sg_batch_add", "sg_batch_remove", "sg_batch_set_block", "sg_batch_run", "sg_batch_block",
-    "sg_batch_set_timing", "sg_batch_sweep_ms", "sg_batch_destroy",
+    "sg_batch_set_timing", "sg_batch_sweep_ms", "sg_batch_set_budget", "sg_batch_get_budget",
+    "sg_batch_destroy",
 )
 
 
@@ -80,6 +81,8 @@ def lib():
         L.sg_batch_block.argtypes = [vp, C.POINTER(i32)]
         L.sg_batch_set_timing.argtypes = [vp, i32]
         L.sg_batch_sweep_ms.argtypes = [vp, C.POINTER(C.c_float)]
+        L.sg_batch_set_budget.argtypes = [vp, vp, u64]
+        L.sg_batch_get_budget.argtypes = [vp, vp, C.POINTER(u64)]
         L.sg_batch_destroy.argtypes = [vp]
         for n in EXPORTS:
             if n not in ("sg_last_error", "sg_wheels_per_copy"):
@@ -264,6 +267,14 @@ class Batch:
 
     def run(self, n: int, stream=None):
         _chk(lib().sg_batch_run(self.h, n, _stream(stream)))
+
+    def set_budget(self, job: Job, sweeps: int):
+        _chk(lib().sg_batch_set_budget(self.h, job.h, sweeps))
+
+    def budget(self, job: Job) -> int:
+        n = C.c_uint64()
+        _chk(lib().sg_batch_get_budget(self.h, job.h, C.byref(n)))
+        return n.value
 
     def set_timing(self, on: bool):
         _chk(lib().sg_batch_set_timing(self.h, int(on)))

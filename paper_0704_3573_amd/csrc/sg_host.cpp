@@ -765,6 +765,8 @@ struct PtTable {
 struct sg_batch {
   sg_ctx *ctx;
   std::vector<sg_job *> jobs;
+  std::vector<uint64_t> budget;  // remaining sweeps per job (UINT64_MAX = unlimited)
+  std::vector<int32_t> run_cap;  // sweeps each job runs in the current period
   int block_req = 0;  // 0 = automatic
   // plan
   bool dirty = true;
@@ -780,6 +782,8 @@ struct sg_batch {
   std::vector<void *> graph_bufs;  // device buffers referenced by captured graphs
   std::map<std::vector<int>, PtTable> pt_cache;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};  // parallel branches while capturing
+  hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the fused sweep launch
 };
@@ -868,22 +872,80 @@ static int plan(sg_batch *b) {
     HIPCHK(hipMemcpy(b->d_done, done.data(), done.size() * sizeof(uint64_t *), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(b->d_cap, cap.data(), cap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
+  b->run_cap.assign(b->jobs.size(), 0x7FFFFFFF);
   b->tpb = tpb;
   b->lds = lds;
   b->dirty = false;
   return SG_OK;
 }
 
+static void account(sg_batch *b, uint64_t chunk) {
+  for (size_t i = 0; i < b->jobs.size(); i++) {
+    const uint64_t ran = std::min<uint64_t>(chunk, b->budget[i]);
+    b->jobs[i]->sweeps_done += ran;
+    if (b->budget[i] != UINT64_MAX) b->budget[i] -= ran;
+  }
+}
+
+// per-job sweep caps of one period; uploads item and counter caps if changed
+static int apply_caps(sg_batch *b, uint64_t chunk, hipStream_t st) {
+  std::vector<int32_t> cap(b->jobs.size());
+  bool changed = false;
+  for (size_t i = 0; i < b->jobs.size(); i++) {
+    const uint64_t c = std::min<uint64_t>(chunk, b->budget[i]);
+    cap[i] = b->budget[i] == UINT64_MAX ? 0x7FFFFFFF : (int32_t)c;
+    if (cap[i] != b->run_cap[i]) changed = true;
+  }
+  if (!changed) return SG_OK;
+  HIPCHK(hipStreamSynchronize(st));  // earlier periods may still read the tables
+  b->run_cap = cap;
+  std::map<const sg_job *, int32_t> by_job;
+  for (size_t i = 0; i < b->jobs.size(); i++) by_job[b->jobs[i]] = cap[i];
+  size_t off = 0;
+  for (auto &a : b->items)
+    for (auto &v : a) {
+      for (Work &w : v) {
+        // items carry the job's arena pointers; find the job by its counter
+        for (size_t i = 0; i < b->jobs.size(); i++)
+          if (w.done == b->jobs[i]->done_ptr()) w.nsweeps_cap = cap[i];
+      }
+      if (!v.empty()) HIPCHK(hipMemcpy(b->d_items + off, v.data(), v.size() * sizeof(Work), hipMemcpyHostToDevice));
+      off += v.size();
+    }
+  HIPCHK(hipMemcpy(b->d_cap, cap.data(), cap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  return SG_OK;
+}
+
 // enqueue one period: fused sweep launches, counters, due PT steps
 static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs, hipStream_t st) {
   size_t off = 0;
-  const bool timed = b->timing && st != b->cap_stream;
+  const bool capturing = st == b->cap_stream;
+  const bool timed = b->timing && !capturing;
   if (timed) HIPCHK(hipEventRecord(b->ev0, st));
+  // one fused launch per (model, algorithm) group; while capturing, groups
+  // become parallel branches of the graph
+  int groups = 0;
+  for (auto &a : b->items)
+    for (auto &v : a) groups += !v.empty();
+  const bool fork = capturing && groups > 1;
+  if (fork) HIPCHK(hipEventRecord(b->fork, st));
+  int g = 0;
   for (int m = 0; m < 2; m++)
     for (int a = 0; a < 2; a++) {
       const auto &v = b->items[m][a];
-      if (!v.empty())
-        HIPCHK(sg::launch_sweep(m, a, b->d_items + off, (int)v.size(), b->tpb, b->lds, nsw, st));
+      if (!v.empty()) {
+        hipStream_t s = st;
+        if (fork && g > 0) {
+          s = b->side[g - 1];
+          HIPCHK(hipStreamWaitEvent(s, b->fork, 0));
+        }
+        HIPCHK(sg::launch_sweep(m, a, b->d_items + off, (int)v.size(), b->tpb, b->lds, nsw, s));
+        if (fork && g > 0) {
+          HIPCHK(hipEventRecord(b->join[g - 1], s));
+          HIPCHK(hipStreamWaitEvent(st, b->join[g - 1], 0));
+        }
+        g++;
+      }
       off += v.size();
     }
   if (timed) HIPCHK(hipEventRecord(b->ev1, st));
@@ -931,6 +993,11 @@ int sg_batch_create(sg_ctx *ctx, sg_batch **out) {
   b->ctx = ctx;
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  for (int i = 0; i < 3; i++) {
+    HIPCHK(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming));
+  }
+  HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
   *out = b;
   return SG_OK;
   GUARD_END
@@ -943,6 +1010,7 @@ int sg_batch_add(sg_batch *b, sg_job *job) {
   if (std::find(b->jobs.begin(), b->jobs.end(), job) != b->jobs.end())
     return fail(SG_E_STATE, "job is already in the batch");
   b->jobs.push_back(job);
+  b->budget.push_back(UINT64_MAX);
   b->dirty = true;
   return SG_OK;
   GUARD_END
@@ -953,10 +1021,29 @@ int sg_batch_remove(sg_batch *b, sg_job *job) {
   if (!b || !job) return fail(SG_E_INVALID, "NULL argument");
   auto it = std::find(b->jobs.begin(), b->jobs.end(), job);
   if (it == b->jobs.end()) return fail(SG_E_STATE, "job is not in the batch");
+  b->budget.erase(b->budget.begin() + (it - b->jobs.begin()));
   b->jobs.erase(it);
   b->dirty = true;
   return SG_OK;
   GUARD_END
+}
+
+int sg_batch_set_budget(sg_batch *b, sg_job *job, uint64_t sweeps) {
+  if (!b || !job) return fail(SG_E_INVALID, "NULL argument");
+  auto it = std::find(b->jobs.begin(), b->jobs.end(), job);
+  if (it == b->jobs.end()) return fail(SG_E_STATE, "job is not in the batch");
+  if (sweeps != UINT64_MAX && job->sp.pt_every > 0 && job->K > 1)
+    return fail(SG_E_INVALID, "sweep budgets are for jobs without parallel tempering");
+  b->budget[it - b->jobs.begin()] = sweeps;
+  return SG_OK;
+}
+
+int sg_batch_get_budget(sg_batch *b, sg_job *job, uint64_t *sweeps) {
+  if (!b || !job || !sweeps) return fail(SG_E_INVALID, "NULL argument");
+  auto it = std::find(b->jobs.begin(), b->jobs.end(), job);
+  if (it == b->jobs.end()) return fail(SG_E_STATE, "job is not in the batch");
+  *sweeps = b->budget[it - b->jobs.begin()];
+  return SG_OK;
 }
 
 int sg_batch_set_block(sg_batch *b, int32_t threads) {
@@ -998,12 +1085,14 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
     }
     rc = prepare_pt(b, key.pt_jobs);
     if (rc) return rc;
+    rc = apply_caps(b, chunk, st);
+    if (rc) return rc;
     if (b->timing) {
       // timing mode: the same period enqueued directly on the caller's stream,
       // with events around the fused sweep launch
       rc = enqueue_period(b, key.nsw, key.pt_jobs, st);
       if (rc) return rc;
-      for (sg_job *j : b->jobs) j->sweeps_done += chunk;
+      account(b, chunk);
       left -= chunk;
       continue;
     }
@@ -1022,7 +1111,7 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
       it = b->graphs.emplace(key, ge).first;
     }
     HIPCHK(hipGraphLaunch(it->second, st));
-    for (sg_job *j : b->jobs) j->sweeps_done += chunk;
+    account(b, chunk);
     left -= chunk;
   }
   return SG_OK;
@@ -1059,6 +1148,11 @@ int sg_batch_destroy(sg_batch *b) {
   if (b->d_done) (void)hipFree(b->d_done);
   if (b->d_cap) (void)hipFree(b->d_cap);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (int i = 0; i < 3; i++) {
+    if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
   return SG_OK;
 }

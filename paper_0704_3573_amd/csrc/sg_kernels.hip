@@ -243,7 +243,10 @@ DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int
   if constexpr (ALGO == 0) {
     // Metropolis: n unsatisfied bonds; flip iff n >= 3 or r < T[n], i.e. n + b >= 3.
     uint32_t acc = n2 | (n1 & (n0 | b0 | b1)) | (b1 & (n0 | b0));
-    if (any_always) {
+    if (__builtin_expect(any_always, 0)) {
+      // a threshold equal to 2^32 (beta ~ 0): kept out of line (the empty asm
+      // stops the compiler from turning this rare path into selects)
+      asm volatile("" ::: "memory");
       const uint32_t A0 = (ln.A & 1) ? ~0u : 0u, A1 = (ln.A & 2) ? ~0u : 0u,
                      A2 = (ln.A & 4) ? ~0u : 0u;
       acc |= A0 | (A1 & (n0 | n1 | n2)) | (A2 & (n1 | n2));
@@ -252,11 +255,12 @@ DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int
   } else {
     // Heat bath: m = #{d : J_d s_d = -1}, k = 6 - m; s = +1 iff r < T[k], i.e. b > m.
     uint32_t plus = gt3(b2, b1, b0, n2, n1, n0);
-    if (any_always && ln.A) {
+    if (__builtin_expect(any_always, 0)) {
       // T[k] = 2^32 for every k >= kmin: force +1 where m <= 6 - kmin
-      const int a = 6 - (__ffs(ln.A) - 1);
+      asm volatile("" ::: "memory");
+      const int a = ln.A ? 6 - (__ffs(ln.A) - 1) : -1;
       const uint32_t a2 = (a & 4) ? ~0u : 0u, a1 = (a & 2) ? ~0u : 0u, a0 = (a & 1) ? ~0u : 0u;
-      plus |= ~gt3(n2, n1, n0, a2, a1, a0);
+      if (a >= 0) plus |= ~gt3(n2, n1, n0, a2, a1, a0);
     }
     *own = ~plus & G::MB;
   }

@@ -159,3 +159,57 @@ def test_c2_size_prefix_with_measurements(ctx):
     assert np.array_equal(np.array(Es), ref["E_log"].reshape(2, -1))
     assert np.array_equal(np.array(Qs), ref["Q_log"].reshape(2, -1))
     assert_same_state(job, ref, "C2")
+
+
+@pytest.mark.parametrize("model,algo,L", [("ising", oracle.METROPOLIS, 24),
+                                          ("ising", oracle.HEATBATH, 16),
+                                          ("potts", oracle.HEATBATH, 16)])
+def test_checkpoint_resume_is_bit_exact(ctx, model, algo, L):
+    from paper_0704_3573_amd import binding as B
+    S, R, K, pe = 1, 2, 3, (2 if model == "ising" else 0)
+    betas = 1.0 / np.linspace(0.8, 1.4, K)
+    inst = instance(model, L, S, R, K, seed=950)
+    full = make_job(ctx, model, algo, L, betas, inst, S=S, R=R, pt_every=pe)
+    full.sweep(9)
+    part = make_job(ctx, model, algo, L, betas, inst, S=S, R=R, pt_every=pe)
+    part.sweep(5)
+    wh, pw = part.wheels()
+    resumed = B.Job(ctx, B.ISING if model == "ising" else B.POTTS, algo, L, betas, inst["J"],
+                    part.spins(), wh, pw if pe else None, n_samples=S, n_replicas=R, pt_every=pe,
+                    slot_of_temp=part.perm(), sweeps_done=5)
+    resumed.sweep(4)
+    assert np.array_equal(resumed.spins(), full.spins())
+    assert np.array_equal(resumed.wheels()[0], full.wheels()[0])
+    assert np.array_equal(resumed.perm(), full.perm())
+    assert np.array_equal(resumed.measure()[0], full.measure()[0])
+
+
+def test_parallel_tempering_many_temperatures(ctx):
+    # K > 64 takes the unfused parallel-tempering kernel
+    L, S, R, K, pe = 4, 1, 1, 70, 1
+    betas = 1.0 / np.linspace(0.5, 3.0, K)
+    inst = instance("ising", L, S=S, R=R, K=K, seed=960)
+    job = make_job(ctx, "ising", oracle.METROPOLIS, L, betas, inst, S=S, R=R, pt_every=pe)
+    job.sweep(6)
+    ref = run_oracle("ising", oracle.METROPOLIS, L, betas, inst, S=S, R=R, n=6, pt_every=pe)
+    assert_same_state(job, ref, "K=70")
+
+
+def test_potts_c4_shape_sampled_chains_full_length(ctx):
+    # q = 4 +-J Potts, L = 16, 128 samples x 2 replicas, heat bath T = 0.9,
+    # 10^4 sweeps; samples 0 and 77 re-run by the oracle
+    L, S, R = 16, 128, 2
+    inst = instance("potts", L, S=S, R=R, seed=4000)
+    job = make_job(ctx, "potts", oracle.HEATBATH, L, [1 / 0.9], inst, S=S, R=R)
+    for _ in range(10):
+        job.sweep(1000)
+    E, Q = job.measure()
+    sp = job.spins()
+    for s in (0, 77):
+        sub = {"J": inst["J"][s:s + 1], "spins": inst["spins"][2 * s:2 * s + 2],
+               "wheels": inst["wheels"][2 * s:2 * s + 2], "ptwheels": inst["ptwheels"][:2]}
+        ref = run_oracle("potts", oracle.HEATBATH, L, [1 / 0.9], sub, R=R, n=10_000,
+                         measure_every=10_000, threads=2)
+        assert np.array_equal(sp[2 * s:2 * s + 2], ref["spins"])
+        assert np.array_equal(E[2 * s:2 * s + 2], ref["E_log"][0].reshape(-1))
+        assert Q[s] == ref["Q_log"][0, 0, 0]

@@ -1,0 +1,128 @@
+"""CPU tests of the serving loop's scheduling: admission by slots and memory
+budget, FIFO order, exact per-job sweep counts under continuous batching.
+A fake backend counts sweeps instead of launching kernels."""
+import pytest
+
+from paper_0704_3573_amd.serving import Request, Server, poisson_stream, summary
+
+
+class FakeJob:
+    def __init__(self, req):
+        self.req = req
+        self.done = 0
+        self.closed = False
+
+    def sweeps_done(self):
+        return self.done
+
+    def close(self):
+        self.closed = True
+
+
+class FakeBatch:
+    def __init__(self):
+        self.jobs = []
+        self.budgets = {}
+        self.runs = []
+
+    def add(self, j):
+        assert j not in self.jobs
+        self.jobs.append(j)
+
+    def remove(self, j):
+        self.jobs.remove(j)
+        self.budgets.pop(id(j))
+
+    def set_budget(self, j, n):
+        self.budgets[id(j)] = n
+
+    def run(self, n):
+        self.runs.append((n, len(self.jobs)))
+        for j in self.jobs:
+            k = min(n, self.budgets[id(j)])
+            j.done += k
+            self.budgets[id(j)] -= k
+
+
+class FakeBackend:
+    def __init__(self, clock):
+        self.clock = clock
+        self.created = []
+
+    def new_batch(self):
+        return FakeBatch()
+
+    def job_bytes(self, req):
+        return req.L ** 3  # stand-in size
+
+    def create(self, req):
+        self.created.append(req.rid)
+        return FakeJob(req)
+
+    def run(self, batch, n):
+        batch.run(n)
+        self.clock.t += 1e-6 * n * len(batch.jobs)
+
+    def finish(self, job, req):
+        assert job.done == req.sweeps
+        req.E = [job.done, -job.done]
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+def run(reqs, budget, slots, period):
+    clock = Clock()
+    be = FakeBackend(clock)
+    srv = Server(be, hbm_budget=budget, max_slots=slots, period=period)
+    done = srv.serve(reqs, clock=clock, sleep=clock.sleep)
+    return srv, be, done
+
+
+def test_every_job_runs_exactly_its_sweeps():
+    reqs = poisson_stream(60, rate=2000.0, seed=3, sweeps_lo=1.0, sweeps_hi=3.0)
+    srv, be, done = run(reqs, budget=10 ** 9, slots=8, period=77)
+    assert len(done) == 60
+    assert all(r.E == [r.sweeps, -r.sweeps] for r in done)
+    assert srv.peak_slots <= 8
+    assert all(r.t_admit >= r.arrival and r.t_done >= r.t_admit for r in done)
+
+
+def test_admission_respects_memory_budget_and_fifo():
+    reqs = [Request(i, "ising", L, 1.0, 50, i, arrival=0.0) for i, L in
+            enumerate([48, 8, 8, 48, 16, 48, 8])]
+    budget = 48 ** 3 + 2 * 8 ** 3
+    srv, be, done = run(reqs, budget=budget, slots=100, period=10)
+    assert srv.peak_used <= budget
+    # FIFO: a large job blocks later small ones until memory frees up
+    assert be.created == [0, 1, 2, 3, 4, 5, 6]
+    assert len(done) == 7
+
+
+def test_oversized_request_is_rejected():
+    with pytest.raises(RuntimeError):
+        run([Request(0, "ising", 48, 1.0, 10, 0)], budget=1000, slots=4, period=10)
+
+
+def test_jobs_join_while_others_run():
+    reqs = [Request(0, "ising", 8, 1.0, 1000, 0, arrival=0.0),
+            Request(1, "potts", 8, 1.0, 100, 1, arrival=1e-4)]
+    srv, be, done = run(reqs, budget=10 ** 9, slots=4, period=100)
+    assert [r.rid for r in done] == [1, 0]
+    # the second job joined a batch that already held the first
+    assert any(k == 2 for _, k in srv.batch.runs)
+
+
+def test_summary_percentiles():
+    reqs = poisson_stream(30, rate=500.0, seed=4, sweeps_lo=1.0, sweeps_hi=2.0)
+    srv, be, done = run(reqs, budget=10 ** 9, slots=16, period=50)
+    s = summary(done, wall=1.0)
+    assert s["jobs"] == 30 and s["p99_latency_s"] >= s["p50_latency_s"] >= 0
