@@ -90,6 +90,36 @@ def build_c3(ctx, B, inputs):
     return jobs
 
 
+def serving_bench(ctx, n_jobs, seed=5):
+    """Continuous-batching request loop: calibrate the saturated capacity with a
+    burst, then serve a Poisson stream at 1.2x that rate.  Jobs: EA Ising
+    (Metropolis) or q=4 Potts (heat bath) with probability 1/2, L uniform in
+    {8,16,24,32,48}, T uniform in [0.7, 1.6], 2 replicas, sweeps log-uniform in
+    10^2.5 .. 10^4 (the 10^3 .. 10^5 range scaled down to fit a short run)."""
+    from paper_0704_3573_amd import serving
+    lo, hi = 2.5, 4.0
+    be = serving.DeviceBackend(ctx)
+    burst = serving.poisson_stream(max(16, n_jobs // 3), rate=0.0, seed=seed + 1, sweeps_lo=lo,
+                                   sweeps_hi=hi, seed0=9000)
+    srv = serving.Server(be, hbm_budget=64 << 30, max_slots=512, period=500)
+    t = time.perf_counter()
+    srv.serve(burst)
+    cap = len(burst) / (time.perf_counter() - t)
+    rate = 1.2 * cap
+    reqs = serving.poisson_stream(n_jobs, rate=rate, seed=seed, sweeps_lo=lo, sweeps_hi=hi)
+    srv = serving.Server(be, hbm_budget=64 << 30, max_slots=512, period=500)
+    t = time.perf_counter()
+    done = srv.serve(reqs)
+    wall = time.perf_counter() - t
+    out = serving.summary(done, wall)
+    out.update({"capacity_jobs_per_s": round(cap, 3), "arrival_rate_per_s": round(rate, 3),
+                "peak_resident_jobs": srv.peak_slots, "periods": srv.periods,
+                "workload": f"{n_jobs} Poisson jobs, Ising-Metropolis/Potts-heat-bath 1:1, "
+                            f"L in {{8,16,24,32,48}}, T~U[0.7,1.6], sweeps 10^U[{lo},{hi}], "
+                            f"2 replicas, HBM budget 64 GiB, 512 slots"})
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """The oracle on a bounded sample of the batched workload: one sample of
     each L with its 64 copies, whole parallel-tempering periods."""
@@ -130,6 +160,9 @@ def main():
                     help="timed plain steps (100 sweeps + measurement each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--serving-jobs", type=int, default=120,
+                    help="jobs in the serving stream (0 = skip the serving measurement)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the block-size autotuner")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched form (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -163,6 +196,12 @@ def main():
     # ------------------------------------------------ batched (headline) --
     jobs = build_c3(ctx, B, inputs)
     batch = B.Batch(ctx, jobs)
+    tune_times = {}
+    if not args.no_tune:
+        from paper_0704_3573_amd import autotune
+        tpb, tune_times = autotune.tune(batch, C3_PT, periods=2, stream=stream, use_cache=False)
+        log(f"[bench] autotuned block: {tpb} threads "
+            f"({', '.join(f'{k}:{v:.3f}ms' for k, v in sorted(tune_times.items()))})")
     tpb = batch.block()
     sites = sum(j.C * j.N for j in jobs)
     log(f"[bench] batched: {len(jobs)} jobs, {sum(j.C for j in jobs)} copies, {sites} sites, "
@@ -223,6 +262,11 @@ def main():
         f"{plain_value:.2f} updates/ns")
     del job
 
+    serving_stats = None
+    if args.serving_jobs > 0:
+        serving_stats = serving_bench(ctx, args.serving_jobs)
+        log(f"[bench] serving: {serving_stats}")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -248,6 +292,7 @@ def main():
                         "sweeps; step = 10 sweeps + PT step",
             "copies": 16384, "sites": sites, "updates_per_step": updates_per_step,
             "block_threads": tpb, "parallelism": "single GPU",
+            "autotune_ms_per_launch": {str(k): round(v, 4) for k, v in sorted(tune_times.items())},
         },
         "roofline": {
             "bound": "alu",
@@ -269,6 +314,7 @@ def main():
             "ms_per_step": round(plain_ms, 3),
         },
         "speedup_batched_over_plain": round(value / plain_value, 2),
+        "serving": serving_stats,
         "cpu_baseline": cpu,
         "context": {"paper_fpga_ea_updates_per_ns": {"Virtex4-LX160": 31.25,
                                                      "Virtex4-LX200": 62.5},
