@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=120,
                     help="jobs in the serving stream (0 = skip the serving measurement)")
     ap.add_argument("--no-tune", action="store_true", help="skip the block-size autotuner")
+    ap.add_argument("--block", type=int, default=0,
+                    help="force the fused launch's threads per workgroup (skips the tuner)")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched form (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -197,7 +199,9 @@ def main():
     jobs = build_c3(ctx, B, inputs)
     batch = B.Batch(ctx, jobs)
     tune_times = {}
-    if not args.no_tune:
+    if args.block:
+        batch.set_block(args.block)
+    elif not args.no_tune:
         from paper_0704_3573_amd import autotune
         tpb, tune_times = autotune.tune(batch, C3_PT, periods=2, stream=stream, use_cache=False)
         log(f"[bench] autotuned block: {tpb} threads "
