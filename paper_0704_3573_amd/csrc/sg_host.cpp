@@ -191,8 +191,9 @@ struct sg_job {
 
 // lanes and LDS bytes of a work item of G copies
 static size_t item_lds(const sg_job *j, int G) {
-  // copies, per-copy tables and counters, and one dummy word
-  if (j->sp.model == SG_ISING) return (size_t)G * j->g.CS * 4 + (size_t)G * 4 + 4;
+  // Ising: copies, per-copy counters and one scratch copy for lanes without a
+  // wheel; Potts: copies, per-copy weight tables and counters, one dummy byte
+  if (j->sp.model == SG_ISING) return (size_t)(G + 1) * j->g.CS * 4 + (size_t)G * 4;
   return (size_t)G * j->N + (size_t)G * 16 * 4 + (size_t)G * 4 + 4;
 }
 
@@ -779,6 +780,7 @@ struct sg_batch {
   int32_t *d_cap = nullptr;
   size_t d_jobs_cap = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<GraphKey, int> seen;  // periods launched directly per key since the last plan
   std::vector<void *> graph_bufs;  // device buffers referenced by captured graphs
   std::map<std::vector<int>, PtTable> pt_cache;
   hipStream_t cap_stream = nullptr;
@@ -791,6 +793,7 @@ struct sg_batch {
 static void drop_graphs(sg_batch *b) {
   for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
   b->graphs.clear();
+  b->seen.clear();
   for (void *p : b->graph_bufs) (void)hipFree(p);
   b->graph_bufs.clear();
   b->pt_cache.clear();
@@ -1097,6 +1100,16 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
       continue;
     }
     auto it = b->graphs.find(key);
+    if (it == b->graphs.end() && b->seen[key]++ == 0) {
+      // first period with this membership and shape: launch directly; a graph
+      // is captured only once the same period recurs (serving changes
+      // membership often, the batched campaign repeats one period)
+      rc = enqueue_period(b, key.nsw, key.pt_jobs, st);
+      if (rc) return rc;
+      account(b, chunk);
+      left -= chunk;
+      continue;
+    }
     if (it == b->graphs.end()) {
       hipGraph_t g;
       HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -97,8 +97,8 @@ DEV uint32_t gt3(uint32_t a2, uint32_t a1, uint32_t a0, uint32_t b2, uint32_t b1
 
 // Per-lane context of the Ising sweep.
 struct IsingLane {
-  uint32_t *sp;        // LDS base of the lane's copy
-  uint32_t *dummy;     // LDS word that lanes without a wheel write to
+  uint32_t *sp;        // LDS base of the lane's copy (lanes without a wheel: a
+                       // scratch copy they may read and overwrite)
   rsrc_t rJ;           // couplings of the job
   uint32_t joff;       // byte offset of (sample, z) in the couplings
   int z, zp, zm, g;
@@ -116,7 +116,6 @@ DEV void ising_neighbours(const IsingLane &ln, int p, int blk, uint32_t &S, uint
   const int y0 = ln.g * G::RHO + blk * G::RPB;
   own = ln.sp + (p * L + ln.z) * G::WZ + wb;
   S = *own;
-  own = ln.dummy ? ln.dummy : own;
   const uint32_t *oc = ln.sp + (q * L + ln.z) * G::WZ;
   const uint32_t Wc = oc[wb];
   N[4] = ln.sp[(q * L + ln.zp) * G::WZ + wb];  // z+
@@ -144,8 +143,15 @@ DEV void ising_neighbours(const IsingLane &ln, int p, int blk, uint32_t &S, uint
   // x neighbours: in a row of parity e = (p + y + z) & 1, site j (x = 2j + e)
   // has x+1 at other-colour index j + e and x-1 at index j + e - 1 (periodic
   // within the row).
-  const uint32_t rl = bfi(G::LOWB, Wc >> (G::H - 1), Wc << 1);  // index j+1 into j
-  const uint32_t rr = bfi(G::TOPB, Wc << (G::H - 1), Wc >> 1);  // index j-1 into j
+  uint32_t rl, rr;
+  if constexpr (G::RPB == 1) {
+    // one row per word: plain rotations of B bits (bits above B are don't-care)
+    rl = (Wc << 1) | (Wc >> (G::B - 1));  // index j+1 into j
+    rr = (Wc >> 1) | (Wc << (G::B - 1));  // index j-1 into j
+  } else {
+    rl = bfi(G::LOWB, Wc >> (G::H - 1), Wc << 1);
+    rr = bfi(G::TOPB, Wc << (G::H - 1), Wc >> 1);
+  }
   const uint32_t em = ((p + y0 + ln.z) & 1) ? G::EVENSEG : G::ODDSEG;
   N[0] = bfi(em, rl, Wc);
   N[1] = bfi(em, Wc, rr);
@@ -154,10 +160,13 @@ DEV void ising_neighbours(const IsingLane &ln, int p, int blk, uint32_t &S, uint
 template <int L>
 DEV void ising_couplings(const IsingLane &ln, int p, int blk, uint32_t Jw[6]) {
   using G = GC<L>;
-  const int wb = ln.g * G::NBLK + blk;
-  const uint32_t off = ln.joff + (uint32_t)((p * G::NWB + wb) * 6 * L) * 4u;
+  // per-lane part (sample, row group, plane) in the VGPR offset, the
+  // wave-uniform part (colour, block, direction) in the SGPR offset
+  const uint32_t voff = ln.joff + (uint32_t)(ln.g * G::NBLK * 6 * L) * 4u;
+  const uint32_t soff =
+      __builtin_amdgcn_readfirstlane((uint32_t)((p * G::NWB + blk) * 6 * L) * 4u);
 #pragma unroll
-  for (int d = 0; d < 6; d++) Jw[d] = bload(ln.rJ, off + d * L * 4);
+  for (int d = 0; d < 6; d++) Jw[d] = bload(ln.rJ, voff, soff + d * L * 4);
 }
 
 // One Metropolis draw: I(k) = I(k-24) + I(k-55), r = I(k) xor I(k-61) (Eq. 5);
@@ -177,6 +186,23 @@ DEV void met_step(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint
       "v_addc_co_u32 %[b0], %[j0], %[b0], %[b0], %[m0]"
       : [n] "=&v"(inew), [r] "=&v"(r), [ts] "=&v"(ts), [m1] "=&s"(m1), [m0] "=&s"(m0),
         [j1] "=&s"(j1), [j0] "=&s"(j0), [b1] "+v"(b1), [b0] "+v"(b0)
+      : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T0] "v"(T0), [T1] "v"(T1), [T2] "v"(T2));
+}
+
+// First draw of a block: as met_step, the accumulators start from the carry.
+DEV void met_step0(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T0,
+                   uint32_t T1, uint32_t T2, uint32_t &b1, uint32_t &b0) {
+  uint32_t r, ts;
+  uint64_t m1, m0, j1, j0;
+  asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
+      "v_xor_b32 %[r], %[n], %[c]\n\t"
+      "v_cmp_lt_u32 %[m1], %[r], %[T1]\n\t"
+      "v_cndmask_b32 %[ts], %[T2], %[T0], %[m1]\n\t"
+      "v_cmp_lt_u32 %[m0], %[r], %[ts]\n\t"
+      "v_addc_co_u32 %[b1], %[j1], 0, 0, %[m1]\n\t"
+      "v_addc_co_u32 %[b0], %[j0], 0, 0, %[m0]"
+      : [n] "=&v"(inew), [r] "=&v"(r), [ts] "=&v"(ts), [m1] "=&s"(m1), [m0] "=&s"(m0),
+        [j1] "=&s"(j1), [j0] "=&s"(j0), [b1] "=&v"(b1), [b0] "=&v"(b0)
       : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T0] "v"(T0), [T1] "v"(T1), [T2] "v"(T2));
 }
 
@@ -223,12 +249,18 @@ DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int
 #pragma unroll
   for (int i = 0; i < B; i++) {
     const int k = VI * B + i;  // static after unrolling
-    if constexpr (ALGO == 0)
-      met_step(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
-               ring[(k + M - 61) % M], ln.T[0], ln.T[1], ln.T[2], b1, b0);
-    else
+    if constexpr (ALGO == 0) {
+      if (i == 0)
+        met_step0(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
+                  ring[(k + M - 61) % M], ln.T[0], ln.T[1], ln.T[2], b1, b0);
+      else
+        met_step(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
+                 ring[(k + M - 61) % M], ln.T[0], ln.T[1], ln.T[2], b1, b0);
+    }
+    else {
       hb_step(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
               ring[(k + M - 61) % M], ln.T, b2, b1, b0);
+    }
   }
   __builtin_amdgcn_sched_barrier(0);
 
@@ -323,7 +355,7 @@ struct Drive {
 template <class K, int VI>
 DEV bool drive_chain(K &k, uint32_t (&ring)[K::M], Drive &d) {
   // every lane of a wave that holds at least one wheel runs the block (lanes
-  // without a wheel compute on copy 0 and store to a dummy word), so the ring
+  // without a wheel compute on scratch data they alone write), so the ring
   // registers never flow around a divergent branch
   k.template block<VI>(ring, d.p, d.blk);
   if (++d.blk == K::NBLK) {
@@ -341,12 +373,13 @@ DEV bool drive_chain(K &k, uint32_t (&ring)[K::M], Drive &d) {
     return false;
 }
 
-// When V divides NBLK every half-sweep starts at ring phase 0: the half-sweep
-// is NBLK / V repetitions of the V phases and the launch has a single exit.
-template <class K, int VI>
-DEV void drive_cycle(K &k, uint32_t (&ring)[K::M], int p, int blk0) {
-  k.template block<VI>(ring, p, blk0 + VI);
-  if constexpr (VI + 1 < K::V) drive_cycle<K, VI + 1>(k, ring, p, blk0);
+// When V divides NBLK every half-sweep starts at ring phase 0: the NBLK
+// blocks of a half-sweep are unrolled (block b at phase b mod V, every block
+// index a compile-time constant) and the launch has a single exit.
+template <class K, int BLK>
+DEV void drive_half(K &k, uint32_t (&ring)[K::M], int p) {
+  k.template block<BLK % K::V>(ring, p, BLK);
+  if constexpr (BLK + 1 < K::NBLK) drive_half<K, BLK + 1>(k, ring, p);
 }
 
 template <class K>
@@ -362,7 +395,7 @@ DEV void drive(K &k, Drive &d) {
   if constexpr (K::NBLK % K::V == 0) {
     for (int s = 0; s < d.nsweeps; s++)
       for (int p = 0; p < 2; p++) {
-        for (int b0 = 0; b0 < K::NBLK; b0 += K::V) drive_cycle<K, 0>(k, ring, p, b0);
+        drive_half<K, 0>(k, ring, p);
         __syncthreads();
       }
     if (d.active) ring_store<K::M, K::M - 1>(ring, d.rwh, d.widx, d.wstride, d.kmod);
@@ -395,7 +428,7 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   const int lanes = w.ncopies * G::NW;
   const bool active = t < lanes;
   int *Ucnt = (int *)(lds + w.ncopies * G::CS);
-  uint32_t *dummy = lds + w.ncopies * G::CS + w.ncopies;
+  uint32_t *scratch_copy = lds + w.ncopies * G::CS + w.ncopies;  // CS words
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
 
   // stage the copies in LDS
@@ -408,8 +441,7 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   const int cl = active ? t / G::NW : 0;
   const int wl = t - cl * G::NW;
   const int copy = w.copy0 + cl;
-  ln.sp = lds + cl * G::CS;
-  ln.dummy = active ? nullptr : dummy;
+  ln.sp = active ? lds + cl * G::CS : scratch_copy;
   ln.g = wl / L;
   ln.z = wl - ln.g * L;
   ln.zp = ln.z + 1 == L ? 0 : ln.z + 1;
