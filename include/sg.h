@@ -151,7 +151,8 @@ int sg_batch_create(sg_ctx *ctx, sg_batch **out);
 int sg_batch_add(sg_batch *b, sg_job *job);
 int sg_batch_remove(sg_batch *b, sg_job *job);
 /* Threads per workgroup of the fused launch (multiple of 64, <= 1024;
- * 0 = automatic).  Results do not depend on it. */
+ * 0 = automatic); the Potts launch uses min(threads, 512).  Results do not
+ * depend on it. */
 int sg_batch_set_block(sg_batch *b, int32_t threads);
 /* Remaining sweep budget of a job in the batch: a run of n sweeps advances
  * the job by min(n, budget) and lowers the budget by that much

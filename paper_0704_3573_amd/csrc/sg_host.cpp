@@ -146,7 +146,7 @@ static Layout layout(const sg_job_spec *sp) {
   Layout l{};
   uint64_t o = 0;
   l.spins_bytes = sp->model == SG_ISING ? C * g.CS * 4 : C * N;
-  l.J_bytes = sp->model == SG_ISING ? S * sg::ising_js(sp->L) * 4 : S * N;
+  l.J_bytes = (sp->model == SG_ISING ? S * sg::ising_js(sp->L) : S * sg::potts_js(sp->L)) * 4;
   l.wheels_bytes = (uint64_t)g.M * C * g.NW * 4;
   l.spins = o; o = al(o + l.spins_bytes);
   l.J = o; o = al(o + l.J_bytes);
@@ -192,13 +192,22 @@ struct sg_job {
 // lanes and LDS bytes of a work item of G copies
 static size_t item_lds(const sg_job *j, int G) {
   // Ising: copies, per-copy counters and one scratch copy for lanes without a
-  // wheel; Potts: copies, per-copy weight tables and counters, one dummy byte
+  // wheel; Potts: the rotation-base table, copies, per-copy weight tables and
+  // counters, and (when a wave can hold lanes without a wheel) the region
+  // those lanes store into
   if (j->sp.model == SG_ISING) return (size_t)(G + 1) * j->g.CS * 4 + (size_t)G * 4;
-  return (size_t)G * j->N + (size_t)G * 16 * 4 + (size_t)G * 4 + 4;
+  const size_t dummy = j->g.NW % 64 ? (size_t)j->g.RHO * j->L * j->L : 0;
+  return (size_t)sg::POTTS_TAB_WORDS * 4 + (size_t)G * sg::potts_lds_copy(j->L) +
+         (size_t)G * sg::POTTS_W_WORDS * 4 + (size_t)G * 4 + dummy;
+}
+
+// threads per workgroup of a model's launch for a requested block size
+static int model_tpb(int model, int tpb) {
+  return model == SG_POTTS ? std::min(tpb, sg::POTTS_MAX_TPB) : tpb;
 }
 
 static int copies_per_item(const sg_job *j, int tpb) {
-  int G = tpb / j->g.NW;
+  int G = model_tpb(j->sp.model, tpb) / j->g.NW;
   G = std::min(G, j->C);
   while (G > 1 && item_lds(j, G) > (size_t)j->ctx->max_lds) G--;
   return G;
@@ -336,15 +345,27 @@ static void unpack_potts_spins(int L, const uint8_t *in, uint8_t *s) {
       for (int x = 0; x < L; x++) s[x + L * (y + L * z)] = (uint8_t)(in[potts_idx(L, x, y, z)] >> 3);
 }
 
-static void pack_potts_J(int L, const int8_t *J, uint8_t *out) {
-  for (int z = 0; z < L; z++)
-    for (int y = 0; y < L; y++)
-      for (int x = 0; x < L; x++) {
-        uint8_t pat = 0;
-        for (int d = 0; d < 6; d++)
-          if (bond(J, L, x, y, z, d) < 0) pat |= (uint8_t)(1u << d);
-        out[potts_idx(L, x, y, z)] = pat;
-      }
+// coupling pattern bytes in wheel draw order (see sg_layout.h)
+static void pack_potts_J(const Geom &g, const int8_t *J, uint32_t *out) {
+  const int L = g.L, BQ = sg::potts_bq(L);
+  for (int p = 0; p < 2; p++)
+    for (int blk = 0; blk < g.NBLK; blk++)
+      for (int q = 0; q < BQ; q++)
+        for (int w = 0; w < g.NW; w++) {
+          const int gr = w / L, z = w % L;
+          uint32_t word = 0;
+          for (int b = 0; b < 4; b++) {
+            const int kb = 4 * q + b;
+            if (kb >= g.B) break;
+            const int y = gr * g.RHO + blk * g.RPB + kb / g.H;
+            const int x = 2 * (kb % g.H) + ((p + y + z) & 1);
+            uint32_t pat = 0;
+            for (int d = 0; d < 6; d++)
+              if (bond(J, L, x, y, z, d) < 0) pat |= 1u << d;
+            word |= pat << (8 * b);
+          }
+          out[((size_t)(p * g.NBLK + blk) * BQ + q) * g.NW + w] = word;
+        }
 }
 
 // wheel words (oldest first) of a state that has drawn k0 numbers -> slots
@@ -523,9 +544,10 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
     HIPCHK(hipMemcpy(j->at<void>(lay.spins), sp.data(), lay.spins_bytes, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(j->at<void>(lay.J), jw.data(), lay.J_bytes, hipMemcpyHostToDevice));
   } else {
-    std::vector<uint8_t> sp((size_t)C * N), jp((size_t)S * N);
+    std::vector<uint8_t> sp((size_t)C * N);
+    std::vector<uint32_t> jp((size_t)S * sg::potts_js(j->L));
     for (uint64_t c = 0; c < C; c++) pack_potts_spins(j->L, (const uint8_t *)spins + c * N, &sp[c * N]);
-    for (uint64_t s = 0; s < S; s++) pack_potts_J(j->L, J + s * 3 * N, &jp[s * N]);
+    for (uint64_t s = 0; s < S; s++) pack_potts_J(j->g, J + s * 3 * N, &jp[s * sg::potts_js(j->L)]);
     HIPCHK(hipMemcpy(j->at<void>(lay.spins), sp.data(), lay.spins_bytes, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(j->at<void>(lay.J), jp.data(), lay.J_bytes, hipMemcpyHostToDevice));
   }
@@ -772,7 +794,7 @@ struct sg_batch {
   // plan
   bool dirty = true;
   int tpb = 0;
-  size_t lds = 0;
+  size_t lds[2][2] = {{0, 0}, {0, 0}};  // per (model, algo) launch
   std::vector<Work> items[2][2];  // [model][algo]
   Work *d_items = nullptr;
   size_t d_items_cap = 0;
@@ -808,7 +830,7 @@ static double idle_fraction(const sg_batch *b, int tpb) {
     if (G < 1) return 2.0;
     const double items = std::ceil((double)j->C / G);
     used += (double)j->C * j->g.NW * j->g.RHO;  // weight by draws per sweep per lane
-    total += items * ((tpb + 63) / 64 * 64) * j->g.RHO;
+    total += items * ((model_tpb(j->sp.model, tpb) + 63) / 64 * 64) * j->g.RHO;
   }
   return total > 0 ? 1.0 - used / total : 0.0;
 }
@@ -832,10 +854,11 @@ static int plan(sg_batch *b) {
     if (j->g.NW > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
   for (auto &a : b->items)
     for (auto &v : a) v.clear();
-  size_t lds = 0, total = 0;
+  size_t lds[2][2] = {{0, 0}, {0, 0}}, total = 0;
   for (sg_job *j : b->jobs) {
     const int G = copies_per_item(j, tpb);
-    lds = std::max(lds, item_lds(j, G));
+    size_t &l = lds[j->sp.model][j->sp.algo];
+    l = std::max(l, item_lds(j, G));
     make_items(j, G, b->items[j->sp.model][j->sp.algo]);
   }
   // longest items first: the launch tail is then made of short items
@@ -877,7 +900,8 @@ static int plan(sg_batch *b) {
   }
   b->run_cap.assign(b->jobs.size(), 0x7FFFFFFF);
   b->tpb = tpb;
-  b->lds = lds;
+  for (int m = 0; m < 2; m++)
+    for (int a = 0; a < 2; a++) b->lds[m][a] = lds[m][a];
   b->dirty = false;
   return SG_OK;
 }
@@ -942,7 +966,8 @@ static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs,
           s = b->side[g - 1];
           HIPCHK(hipStreamWaitEvent(s, b->fork, 0));
         }
-        HIPCHK(sg::launch_sweep(m, a, b->d_items + off, (int)v.size(), b->tpb, b->lds, nsw, s));
+        HIPCHK(sg::launch_sweep(m, a, b->d_items + off, (int)v.size(), model_tpb(m, b->tpb),
+                                b->lds[m][a], nsw, s));
         if (fork && g > 0) {
           HIPCHK(hipEventRecord(b->join[g - 1], s));
           HIPCHK(hipStreamWaitEvent(st, b->join[g - 1], 0));

@@ -169,66 +169,103 @@ DEV void ising_couplings(const IsingLane &ln, int p, int blk, uint32_t Jw[6]) {
   for (int d = 0; d < 6; d++) Jw[d] = bload(ln.rJ, voff, soff + d * L * 4);
 }
 
-// One Metropolis draw: I(k) = I(k-24) + I(k-55), r = I(k) xor I(k-61) (Eq. 5);
-// c1 = [r < T1], c0 = [r < (c1 ? T0 : T2)]; both 64-lane compare masks are
-// shifted into the per-lane accumulators by add-with-carry (acc = 2 acc + c).
-// ALU instructions only; 7 VALU operations per site.
-DEV void met_step(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T0,
-                  uint32_t T1, uint32_t T2, uint32_t &b1, uint32_t &b0) {
-  uint32_t r, ts;
-  uint64_t m1, m0, j1, j0;
+// Per-draw ALU steps in inline assembly.  Each draw computes
+// I(k) = I(k-24) + I(k-55) and r = I(k) xor I(k-61) (Eq. 5), compares r with
+// the site's thresholds (64-lane masks in SGPR pairs) and shifts the compare
+// results into per-lane accumulator words by add-with-carry (acc = 2 acc + c).
+//
+// On gfx94x / gfx950 a VALU instruction that reads an SGPR written by another
+// VALU instruction (here: a compare mask used as select mask or carry-in) must
+// issue at least two instructions after it.  The draws of a block are
+// therefore issued as a software pipeline: each draw is split into stages and
+// the stages of neighbouring draws are interleaved (volatile asm statements
+// keep their order), so every mask is read at least two instructions after it
+// was written without any wait instructions.
+//
+// Metropolis (7 VALU operations per site): c1 = [r < T1], c0 = [r < (c1 ? T0 :
+// T2)], accumulators b1, b0.
+//   stage 1: add, xor, compare c1;  stage 2: select, compare c0;
+//   stage 3: insert c1, insert c0.
+// Order: stage 1 of draw 0, then for i = 0 .. B: stage 1 of draw i + 1,
+// stage 2 of draw i, stage 3 of draw i - 1 (gaps: c1 -> select >= 3
+// instructions, c0 -> insert >= 3, for B >= 2).
+DEV void met_s1(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T1,
+                uint32_t &r, uint64_t &m1) {
   asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
-      "v_xor_b32 %[r], %[n], %[c]\n\t"
-      "v_cmp_lt_u32 %[m1], %[r], %[T1]\n\t"
-      "v_cndmask_b32 %[ts], %[T2], %[T0], %[m1]\n\t"
-      "v_cmp_lt_u32 %[m0], %[r], %[ts]\n\t"
-      "v_addc_co_u32 %[b1], %[j1], %[b1], %[b1], %[m1]\n\t"
-      "v_addc_co_u32 %[b0], %[j0], %[b0], %[b0], %[m0]"
-      : [n] "=&v"(inew), [r] "=&v"(r), [ts] "=&v"(ts), [m1] "=&s"(m1), [m0] "=&s"(m0),
-        [j1] "=&s"(j1), [j0] "=&s"(j0), [b1] "+v"(b1), [b0] "+v"(b0)
-      : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T0] "v"(T0), [T1] "v"(T1), [T2] "v"(T2));
+               "v_xor_b32 %[r], %[n], %[c]\n\t"
+               "v_cmp_lt_u32 %[m1], %[r], %[T1]"
+               : [n] "=&v"(inew), [r] "=&v"(r), [m1] "=&s"(m1)
+               : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T1] "v"(T1));
 }
 
-// First draw of a block: as met_step, the accumulators start from the carry.
-DEV void met_step0(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T0,
-                   uint32_t T1, uint32_t T2, uint32_t &b1, uint32_t &b0) {
-  uint32_t r, ts;
-  uint64_t m1, m0, j1, j0;
-  asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
-      "v_xor_b32 %[r], %[n], %[c]\n\t"
-      "v_cmp_lt_u32 %[m1], %[r], %[T1]\n\t"
-      "v_cndmask_b32 %[ts], %[T2], %[T0], %[m1]\n\t"
-      "v_cmp_lt_u32 %[m0], %[r], %[ts]\n\t"
-      "v_addc_co_u32 %[b1], %[j1], 0, 0, %[m1]\n\t"
-      "v_addc_co_u32 %[b0], %[j0], 0, 0, %[m0]"
-      : [n] "=&v"(inew), [r] "=&v"(r), [ts] "=&v"(ts), [m1] "=&s"(m1), [m0] "=&s"(m0),
-        [j1] "=&s"(j1), [j0] "=&s"(j0), [b1] "=&v"(b1), [b0] "=&v"(b0)
-      : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T0] "v"(T0), [T1] "v"(T1), [T2] "v"(T2));
+DEV void met_s2(uint32_t r, uint64_t m1, uint32_t T0, uint32_t T2, uint64_t &m0) {
+  uint32_t ts;
+  asm volatile("v_cndmask_b32 %[ts], %[T2], %[T0], %[m1]\n\t"
+               "v_cmp_lt_u32 %[m0], %[r], %[ts]"
+               : [ts] "=&v"(ts), [m0] "=&s"(m0)
+               : [r] "v"(r), [m1] "s"(m1), [T0] "v"(T0), [T2] "v"(T2));
 }
 
-// One heat-bath draw: b = #{k : r < T[k]} over seven nested thresholds, three
-// bits found by binary search and shifted into b2, b1, b0.  11 VALU operations.
-DEV void hb_step(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, const uint32_t T[7],
-                 uint32_t &b2, uint32_t &b1, uint32_t &b0) {
-  uint32_t r, ta, x, y, tb;
-  uint64_t m2, m1, m0, j2, j1, j0;
+// first draw of a block: the accumulators start from the carry; the carry-out
+// of the inserts is not used (written to VCC)
+DEV void met_s3(bool first, uint64_t m1, uint64_t m0, uint32_t &b1, uint32_t &b0) {
+  if (first)
+    asm volatile("v_addc_co_u32 %[b1], vcc, 0, 0, %[m1]\n\t"
+                 "v_addc_co_u32 %[b0], vcc, 0, 0, %[m0]"
+                 : [b1] "=&v"(b1), [b0] "=&v"(b0)
+                 : [m1] "s"(m1), [m0] "s"(m0)
+                 : "vcc");
+  else
+    asm volatile("v_addc_co_u32 %[b1], vcc, %[b1], %[b1], %[m1]\n\t"
+                 "v_addc_co_u32 %[b0], vcc, %[b0], %[b0], %[m0]"
+                 : [b1] "+v"(b1), [b0] "+v"(b0)
+                 : [m1] "s"(m1), [m0] "s"(m0)
+                 : "vcc");
+}
+
+// Heat bath (11 VALU operations per site): b = #{k : r < T[k]} over seven
+// nested thresholds, three bits by binary search into b2, b1, b0.
+//   stage 1: add, xor, compare c2 = [r < T3];
+//   stage 2: three selects by c2, compare c1 = [r < (c2 ? T1 : T5)];
+//   stage 3: select by c1, compare c0;  stage 4: insert c2, c1, c0.
+// Order: stage 1 of draw 0, then for i = 0 .. B + 1: stage 1 of draw i + 1,
+// stage 2 of draw i, stage 3 of draw i - 1, stage 4 of draw i - 2.
+DEV void hb_s1(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T3,
+               uint32_t &r, uint64_t &m2) {
   asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
-      "v_xor_b32 %[r], %[n], %[c]\n\t"
-      "v_cmp_lt_u32 %[m2], %[r], %[T3]\n\t"
-      "v_cndmask_b32 %[ta], %[T5], %[T1], %[m2]\n\t"
-      "v_cndmask_b32 %[x], %[T6], %[T2], %[m2]\n\t"
-      "v_cndmask_b32 %[y], %[T4], %[T0], %[m2]\n\t"
-      "v_cmp_lt_u32 %[m1], %[r], %[ta]\n\t"
-      "v_cndmask_b32 %[tb], %[x], %[y], %[m1]\n\t"
-      "v_cmp_lt_u32 %[m0], %[r], %[tb]\n\t"
-      "v_addc_co_u32 %[b2], %[j2], %[b2], %[b2], %[m2]\n\t"
-      "v_addc_co_u32 %[b1], %[j1], %[b1], %[b1], %[m1]\n\t"
-      "v_addc_co_u32 %[b0], %[j0], %[b0], %[b0], %[m0]"
-      : [n] "=&v"(inew), [r] "=&v"(r), [ta] "=&v"(ta), [x] "=&v"(x), [y] "=&v"(y),
-        [tb] "=&v"(tb), [m2] "=&s"(m2), [m1] "=&s"(m1), [m0] "=&s"(m0), [j2] "=&s"(j2),
-        [j1] "=&s"(j1), [j0] "=&s"(j0), [b2] "+v"(b2), [b1] "+v"(b1), [b0] "+v"(b0)
-      : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T0] "v"(T[0]), [T1] "v"(T[1]),
-        [T2] "v"(T[2]), [T3] "v"(T[3]), [T4] "v"(T[4]), [T5] "v"(T[5]), [T6] "v"(T[6]));
+               "v_xor_b32 %[r], %[n], %[c]\n\t"
+               "v_cmp_lt_u32 %[m2], %[r], %[T3]"
+               : [n] "=&v"(inew), [r] "=&v"(r), [m2] "=&s"(m2)
+               : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T3] "v"(T3));
+}
+
+DEV void hb_s2(uint32_t r, uint64_t m2, const uint32_t T[7], uint32_t &x, uint32_t &y,
+               uint64_t &m1) {
+  uint32_t ta;
+  asm volatile("v_cndmask_b32 %[ta], %[T5], %[T1], %[m2]\n\t"
+               "v_cndmask_b32 %[x], %[T6], %[T2], %[m2]\n\t"
+               "v_cndmask_b32 %[y], %[T4], %[T0], %[m2]\n\t"
+               "v_cmp_lt_u32 %[m1], %[r], %[ta]"
+               : [ta] "=&v"(ta), [x] "=&v"(x), [y] "=&v"(y), [m1] "=&s"(m1)
+               : [r] "v"(r), [m2] "s"(m2), [T0] "v"(T[0]), [T1] "v"(T[1]), [T2] "v"(T[2]),
+                 [T4] "v"(T[4]), [T5] "v"(T[5]), [T6] "v"(T[6]));
+}
+
+DEV void hb_s3(uint32_t r, uint64_t m1, uint32_t x, uint32_t y, uint64_t &m0) {
+  uint32_t tb;
+  asm volatile("v_cndmask_b32 %[tb], %[x], %[y], %[m1]\n\t"
+               "v_cmp_lt_u32 %[m0], %[r], %[tb]"
+               : [tb] "=&v"(tb), [m0] "=&s"(m0)
+               : [r] "v"(r), [m1] "s"(m1), [x] "v"(x), [y] "v"(y));
+}
+
+DEV void hb_s4(uint64_t m2, uint64_t m1, uint64_t m0, uint32_t &b2, uint32_t &b1, uint32_t &b0) {
+  asm volatile("v_addc_co_u32 %[b2], vcc, %[b2], %[b2], %[m2]\n\t"
+               "v_addc_co_u32 %[b1], vcc, %[b1], %[b1], %[m1]\n\t"
+               "v_addc_co_u32 %[b0], vcc, %[b0], %[b0], %[m0]"
+               : [b2] "+v"(b2), [b1] "+v"(b1), [b0] "+v"(b0)
+               : [m2] "s"(m2), [m1] "s"(m1), [m0] "s"(m0)
+               : "vcc");
 }
 
 // One block: B draws of the lane's wheel at ring phase VI, one per site.
@@ -245,21 +282,37 @@ DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int
   ising_neighbours<L>(ln, p, blk, S, N, own);
   __builtin_amdgcn_sched_barrier(0);
 
+  static_assert(B >= 2, "the draw pipeline needs two draws per block");
   uint32_t b0 = 0, b1 = 0, b2 = 0;
+  uint32_t r[B];
+  uint64_t m2[B], m1[B], m0[B];
+  if constexpr (ALGO == 0) {
+    auto s1 = [&](int i) {
+      const int k = VI * B + i;  // static after unrolling
+      met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
+             ln.T[1], r[i], m1[i]);
+    };
+    s1(0);
 #pragma unroll
-  for (int i = 0; i < B; i++) {
-    const int k = VI * B + i;  // static after unrolling
-    if constexpr (ALGO == 0) {
-      if (i == 0)
-        met_step0(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
-                  ring[(k + M - 61) % M], ln.T[0], ln.T[1], ln.T[2], b1, b0);
-      else
-        met_step(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
-                 ring[(k + M - 61) % M], ln.T[0], ln.T[1], ln.T[2], b1, b0);
+    for (int i = 0; i <= B; i++) {
+      if (i + 1 < B) s1(i + 1);
+      if (i < B) met_s2(r[i], m1[i], ln.T[0], ln.T[2], m0[i]);
+      if (i >= 1) met_s3(i == 1, m1[i - 1], m0[i - 1], b1, b0);
     }
-    else {
-      hb_step(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M],
-              ring[(k + M - 61) % M], ln.T, b2, b1, b0);
+  } else {
+    uint32_t x[B], y[B];
+    auto s1 = [&](int i) {
+      const int k = VI * B + i;  // static after unrolling
+      hb_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
+            ln.T[3], r[i], m2[i]);
+    };
+    s1(0);
+#pragma unroll
+    for (int i = 0; i <= B + 1; i++) {
+      if (i + 1 < B) s1(i + 1);
+      if (i < B) hb_s2(r[i], m2[i], ln.T, x[i], y[i], m1[i]);
+      if (i >= 1 && i <= B) hb_s3(r[i - 1], m1[i - 1], x[i - 1], y[i - 1], m0[i - 1]);
+      if (i >= 2) hb_s4(m2[i - 2], m1[i - 2], m0[i - 2], b2, b1, b0);
     }
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -436,10 +489,12 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   for (int i = t; i < w.ncopies * G::CS; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
   for (int i = t; i < w.ncopies; i += nthr) Ucnt[i] = 0;
 
+  // lanes without a wheel serve wheel (z = t mod L, row group 0) of the
+  // scratch copy, so all their accesses stay inside it
   IsingK<L, ALGO> k;
   IsingLane &ln = k.ln;
   const int cl = active ? t / G::NW : 0;
-  const int wl = t - cl * G::NW;
+  const int wl = active ? t - cl * G::NW : t % L;
   const int copy = w.copy0 + cl;
   ln.sp = active ? lds + cl * G::CS : scratch_copy;
   ln.g = wl / L;
@@ -479,101 +534,166 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
 }
 
 // ---------------------------------------------------------------------------
-// q = 4 +-J Potts heat bath.  One lane per wheel; each draw updates one site:
-//   h_a = sum_j J_ij delta(a, sigma_j) is accumulated in four byte fields of one
-//   word (J = +1 counts in the low nibble, J = -1 in the high nibble of byte a),
-//   w_a = W[h_max - h_a] comes from the lane's LDS table, t = (r S) >> 32 and
-//   sigma = #{a < 3 : C_a <= t} with C_a the running sums of w.
+// q = 4 +-J Potts heat bath.  One lane per wheel; each draw updates one site.
+//
+// Local field bytes.  With n- the number of J = -1 bonds of site i,
+//   c_a = 4 (h_a + n-) = 4 (#{J = +1, sigma_j = a} + #{J = -1, sigma_j != a})
+// lies in [0, 24] and differs from 4 h_a by a constant, so c_max - c_a is
+// 4 (h_max - h_a).  Neighbour j adds rotr32(R, 8 sigma_j) with the rotation
+// base R = 4 for J = +1 (a single 4 in byte (4 - sigma_j) & 3) or 0x04040400
+// for J = -1 (a 4 in every other byte); byte (4 - a) & 3 of the sum is c_a.
+// The six bases of a site come from an LDS table indexed by its coupling
+// pattern.  Then w_a = W[h_max - h_a] is read from the lane's weight table
+// (entries 4 bytes apart, so c_max - c_a is already the byte offset),
+// S = sum w_a, t = (r S) >> 32 and sigma = #{a < 3 : w_0 + ... + w_a <= t},
+// which is the sequential search for the first a with t < w_0 + ... + w_a.
+//
+// Same-colour sites are never neighbours, so the new spins of a row are kept
+// in registers and stored after the row's last draw: every LDS read of the
+// row can be scheduled ahead of any of its stores.
 // ---------------------------------------------------------------------------
-DEV uint32_t bload_u8(rsrc_t r, uint32_t voff) {
-  return __builtin_amdgcn_raw_buffer_load_b8(r, voff, 0, 0);
-}
-
 template <int L>
 struct PottsK {
   using G = GC<L>;
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK, H = G::H, RPB = G::RPB,
-                       RHO = G::RHO;
-  uint8_t *sp;         // LDS bytes of the lane's copy, [y][x][z], value 8 sigma
-  uint8_t *dummy;      // LDS byte that lanes without a wheel write to
-  const uint32_t *Wl;  // LDS weight table of the lane's temperature
-  rsrc_t rJ;           // coupling patterns of the job
-  uint32_t joff;       // byte offset of the lane's sample
+                       RHO = G::RHO, NW = G::NW, BQ = potts_bq(L);
+  uint8_t *sp;          // LDS bytes of the lane's copy, [y][x][z] (rows at row(y)), 8 sigma
+  uint8_t *wp;          // where the lane stores its new spins: sp, or a dummy
+                        // region for lanes without a wheel
+  const uint32_t *tab;  // LDS rotation bases of the 64 coupling patterns
+  const uint8_t *Wb;    // LDS weight table of the lane's temperature
+  rsrc_t rJ;            // coupling patterns of the job
+  uint32_t voff;        // byte offset of the lane's pattern words
+  bool active;          // the lane serves a wheel
   int z, zp, zm, g;
+  uint32_t nextpat[BQ];  // pattern words of the next block, loaded one block ahead
 
-  // local fields of site with neighbour states s[6] (8 sigma) and pattern pat
-  static DEV uint32_t fields(const uint32_t s[6], uint32_t pat) {
-    uint32_t acc = 0;
+  // LDS byte offset of row y (row groups skewed by L bytes)
+  static DEV int row(int y) { return y * L * L + (y / RHO) * L; }
+
+  DEV void fetch(int p, int blk) {
+    const uint32_t s0 =
+        __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * BQ) * NW * 4u);
 #pragma unroll
-    for (int d = 0; d < 6; d++) acc += 1u << (s[d] + (((pat >> d) & 1u) << 2));
-    const uint32_t lo = acc & 0x0F0F0F0Fu, hi = (acc >> 4) & 0x0F0F0F0Fu;
-    return lo + 0x06060606u - hi;  // byte a = 6 + h_a in 0..12
+    for (int q = 0; q < BQ; q++) nextpat[q] = bload(rJ, voff, s0 + (uint32_t)q * NW * 4u);
   }
 
   template <int VI>
   DEV void block(uint32_t (&ring)[M], int p, int blk) {
-    const int y0 = g * RHO + blk * RPB;
+    uint32_t pat[BQ];
+#pragma unroll
+    for (int q = 0; q < BQ; q++) pat[q] = nextpat[q];
+    if (blk + 1 < NBLK)
+      fetch(p, blk + 1);
+    else
+      fetch(p ^ 1, 0);
+    rows<VI>(ring, pat, p, g * RHO + blk * RPB, sp, wp, tab, Wb);
+  }
+
+  // The block's spins are read through rd (the lane's copy) and written
+  // through wr (the same copy, or the dummy region): every site read is of
+  // the other colour and every site written of this one, so no byte is
+  // accessed through both.  The B sites are software-pipelined in program
+  // order: while site n is finished (draw, weights, multiply, select, store),
+  // the fields of site n + 1 are formed and its weights requested, and the
+  // neighbour bytes and rotation bases of site n + 2 are requested; the
+  // scheduling barriers keep that order, so each LDS round trip overlaps the
+  // work of other sites.
+  template <int VI>
+  DEV void rows(uint32_t (&ring)[M], const uint32_t (&pat)[BQ], int p, int y0,
+                const uint8_t *__restrict__ rd, uint8_t *__restrict__ wr,
+                const uint32_t *__restrict__ tb, const uint8_t *__restrict__ wt) const {
+    int base[RPB], bxw[RPB], byp[RPB], bym[RPB];
 #pragma unroll
     for (int rr = 0; rr < RPB; rr++) {
       const int y = y0 + rr;
       const int e = (p + y + z) & 1;
       const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
-      const int base = (y * L + e) * L + z;          // site j = 0 of the row
-      const int bxw = e ? base - L : base + (L - 1) * L;  // periodic x neighbour
-      const int byp = (yp * L + e) * L + z, bym = (ym * L + e) * L + z;
-      const int bzp = base - z + zp, bzm = base - z + zm;
-#pragma unroll
-      for (int j = 0; j < H; j++) {
-        const int k = VI * B + rr * H + j;  // static
-        ring[k % M] = ring[(k + M - 24) % M] + ring[(k + M - 55) % M];
-        const uint32_t r = ring[k % M] ^ ring[(k + M - 61) % M];
-        const int o = 2 * j * L;
-        uint32_t s[6];
-        s[0] = sp[j == H - 1 ? bxw : base + o + L];
-        s[1] = sp[j == 0 ? bxw : base + o - L];
-        s[2] = sp[byp + o];
-        s[3] = sp[bym + o];
-        s[4] = sp[bzp + o];
-        s[5] = sp[bzm + o];
-        const uint32_t pat = bload_u8(rJ, joff + base + o);
-        const uint32_t c = fields(s, pat);
-        const uint32_t c0 = c & 0xFFu, c1 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c3 = c >> 24;
-        const uint32_t cm = max(max(c0, c1), max(c2, c3));
-        const uint32_t w0 = Wl[cm - c0], w1 = Wl[cm - c1], w2 = Wl[cm - c2], w3 = Wl[cm - c3];
-        const uint32_t S = w0 + w1 + w2 + w3;
-        const uint32_t t = __umulhi(r, S);
-        const uint32_t C0 = w0, C1 = w0 + w1, C2 = C1 + w2;
-        const uint32_t sig = (uint32_t)(t >= C0) + (uint32_t)(t >= C1) + (uint32_t)(t >= C2);
-        *(dummy ? dummy : sp + base + o) = (uint8_t)(sig << 3);
-      }
+      base[rr] = row(y) + e * L + z;                        // site j = 0 of the row
+      bxw[rr] = e ? base[rr] - L : base[rr] + (L - 1) * L;  // periodic x neighbour
+      byp[rr] = row(yp) + e * L + z;
+      bym[rr] = row(ym) + e * L + z;
     }
+    const int dzp = zp - z, dzm = zm - z;
+    uint32_t nb[B][6], rb[B][6], w[B][4];
+
+    auto request_site = [&](int kb) {
+      const int rr = kb / H, j = kb - rr * H, o = 2 * j * L;
+      const uint32_t *r6 = tb + POTTS_TAB_STRIDE * ((pat[kb >> 2] >> (8 * (kb & 3))) & 0xFFu);
+#pragma unroll
+      for (int d = 0; d < 6; d++) rb[kb][d] = r6[d];
+      nb[kb][0] = rd[j == H - 1 ? bxw[rr] : base[rr] + o + L];
+      nb[kb][1] = rd[j == 0 ? bxw[rr] : base[rr] + o - L];
+      nb[kb][2] = rd[byp[rr] + o];
+      nb[kb][3] = rd[bym[rr] + o];
+      nb[kb][4] = rd[base[rr] + o + dzp];
+      nb[kb][5] = rd[base[rr] + o + dzm];
+    };
+    auto request_weights = [&](int kb) {
+      const uint32_t c = __builtin_rotateright32(rb[kb][0], nb[kb][0]) +
+                         __builtin_rotateright32(rb[kb][1], nb[kb][1]) +
+                         __builtin_rotateright32(rb[kb][2], nb[kb][2]) +
+                         __builtin_rotateright32(rb[kb][3], nb[kb][3]) +
+                         __builtin_rotateright32(rb[kb][4], nb[kb][4]) +
+                         __builtin_rotateright32(rb[kb][5], nb[kb][5]);
+      const uint32_t c0 = c & 0xFFu, c3 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c1 = c >> 24;
+      const uint8_t *wm = wt + max(max(c0, c3), max(c2, c1));
+      w[kb][0] = *(const uint32_t *)(wm - c0);
+      w[kb][1] = *(const uint32_t *)(wm - c1);
+      w[kb][2] = *(const uint32_t *)(wm - c2);
+      w[kb][3] = *(const uint32_t *)(wm - c3);
+    };
+    auto finish_site = [&](int kb) {
+      const int rr = kb / H, j = kb - rr * H;
+      const int k = VI * B + kb;  // ring slot (static)
+      ring[k % M] = ring[(k + M - 24) % M] + ring[(k + M - 55) % M];
+      const uint32_t r = ring[k % M] ^ ring[(k + M - 61) % M];
+      const uint32_t C1 = w[kb][0] + w[kb][1], C2 = C1 + w[kb][2];
+      const uint32_t t = __umulhi(r, C2 + w[kb][3]);
+      uint32_t v = t >= w[kb][0] ? 8u : 0u;
+      v = t >= C1 ? 16u : v;
+      v = t >= C2 ? 24u : v;
+      wr[base[rr] + 2 * j * L] = (uint8_t)v;
+    };
+
+    request_site(0);
+    if constexpr (B > 1) request_site(1);
+    __builtin_amdgcn_sched_barrier(0);
+    request_weights(0);
+#pragma unroll
+    for (int kb = 0; kb < B; kb++) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (kb + 2 < B) request_site(kb + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kb + 1 < B) request_weights(kb + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      finish_site(kb);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 
-  // sum over the lane's colour-0 sites of h_{sigma_i} (each bond once)
-  DEV int lane_bond_sum(int) const {
+  // sum over the lane's colour-0 sites of h_{sigma_i} = sum_j J_ij delta(sigma_i, sigma_j):
+  // every bond joins a colour-0 and a colour-1 site, so each is counted once
+  DEV int lane_bond_sum() const {
     int hsum = 0;
     for (int blk = 0; blk < NBLK; blk++) {
       const int y0 = g * RHO + blk * RPB;
-      for (int rr = 0; rr < RPB; rr++) {
+      for (int kb = 0; kb < B; kb++) {
+        const int rr = kb / H, j = kb - rr * H;
         const int y = y0 + rr;
         const int e = (y + z) & 1;
         const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
-        const int base = (y * L + e) * L + z;
+        const int base = row(y) + e * L + z;
         const int bxw = e ? base - L : base + (L - 1) * L;
-        const int byp = (yp * L + e) * L + z, bym = (ym * L + e) * L + z;
-        const int bzp = base - z + zp, bzm = base - z + zm;
-        for (int j = 0; j < H; j++) {
-          const int o = 2 * j * L;
-          uint32_t s[6];
-          s[0] = sp[j == H - 1 ? bxw : base + o + L];
-          s[1] = sp[j == 0 ? bxw : base + o - L];
-          s[2] = sp[byp + o];
-          s[3] = sp[bym + o];
-          s[4] = sp[bzp + o];
-          s[5] = sp[bzm + o];
-          const uint32_t c = fields(s, bload_u8(rJ, joff + base + o));
-          hsum += (int)((c >> sp[base + o]) & 0xFFu) - 6;
-        }
+        const int o = 2 * j * L;
+        const int nb[6] = {j == H - 1 ? bxw : base + o + L, j == 0 ? bxw : base + o - L,
+                           row(yp) + e * L + z + o,         row(ym) + e * L + z + o,
+                           base - z + zp + o,               base - z + zm + o};
+        const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * BQ + (kb >> 2)) * NW) * 4u);
+        const uint32_t pat = (pw >> (8 * (kb & 3))) & 0xFFu;
+        const uint32_t si = sp[base + o];
+        for (int d = 0; d < 6; d++)
+          if (sp[nb[d]] == si) hsum += ((pat >> d) & 1u) ? -1 : 1;
       }
     }
     return hsum;
@@ -584,36 +704,52 @@ template <int L>
 DEV void potts_run(const Work &w, uint32_t *lds) {
   using G = GC<L>;
   constexpr int N3 = L * L * L;
-  constexpr int CW = N3 / 4;  // words per copy in LDS
+  constexpr int CW = potts_lds_copy(L) / 4;  // LDS words per copy
+  constexpr int GW = G::RHO * L * L / 4;     // HBM words per row group
   const int t = threadIdx.x;
   const int nthr = blockDim.x;
   const int lanes = w.ncopies * G::NW;
   const bool active = t < lanes;
-  uint32_t *Wt = lds + w.ncopies * CW;          // [ncopies][16] weight tables
-  int *Hcnt = (int *)(Wt + w.ncopies * 16);     // [ncopies]
-  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);
+  uint32_t *tab = lds;                                  // [64][7] rotation bases
+  uint32_t *cp = lds + POTTS_TAB_WORDS;                 // [ncopies][CW] spins
+  uint32_t *Wt = cp + w.ncopies * CW;                   // [ncopies][POTTS_W_WORDS]
+  int *Hcnt = (int *)(Wt + w.ncopies * POTTS_W_WORDS);  // [ncopies]
+  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);       // RHO L^2 bytes if NW % 64 != 0
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
   const uint32_t sbase = (uint32_t)w.copy0 * N3;
-  for (int i = t; i < w.ncopies * CW; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
-  for (int i = t; i < w.ncopies * 16; i += nthr) {
-    const int c = w.copy0 + i / 16;
-    Wt[i] = w.thr[w.temp_of_slot[c] * THR_WORDS + (i & 15)];
+  for (int i = t; i < POTTS_TAB_WORDS; i += nthr) {
+    const int pat = i / POTTS_TAB_STRIDE, d = i - POTTS_TAB_STRIDE * pat;
+    tab[i] = d < 6 && ((pat >> d) & 1) ? 0x04040400u : 4u;
+  }
+  // word i of a copy in HBM (rows at y L^2) -> LDS word i + (row group) L / 4
+  for (int i = t; i < w.ncopies * (N3 / 4); i += nthr) {
+    const int c = i / (N3 / 4), u = i - c * (N3 / 4);
+    cp[c * CW + u + (u / GW) * L / 4] = bload(rsp, i * 4, sbase);
+  }
+  for (int i = t; i < w.ncopies * POTTS_W_WORDS; i += nthr) {
+    const int c = w.copy0 + i / POTTS_W_WORDS;
+    Wt[i] = w.thr[w.temp_of_slot[c] * THR_WORDS + i % POTTS_W_WORDS];
   }
   for (int i = t; i < w.ncopies; i += nthr) Hcnt[i] = 0;
 
+  // lanes without a wheel run the blocks of wheel (z = t mod L, row group 0)
+  // of the first copy and store into the dummy region (the rows of row group
+  // 0 span RHO L^2 bytes); distinct z keep their stores on distinct bytes
   PottsK<L> k;
   const int cl = active ? t / G::NW : 0;
-  const int wl = t - cl * G::NW;
+  const int wl = active ? t - cl * G::NW : t % L;
   const int copy = w.copy0 + cl;
-  k.sp = (uint8_t *)(lds + cl * CW);
-  k.Wl = Wt + cl * 16;
-  k.dummy = active ? nullptr : dummy;
+  k.sp = (uint8_t *)(cp + cl * CW);
+  k.wp = active ? k.sp : dummy;
+  k.tab = tab;
+  k.Wb = (const uint8_t *)(Wt + cl * POTTS_W_WORDS);
+  k.active = active;
   k.g = wl / L;
   k.z = wl - k.g * L;
   k.zp = k.z + 1 == L ? 0 : k.z + 1;
   k.zm = k.z == 0 ? L - 1 : k.z - 1;
   k.rJ = make_rsrc(w.J, w.J_bytes);
-  k.joff = (uint32_t)(copy / w.RK) * N3;
+  k.voff = ((uint32_t)(copy / w.RK) * potts_js(L) + wl) * 4u;
 
   Drive d;
   d.nsweeps = w.nsweeps_cap;
@@ -623,17 +759,21 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   d.widx = ((uint32_t)copy * G::NW + wl) * 4u;
   d.kmod = (int)__builtin_amdgcn_readfirstlane((uint32_t)((*w.done * (uint64_t)(G::RHO * L)) % G::M));
   __syncthreads();
+  k.fetch(0, 0);
   drive(k, d);
 
-  if (active) atomicAdd(&Hcnt[cl], k.lane_bond_sum(0));
+  if (active) atomicAdd(&Hcnt[cl], k.lane_bond_sum());
   __syncthreads();
   if (w.nsweeps_cap > 0)
-    for (int i = t; i < w.ncopies * CW; i += nthr) bstore(rsp, lds[i], i * 4, sbase);
+    for (int i = t; i < w.ncopies * (N3 / 4); i += nthr) {
+      const int c = i / (N3 / 4), u = i - c * (N3 / 4);
+      bstore(rsp, cp[c * CW + u + (u / GW) * L / 4], i * 4, sbase);
+    }
   for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = -(int64_t)Hcnt[i];
 }
 
-__global__ __launch_bounds__(1024) void potts_sweep_kernel(const Work *__restrict__ works,
-                                                          int nsweeps) {
+__global__ __launch_bounds__(POTTS_MAX_TPB) void potts_sweep_kernel(const Work *__restrict__ works,
+                                                                    int nsweeps) {
   extern __shared__ uint32_t lds[];
   Work w = works[blockIdx.x];
   w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
@@ -649,7 +789,6 @@ __global__ __launch_bounds__(1024) void potts_sweep_kernel(const Work *__restric
     default: break;
   }
 }
-
 // ---------------------------------------------------------------------------
 // Overlap between replica 0 and replica 1 at every temperature.
 //   Ising: Q = N - 2 popcount(a xor b) over the packed words (pads are zero);

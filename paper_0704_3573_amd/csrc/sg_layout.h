@@ -15,9 +15,14 @@
 //   [p][wb][d][z] so that the lanes of a wave (consecutive z) read one
 //   contiguous segment.
 // Potts copy: one byte per site holding 8 * sigma, ordered [y][x][z] (z
-//   fastest: the lanes of a wave serve consecutive z planes).  Potts
-//   couplings: one byte per site whose bit d is set when the bond in
-//   direction d (x+, x-, y+, y-, z+, z-) has J = -1, same [y][x][z] order.
+//   fastest: the lanes of a wave serve consecutive z planes).
+// Potts couplings: one pattern byte per site whose bit d is set when the
+//   bond in direction d (x+, x-, y+, y-, z+, z-) has J = -1, stored in the
+//   order the wheels consume the sites: word ((p * NBLK + blk) * BQ + q) * NW
+//   + wheel holds, in byte b, the pattern of the (4q + b)-th site of block blk
+//   of half-sweep p of that wheel (BQ = ceil(B / 4) words per block), so one
+//   dword load per lane serves four consecutive draws and a wave's loads are
+//   contiguous.
 // Wheels: M >= 62 slots per wheel, slot (k mod M) holds I(k); slots are
 //   stored [slot][copy * NW + wheel] (coalesced across lanes).
 #pragma once
@@ -66,6 +71,25 @@ SG_HD constexpr bool potts_supported_L(int L) { return supported_L(L) && L <= 48
 
 // Words of Ising couplings per sample.
 SG_HD constexpr int ising_js(int L) { return 2 * geom(L).NWB * 6 * L; }
+
+// Potts pattern words per block and per sample.
+SG_HD constexpr int potts_bq(int L) { return (geom(L).B + 3) / 4; }
+SG_HD constexpr int potts_js(int L) { return 2 * geom(L).NBLK * potts_bq(L) * geom(L).NW; }
+
+// Potts work items: at most 512 lanes per workgroup (the kernel keeps up to
+// 256 VGPRs per lane).  LDS = the 64-entry rotation-base table (6 words per
+// coupling pattern at an odd stride of 7 words, so that lanes reading
+// different entries hit different banks), then the copies, then per copy 8
+// weight words and 1 counter.  In LDS a copy's row y starts at byte
+// y L^2 + (y / RHO) L (each row group is skewed by L bytes) and copies are
+// potts_lds_copy(L) bytes apart (= N + NG L, 0 mod 4): the lanes of a wave
+// (consecutive z of consecutive row groups and copies) then touch
+// consecutive bytes, i.e. distinct LDS banks.
+constexpr int POTTS_MAX_TPB = 512;
+constexpr int POTTS_TAB_STRIDE = 7;
+constexpr int POTTS_TAB_WORDS = 64 * POTTS_TAB_STRIDE;
+constexpr int POTTS_W_WORDS = 8;
+SG_HD constexpr int potts_lds_copy(int L) { return (L * L * L + geom(L).NG * L + 3) / 4 * 4; }
 
 // Per-temperature threshold row: 16 words.  Ising Metropolis uses [0..2],
 // heat bath [0..6], Potts [0..12]; a threshold equal to 2^32 is stored as

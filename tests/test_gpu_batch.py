@@ -112,3 +112,27 @@ def test_full_size_batched_pt_workload_sampled_chains(ctx):
         wh, pw = job.wheels()
         assert np.array_equal(wh[5 * 64:6 * 64], ref["wheels"]), f"L={L}"
         assert np.array_equal(pw[10:12], ref["ptwheels"]), f"L={L}"
+
+
+@pytest.mark.parametrize("block", [320, 448, 512, 1024])
+def test_partial_waves_match_oracle(ctx, block):
+    """Copies whose wheel count is not a multiple of 64 (L = 24, 40, 48, and an
+    odd number of L = 16 Potts copies) leave lanes without a wheel in a live
+    wave; those lanes must not disturb any result, at every block size (the
+    Potts launch uses at most 512 threads)."""
+    from paper_0704_3573_amd import binding as B
+    specs = [("potts", oracle.HEATBATH, 48, 1, 1, 1), ("potts", oracle.HEATBATH, 40, 1, 1, 1),
+             ("potts", oracle.HEATBATH, 24, 1, 3, 1), ("potts", oracle.HEATBATH, 16, 1, 3, 1),
+             ("ising", oracle.METROPOLIS, 24, 1, 3, 1), ("ising", oracle.HEATBATH, 40, 1, 1, 1)]
+    jobs = []
+    for n, (model, algo, L, S, R, K) in enumerate(specs):
+        betas = [1.0 / (0.8 + 0.1 * n)]
+        inst = instance(model, L, S, R, K, seed=900 + n)
+        jobs.append((model, algo, L, S, R, betas, inst,
+                     make_job(ctx, model, algo, L, betas, inst, S=S, R=R)))
+    batch = B.Batch(ctx, [j[-1] for j in jobs], block=block)
+    batch.run(3)
+    batch.run(2)
+    for model, algo, L, S, R, betas, inst, job in jobs:
+        ref = run_oracle(model, algo, L, betas, inst, S=S, R=R, n=5)
+        assert_same_state(job, ref, f"block={block} {model} L={L} copies={S * R}")
