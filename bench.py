@@ -151,6 +151,42 @@ def cpu_baseline(budget_s=15.0):
                       f"of {C3_PT} sweeps each, {updates:.3g} updates in {elapsed:.1f}s"}
 
 
+def potts_c4(ctx, B, inputs, np, torch, stream, sweeps):
+    """q = 4 +-J Potts glass, L = 16 and 32, 128 samples x 2 replicas, heat
+    bath at T = 0.9: updates/ns over periods of `sweeps` sweeps (one launch
+    each), wall clock and HIP-event kernel time."""
+    out = {}
+    for L in (16, 32):
+        inst = inputs.make_instance("potts", L, 128, 2, 1, seed=4000)
+        job = B.Job(ctx, B.POTTS, B.HEATBATH, L, [1 / 0.9], inst["J"], inst["spins"],
+                    inst["wheels"], n_samples=128, n_replicas=2)
+        del inst
+        pb = B.Batch(ctx, [job])
+        pb.run(sweeps, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            pb.run(sweeps, stream)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3 / 3
+        pb.set_timing(True)
+        pk = []
+        for _ in range(3):
+            pb.run(sweeps, stream)
+            pk.append(pb.sweep_ms())
+        ups = job.C * job.N * sweeps
+        out[f"L{L}"] = {"value": round(ups / (wall_ms * 1e6), 3), "unit": "spin updates/ns",
+                        "ms_per_period": round(wall_ms, 3),
+                        "kernel_ms_per_period": round(float(np.mean(pk)), 3),
+                        "block_threads": pb.block()}
+        log(f"[bench] Potts L={L}: {wall_ms:.2f} ms per {sweeps} sweeps, "
+            f"{out[f'L{L}']['value']:.1f} updates/ns")
+        del pb, job
+    out["workload"] = (f"q=4 +-J Potts glass, 128 samples x 2 replicas, heat bath T=0.9, "
+                       f"period = {sweeps} sweeps (one launch)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,11 +198,15 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serving-jobs", type=int, default=120,
                     help="jobs in the serving stream (0 = skip the serving measurement)")
+    ap.add_argument("--potts-sweeps", type=int, default=200,
+                    help="sweeps per timed Potts period (0 = skip the Potts measurement)")
     ap.add_argument("--no-tune", action="store_true", help="skip the block-size autotuner")
     ap.add_argument("--block", type=int, default=0,
                     help="force the fused launch's threads per workgroup (skips the tuner)")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched form (profiling runs)")
+    ap.add_argument("--potts-only", action="store_true",
+                    help="time only the Potts heat-bath workload (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -194,6 +234,10 @@ def main():
         return
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
+
+    if args.potts_only:
+        log(f"[bench] Potts only: {potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps)}")
+        return
 
     # ------------------------------------------------ batched (headline) --
     jobs = build_c3(ctx, B, inputs)
@@ -266,6 +310,10 @@ def main():
         f"{plain_value:.2f} updates/ns")
     del job
 
+    # ------------------------------------------- q = 4 Potts, heat bath --
+    potts = potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps) \
+        if args.potts_sweeps > 0 else None
+
     serving_stats = None
     if args.serving_jobs > 0:
         serving_stats = serving_bench(ctx, args.serving_jobs)
@@ -318,6 +366,7 @@ def main():
             "ms_per_step": round(plain_ms, 3),
         },
         "speedup_batched_over_plain": round(value / plain_value, 2),
+        "potts_c4": potts,
         "serving": serving_stats,
         "cpu_baseline": cpu,
         "context": {"paper_fpga_ea_updates_per_ns": {"Virtex4-LX160": 31.25,

@@ -568,8 +568,8 @@ struct PottsK {
   int z, zp, zm, g;
   uint32_t nextpat[BQ];  // pattern words of the next block, loaded one block ahead
 
-  // LDS byte offset of row y (row groups skewed by L bytes)
-  static DEV int row(int y) { return y * L * L + (y / RHO) * L; }
+  // LDS byte offset of row y (row groups skewed by 2L bytes)
+  static DEV int row(int y) { return y * L * L + (y / RHO) * 2 * L; }
 
   DEV void fetch(int p, int blk) {
     const uint32_t s0 =
@@ -721,10 +721,10 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
     const int pat = i / POTTS_TAB_STRIDE, d = i - POTTS_TAB_STRIDE * pat;
     tab[i] = d < 6 && ((pat >> d) & 1) ? 0x04040400u : 4u;
   }
-  // word i of a copy in HBM (rows at y L^2) -> LDS word i + (row group) L / 4
+  // word u of a copy in HBM (rows at y L^2) -> LDS word u + (row group) L / 2
   for (int i = t; i < w.ncopies * (N3 / 4); i += nthr) {
     const int c = i / (N3 / 4), u = i - c * (N3 / 4);
-    cp[c * CW + u + (u / GW) * L / 4] = bload(rsp, i * 4, sbase);
+    cp[c * CW + u + (u / GW) * L / 2] = bload(rsp, i * 4, sbase);
   }
   for (int i = t; i < w.ncopies * POTTS_W_WORDS; i += nthr) {
     const int c = w.copy0 + i / POTTS_W_WORDS;
@@ -767,7 +767,7 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   if (w.nsweeps_cap > 0)
     for (int i = t; i < w.ncopies * (N3 / 4); i += nthr) {
       const int c = i / (N3 / 4), u = i - c * (N3 / 4);
-      bstore(rsp, cp[c * CW + u + (u / GW) * L / 4], i * 4, sbase);
+      bstore(rsp, cp[c * CW + u + (u / GW) * L / 2], i * 4, sbase);
     }
   for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = -(int64_t)Hcnt[i];
 }

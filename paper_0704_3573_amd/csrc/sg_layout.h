@@ -81,15 +81,17 @@ SG_HD constexpr int potts_js(int L) { return 2 * geom(L).NBLK * potts_bq(L) * ge
 // coupling pattern at an odd stride of 7 words, so that lanes reading
 // different entries hit different banks), then the copies, then per copy 8
 // weight words and 1 counter.  In LDS a copy's row y starts at byte
-// y L^2 + (y / RHO) L (each row group is skewed by L bytes) and copies are
-// potts_lds_copy(L) bytes apart (= N + NG L, 0 mod 4): the lanes of a wave
-// (consecutive z of consecutive row groups and copies) then touch
-// consecutive bytes, i.e. distinct LDS banks.
+// y L^2 + (y / RHO) 2L (each row group is skewed by 2L bytes) and copies are
+// potts_lds_copy(L) bytes apart (= N + 2 NG L, 0 mod 4).  The lanes of one
+// row group (consecutive z, sites x = 2j + e with e alternating in z) touch
+// a 2L-byte window of a row; with these offsets the windows of the row
+// groups and copies of a wave are consecutive modulo 256 bytes, i.e. they
+// fall on distinct LDS banks.
 constexpr int POTTS_MAX_TPB = 512;
 constexpr int POTTS_TAB_STRIDE = 7;
 constexpr int POTTS_TAB_WORDS = 64 * POTTS_TAB_STRIDE;
 constexpr int POTTS_W_WORDS = 8;
-SG_HD constexpr int potts_lds_copy(int L) { return (L * L * L + geom(L).NG * L + 3) / 4 * 4; }
+SG_HD constexpr int potts_lds_copy(int L) { return (L * L * L + 2 * geom(L).NG * L + 3) / 4 * 4; }
 
 // Per-temperature threshold row: 16 words.  Ising Metropolis uses [0..2],
 // heat bath [0..6], Potts [0..12]; a threshold equal to 2^32 is stored as
