@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-ISING, POTTS = 0, 1
+ISING, POTTS, GPOTTS = 0, 1, 2  # GPOTTS: glassy (permutation) Potts, Eq. (3)
 METROPOLIS, HEATBATH = 0, 1
 
 _lib = None
@@ -64,7 +64,12 @@ def lib():
         _lib.or_potts_update_site.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                               C.c_uint32, u64p]
         _lib.or_potts_update_site.restype = C.c_int32
-        for n in ("or_ising_energy", "or_potts_energy"):
+        _lib.or_gpotts_update_site.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                               C.c_uint32, u64p]
+        _lib.or_gpotts_update_site.restype = C.c_int32
+        _lib.or_gpotts_fields.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                          C.POINTER(C.c_int32)]
+        for n in ("or_ising_energy", "or_potts_energy", "or_gpotts_energy"):
             getattr(_lib, n).argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
             getattr(_lib, n).restype = C.c_int64
         for n in ("or_ising_overlap", "or_potts_overlap"):
@@ -138,10 +143,32 @@ def potts_update_site(L, s, J, i, r, W) -> int:
                                           _p(W, C.c_uint64)))
 
 
+def gpotts_update_site(L, s, P, i, r, W) -> int:
+    """Glassy Potts: update site i of uint8 spins s with permutation bytes P [3][N]."""
+    W = np.ascontiguousarray(W, dtype=np.uint64)
+    assert s.dtype == np.uint8 and P.dtype == np.uint8 and s.flags.c_contiguous
+    return int(lib().or_gpotts_update_site(L, s.ctypes.data, P.ctypes.data, i, r,
+                                           _p(W, C.c_uint64)))
+
+
+def gpotts_fields(L, s, P, i) -> np.ndarray:
+    """Local fields h_a (a = 0..3) of site i of the glassy Potts model."""
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    P = np.ascontiguousarray(P, dtype=np.uint8)
+    h = np.zeros(4, dtype=np.int32)
+    lib().or_gpotts_fields(L, s.ctypes.data, P.ctypes.data, i, _p(h, C.c_int32))
+    return h
+
+
+def _couplings(model, J):
+    return np.ascontiguousarray(J, dtype=np.uint8 if model == GPOTTS else np.int8)
+
+
 def energy(model, L, s, J) -> int:
     s = np.ascontiguousarray(s)
-    J = np.ascontiguousarray(J, dtype=np.int8)
-    f = lib().or_ising_energy if model == ISING else lib().or_potts_energy
+    J = _couplings(model, J)
+    f = {ISING: lib().or_ising_energy, POTTS: lib().or_potts_energy,
+         GPOTTS: lib().or_gpotts_energy}[model]
     return int(f(L, s.ctypes.data, J.ctypes.data))
 
 
@@ -176,7 +203,7 @@ def run(model, algo, L, betas, J, spins, wheels, ptwheels=None, slot_of_temp=Non
     Cn = S * R * K
     N = L ** 3
     NW = wheels_per_copy(L)
-    J = np.ascontiguousarray(J, dtype=np.int8).reshape(S, 3, N)
+    J = _couplings(model, J).reshape(S, 3, N)
     sp = np.array(spins, dtype=np.int8 if model == ISING else np.uint8, copy=True).reshape(Cn, N)
     wh = np.array(wheels, dtype=np.uint32, copy=True).reshape(Cn, NW, 61)
     if ptwheels is None:

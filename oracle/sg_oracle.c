@@ -143,10 +143,12 @@ static int32_t ising_update(int32_t algo, int8_t *s, const int8_t *J, int64_t i,
   return -(nw - old) * h;
 }
 
-static int32_t potts_update(uint8_t *s, const int8_t *J, int64_t i, const int64_t nb[6],
-                            const int64_t bond[6], uint32_t r, const uint64_t W[13]) {
-  int32_t h[4] = {0, 0, 0, 0}; /* h_a = sum_j J_ij delta(a, s_j) */
-  for (int d = 0; d < 6; d++) h[s[nb[d]]] += J[bond[d]];
+/* Heat bath over the four states given their local fields h_a (the energy
+ * of state a is -h_a): P(a) ~ exp(beta h_a), drawn with the integer weights
+ * w_a = W[h_max - h_a] and t = floor(r S / 2^32), S = sum w_a: the new state
+ * is the first a with t < w_0 + ... + w_a.  Returns the energy change. */
+static int32_t potts_heat_bath(uint8_t *s, int64_t i, const int32_t h[4], uint32_t r,
+                               const uint64_t W[13]) {
   int32_t hmax = h[0];
   for (int a = 1; a < 4; a++)
     if (h[a] > hmax) hmax = h[a];
@@ -171,6 +173,41 @@ static int32_t potts_update(uint8_t *s, const int8_t *J, int64_t i, const int64_
   return -(h[nw] - h[old]);
 }
 
+static int32_t potts_update(uint8_t *s, const int8_t *J, int64_t i, const int64_t nb[6],
+                            const int64_t bond[6], uint32_t r, const uint64_t W[13]) {
+  int32_t h[4] = {0, 0, 0, 0}; /* h_a = sum_j J_ij delta(a, s_j) */
+  for (int d = 0; d < 6; d++) h[s[nb[d]]] += J[bond[d]];
+  return potts_heat_bath(s, i, h, r, W);
+}
+
+/* Glassy Potts, Eq. (3).  The term of the bond between i and j = i + e_d
+ * (stored at i as pi) is delta(s_i, pi(s_j)).  For the fields of i:
+ *   bond to j = i + e_d (stored at i):   s_i = a scores iff a = pi(s_j);
+ *   bond to j = i - e_d (stored at j):   s_i = a scores iff pi(a) = s_j. */
+static int perm_image(uint8_t P, int v) { return (P >> (2 * v)) & 3; }
+
+static void gpotts_fields(const uint8_t *s, const uint8_t *P, const int64_t nb[6],
+                          const int64_t bond[6], int32_t h[4]) {
+  for (int a = 0; a < 4; a++) h[a] = 0;
+  for (int d = 0; d < 6; d++) {
+    uint8_t pi = P[bond[d]];
+    int sj = s[nb[d]];
+    if ((d & 1) == 0) {
+      h[perm_image(pi, sj)] += 1;
+    } else {
+      for (int a = 0; a < 4; a++)
+        if (perm_image(pi, a) == sj) h[a] += 1;
+    }
+  }
+}
+
+static int32_t gpotts_update(uint8_t *s, const uint8_t *P, int64_t i, const int64_t nb[6],
+                             const int64_t bond[6], uint32_t r, const uint64_t W[13]) {
+  int32_t h[4];
+  gpotts_fields(s, P, nb, bond, h);
+  return potts_heat_bath(s, i, h, r, W);
+}
+
 int32_t or_ising_update_site(int32_t L, int32_t algo, int8_t *s, const int8_t *J,
                              int64_t i, uint32_t r, const uint64_t *T) {
   int64_t nb[6], bond[6];
@@ -183,6 +220,19 @@ int32_t or_potts_update_site(int32_t L, uint8_t *s, const int8_t *J, int64_t i, 
   int64_t nb[6], bond[6];
   neighbours(L, i, nb, bond);
   return potts_update(s, J, i, nb, bond, r, W);
+}
+
+int32_t or_gpotts_update_site(int32_t L, uint8_t *s, const uint8_t *P, int64_t i, uint32_t r,
+                              const uint64_t W[13]) {
+  int64_t nb[6], bond[6];
+  neighbours(L, i, nb, bond);
+  return gpotts_update(s, P, i, nb, bond, r, W);
+}
+
+void or_gpotts_fields(int32_t L, const uint8_t *s, const uint8_t *P, int64_t i, int32_t h[4]) {
+  int64_t nb[6], bond[6];
+  neighbours(L, i, nb, bond);
+  gpotts_fields(s, P, nb, bond, h);
 }
 
 int64_t or_ising_energy(int32_t L, const int8_t *s, const int8_t *J) {
@@ -202,6 +252,18 @@ int64_t or_potts_energy(int32_t L, const uint8_t *s, const int8_t *J) {
     neighbours(L, i, nb, bond);
     for (int d = 0; d < 6; d += 2)
       if (s[i] == s[nb[d]]) E -= J[bond[d]];
+  }
+  return E;
+}
+
+/* Eq. (3): each bond once, as the term stored at its lower site. */
+int64_t or_gpotts_energy(int32_t L, const uint8_t *s, const uint8_t *P) {
+  int64_t N = (int64_t)L * L * L, E = 0;
+  for (int64_t i = 0; i < N; i++) {
+    int64_t nb[6], bond[6];
+    neighbours(L, i, nb, bond);
+    for (int d = 0; d < 6; d += 2)
+      if (s[i] == perm_image(P[bond[d]], s[nb[d]])) E -= 1;
   }
   return E;
 }
@@ -247,19 +309,22 @@ static void copy_sweep(const or_spec *sp, void *spins, const int8_t *J, or_wheel
             neighbours_xyz(L, x, y, z, nb, bond);
             if (sp->model == OR_ISING)
               *E += ising_update(sp->algo, (int8_t *)spins, J, i, nb, bond, r, T);
-            else
+            else if (sp->model == OR_POTTS)
               *E += potts_update((uint8_t *)spins, J, i, nb, bond, r, T);
+            else
+              *E += gpotts_update((uint8_t *)spins, (const uint8_t *)J, i, nb, bond, r, T);
           }
       }
 }
 
 static int64_t copy_energy(const or_spec *sp, const void *spins, const int8_t *J) {
   if (sp->model == OR_ISING) return or_ising_energy(sp->L, (const int8_t *)spins, J);
-  return or_potts_energy(sp->L, (const uint8_t *)spins, J);
+  if (sp->model == OR_POTTS) return or_potts_energy(sp->L, (const uint8_t *)spins, J);
+  return or_gpotts_energy(sp->L, (const uint8_t *)spins, (const uint8_t *)J);
 }
 
 static void copy_tables(const or_spec *sp, double beta, uint64_t T[13]) {
-  if (sp->model == OR_POTTS)
+  if (sp->model == OR_POTTS || sp->model == OR_GPOTTS)
     or_tables_potts(beta, T);
   else if (sp->algo == OR_METROPOLIS)
     or_tables_metropolis(beta, T);
@@ -388,8 +453,8 @@ int32_t or_run(const or_spec *sp, const double *betas, const int8_t *J, void *sp
                int64_t *Q_log, uint64_t *pt_accepts) {
   if (!sp || !valid_L(sp->L) || sp->n_samples < 1 || sp->n_replicas < 1 || sp->n_temps < 1)
     return OR_EINVAL;
-  if (sp->model != OR_ISING && sp->model != OR_POTTS) return OR_EINVAL;
-  if (sp->model == OR_POTTS && sp->algo != OR_HEATBATH) return OR_EINVAL;
+  if (sp->model != OR_ISING && sp->model != OR_POTTS && sp->model != OR_GPOTTS) return OR_EINVAL;
+  if (sp->model != OR_ISING && sp->algo != OR_HEATBATH) return OR_EINVAL;
   uint8_t *spins = (uint8_t *)spins_v;
   int64_t N = (int64_t)sp->L * sp->L * sp->L;
   int32_t NW = or_wheels_per_copy(sp->L);

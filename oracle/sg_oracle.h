@@ -1,7 +1,8 @@
 /*
  * CPU oracle for checkerboard Metropolis / heat-bath sweeps of the 3D
- * Edwards-Anderson +-J Ising glass and the q = 4 +-J Potts glass, driven by
- * Parisi-Rapuano shift-register random numbers.
+ * Edwards-Anderson +-J Ising glass, the q = 4 +-J Potts glass and the q = 4
+ * glassy (permutation) Potts model, driven by Parisi-Rapuano shift-register
+ * random numbers.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
  * calls this code; only the test suite, the smoke check and the CPU baseline
@@ -19,8 +20,12 @@
  *   checkerboard (bipartite) parallel update                (sec. 3.1)
  *   Parisi-Rapuano generator, Eq. (5)                       (sec. 3.3)
  *   parallel tempering, named as an add-on                  (sec. 2.2)
- * The Potts model here is the +-J glass H = -sum J_ij delta(s_i, s_j), not
- * the permutation glass of Eq. (3).
+ *   Eq. (3)  glassy Potts model with permutation couplings  (sec. 2.1)
+ * Two Potts models: the +-J glass H = -sum J_ij delta(s_i, s_j) (OR_POTTS)
+ * and the glassy model of Eq. (3), H = -sum_<ij> delta(s_i, pi_ij(s_j))
+ * (OR_GPOTTS).  For the latter the bond between i and j = i + e_d is stored
+ * at i as the permutation pi of that term, one byte holding its images:
+ * pi(v) = (byte >> 2v) & 3.
  */
 #ifndef SG_ORACLE_H
 #define SG_ORACLE_H
@@ -31,7 +36,7 @@
 extern "C" {
 #endif
 
-enum { OR_ISING = 0, OR_POTTS = 1 };
+enum { OR_ISING = 0, OR_POTTS = 1, OR_GPOTTS = 2 };
 enum { OR_METROPOLIS = 0, OR_HEATBATH = 1 };
 
 /* Errors returned by or_run. */
@@ -75,10 +80,17 @@ int32_t or_ising_update_site(int32_t L, int32_t algo, int8_t *s, const int8_t *J
                              int64_t i, uint32_t r, const uint64_t *T);
 int32_t or_potts_update_site(int32_t L, uint8_t *s, const int8_t *J, int64_t i,
                              uint32_t r, const uint64_t W[13]);
+/* Glassy Potts: J holds the permutation bytes [3][N] (bond i -> i + e_d). */
+int32_t or_gpotts_update_site(int32_t L, uint8_t *s, const uint8_t *P, int64_t i,
+                              uint32_t r, const uint64_t W[13]);
+/* Local fields h_a, a = 0..3, of site i of the glassy Potts model (the
+ * number of bonds of i whose term is 1 when s_i = a). */
+void or_gpotts_fields(int32_t L, const uint8_t *s, const uint8_t *P, int64_t i, int32_t h[4]);
 
 /* Energies and overlaps, by direct summation over the 3N bonds / N sites. */
 int64_t or_ising_energy(int32_t L, const int8_t *s, const int8_t *J);
 int64_t or_potts_energy(int32_t L, const uint8_t *s, const int8_t *J);
+int64_t or_gpotts_energy(int32_t L, const uint8_t *s, const uint8_t *P);
 int64_t or_ising_overlap(int32_t L, const int8_t *a, const int8_t *b);
 int64_t or_potts_overlap(int32_t L, const uint8_t *a, const uint8_t *b);
 
@@ -86,7 +98,7 @@ int64_t or_potts_overlap(int32_t L, const uint8_t *a, const uint8_t *b);
 int32_t or_wheels_per_copy(int32_t L);
 
 typedef struct {
-  int32_t model;          /* OR_ISING or OR_POTTS (q = 4)                        */
+  int32_t model;          /* OR_ISING, OR_POTTS or OR_GPOTTS (q = 4)             */
   int32_t algo;           /* OR_METROPOLIS or OR_HEATBATH (Potts: heat bath)     */
   int32_t L;              /* even side; 2, 4 or a multiple of 8                  */
   int32_t n_samples;      /* S disorder samples                                  */
@@ -101,7 +113,7 @@ typedef struct {
 /*
  * Run n_sweeps sweeps of every copy.  Copy (slot) c = (s R + r) K + k.
  *   betas         [K]            inverse temperatures, by temperature index
- *   J             [S][3][N]      int8 +-1
+ *   J             [S][3][N]      int8 +-1 (glassy Potts: permutation bytes)
  *   spins         [C][N]         int8 +-1 (Ising) or uint8 0..3 (Potts), in/out
  *   wheels        [C][NW][61]    oldest first, in/out
  *   ptwheels      [S R][61]      one wheel per chain, in/out (unused if no PT)
@@ -112,8 +124,8 @@ typedef struct {
  *   E_log         [n_meas][S R][K] energy at each measurement, by chain and
  *                                temperature index (the slot holding it)
  *   Q_log         [n_meas][S][K] replica-0 / replica-1 overlap per
- *                                temperature (Ising sum s^a s^b, Potts count of
- *                                equal sites); needs R >= 2, else untouched
+ *                                temperature (Ising sum s^a s^b, Potts models:
+ *                                count of equal sites); needs R >= 2, else untouched
  *   pt_accepts    [S R][K-1]     accepted swaps per pair, accumulated
  * Measurements are taken after sweeps measure_every, 2 measure_every, ... of
  * this call, after any parallel-tempering step due at the same sweep.

@@ -16,6 +16,10 @@ Encodings (canonical, host side):
   * site index i = x + L*(y + L*z), periodic cubic lattice of side L;
   * couplings J: int8 array [3][N], J[d][i] joins i and i + e_d (d = x, y, z);
     bit b of stream output u gives element 64*u + b, bit 1 -> -1;
+  * glassy-Potts couplings (permutations of 0..3, Eq. 3): uint8 [3][N], the
+    bond joining i and i + e_d holds the permutation pi of its term
+    delta(s_i, pi(s_{i+e_d})) as its images, pi(v) = (byte >> 2v) & 3; element
+    n is permutation number (stream output n mod 24) in lexicographic order;
   * Ising spins: int8 +-1, same bit rule;  Potts spins: uint8 0..3, two bits
     per site (bits 2k, 2k+1 of the stream word, little end first);
   * wheel seeds: 61 uint32 words per wheel, oldest first, I(-61) .. I(-1),
@@ -34,6 +38,7 @@ TAG_J = 0x4A  # 'J' couplings
 TAG_S = 0x53  # 'S' initial spins
 TAG_W = 0x57  # 'W' sweep wheels
 TAG_P = 0x50  # 'P' parallel-tempering wheels
+TAG_Q = 0x51  # 'Q' glassy-Potts permutation couplings
 
 
 def mix64(z):
@@ -74,6 +79,21 @@ def couplings(seed: int, sample: int, L: int) -> np.ndarray:
     n = L ** 3
     b = _bits(stream_key(seed, TAG_J, sample), 3 * n)
     return (1 - 2 * b.astype(np.int8)).reshape(3, n)
+
+
+def permutation_bytes() -> np.ndarray:
+    """uint8 [24]: the permutations of (0, 1, 2, 3) in lexicographic order,
+    each as the byte pi(0) | pi(1) << 2 | pi(2) << 4 | pi(3) << 6."""
+    import itertools
+    return np.array([sum(p[v] << (2 * v) for v in range(4))
+                     for p in itertools.permutations(range(4))], dtype=np.uint8)
+
+
+def glassy_couplings(seed: int, sample: int, L: int) -> np.ndarray:
+    """uint8 [3][L^3] iid uniform random permutations, one per bond."""
+    n = L ** 3
+    u = stream(stream_key(seed, TAG_Q, sample), 3 * n) % np.uint64(24)
+    return permutation_bytes()[u.astype(np.int64)].reshape(3, n)
 
 
 def ising_spins(seed: int, copies, L: int) -> np.ndarray:
@@ -125,6 +145,7 @@ def wheels_per_copy(L: int) -> int:
 def make_instance(model: str, L: int, n_samples: int, n_replicas: int,
                   n_temps: int, seed: int, sample0: int = 0):
     """All inputs of one job: couplings, spins, sweep wheels, PT wheels.
+    model: "ising", "potts" (+-J Potts glass) or "gpotts" (glassy Potts).
 
     Copy (slot) c = (s * R + r) * K + k for sample s, replica r, slot k.
     Samples are numbered from `sample0` so that one large campaign can be
@@ -132,11 +153,12 @@ def make_instance(model: str, L: int, n_samples: int, n_replicas: int,
     """
     S, R, K = n_samples, n_replicas, n_temps
     C = S * R * K
-    J = np.stack([couplings(seed, sample0 + s, L) for s in range(S)])
+    make_J = glassy_couplings if model == "gpotts" else couplings
+    J = np.stack([make_J(seed, sample0 + s, L) for s in range(S)])
     glob = np.arange(C, dtype=np.uint64) + np.uint64(sample0 * R * K)
     if model == "ising":
         sp = ising_spins(seed, glob, L)
-    elif model == "potts":
+    elif model in ("potts", "gpotts"):
         sp = potts_spins(seed, glob, L)
     else:
         raise ValueError(model)
