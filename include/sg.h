@@ -58,7 +58,8 @@ extern "C" {
 #define SG_E_STATE (-5)       /* call not valid in the current state        */
 
 #define SG_ISING 0
-#define SG_POTTS 1
+#define SG_POTTS 1  /* q = 4 +-J Potts glass, H = -sum J_ij delta(s_i, s_j)          */
+#define SG_GPOTTS 2 /* q = 4 glassy Potts model of Eq. (3), permutation couplings */
 #define SG_METROPOLIS 0
 #define SG_HEATBATH 1
 
@@ -67,8 +68,8 @@ typedef struct sg_job sg_job;
 typedef struct sg_batch sg_batch;
 
 typedef struct sg_job_spec {
-  int32_t model;      /* SG_ISING or SG_POTTS                                  */
-  int32_t algo;       /* SG_METROPOLIS or SG_HEATBATH (Potts: heat bath only)   */
+  int32_t model;      /* SG_ISING, SG_POTTS or SG_GPOTTS                       */
+  int32_t algo;       /* SG_METROPOLIS or SG_HEATBATH (Potts models: heat bath) */
   int32_t q;          /* Potts states, must be 4 (ignored for Ising)            */
   int32_t L;          /* 2, 4, 8, 16, 24, 32, 40, 48, 56, 64 (Potts: <= 48)     */
   int32_t n_samples;  /* S >= 1                                                 */
@@ -94,7 +95,11 @@ int sg_job_bytes(const sg_job_spec *spec, uint64_t *bytes);
  * Create a job in the caller's device arena and upload its state (blocks
  * until the upload has finished).
  *   betas         [K] inverse temperatures >= 0, by temperature index;
- *   J             [S][3][N] int8;  spins [C][N] int8 or uint8;
+ *   J             [S][3][N] int8, J[d][i] couples i and i + e_d: +-1 (Ising,
+ *                 +-J Potts); for SG_GPOTTS the bytes are read as uint8
+ *                 permutations pi of (0, 1, 2, 3), the bond's term being
+ *                 delta(s_i, pi(s_{i+e_d})) with pi(v) = (byte >> 2v) & 3;
+ *   spins         [C][N] int8 +-1 (Ising) or uint8 0..3 (Potts models);
  *   wheels        [C][NW][61];      ptwheels [S*R][61] (may be NULL if
  *                 pt_every == 0);
  *   slot_of_temp  [S*R][K] or NULL (identity);

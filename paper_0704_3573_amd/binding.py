@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsg.so")
 
-ISING, POTTS = 0, 1
+ISING, POTTS, GPOTTS = 0, 1, 2  # GPOTTS: glassy Potts model (permutation couplings)
 METROPOLIS, HEATBATH = 0, 1
 
 SG_OK, SG_E_INVALID, SG_E_UNSUPPORTED, SG_E_NOMEM, SG_E_HIP, SG_E_STATE = 0, -1, -2, -3, -4, -5
@@ -158,7 +158,8 @@ class Job:
         if arena is None:
             arena = torch.empty(self.bytes, dtype=torch.uint8, device=f"cuda:{ctx.device}")
         self.arena = arena
-        J = np.ascontiguousarray(J, dtype=np.int8)
+        # +-1 couplings as int8; glassy-Potts permutation bytes as uint8 (same width)
+        J = np.ascontiguousarray(J, dtype=np.uint8 if model == GPOTTS else np.int8)
         spins = np.ascontiguousarray(spins, dtype=np.int8 if model == ISING else np.uint8)
         wheels = np.ascontiguousarray(wheels, dtype=np.uint32)
         assert J.size == self.S * 3 * self.N and spins.size == self.C * self.N

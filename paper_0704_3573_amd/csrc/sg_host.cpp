@@ -78,7 +78,7 @@ static void threshold_row(int model, int algo, double beta, uint32_t row[sg::THR
   std::memset(row, 0, sizeof(uint32_t) * sg::THR_WORDS);
   uint64_t T[13];
   int n = 0;
-  if (model == SG_POTTS) {
+  if (model != SG_ISING) {
     for (int d = 0; d < 13; d++) T[d] = scaled_floor(std::exp(-beta * (double)d), 28);
     n = 13;
   } else if (algo == SG_METROPOLIS) {
@@ -102,7 +102,7 @@ static void threshold_row(int model, int algo, double beta, uint32_t row[sg::THR
       row[k] = (uint32_t)T[k];
     }
   }
-  if (model != SG_POTTS) row[15] = always;
+  if (model == SG_ISING) row[15] = always;
 }
 
 // ------------------------------------------------------------------- ctx --
@@ -122,13 +122,14 @@ static uint64_t al(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
 static int check_spec(const sg_job_spec *sp) {
   if (!sp) return fail(SG_E_INVALID, "spec is NULL");
-  if (sp->model != SG_ISING && sp->model != SG_POTTS) return fail(SG_E_INVALID, "bad model %d", sp->model);
+  if (sp->model != SG_ISING && sp->model != SG_POTTS && sp->model != SG_GPOTTS)
+    return fail(SG_E_INVALID, "bad model %d", sp->model);
   if (sp->algo != SG_METROPOLIS && sp->algo != SG_HEATBATH) return fail(SG_E_INVALID, "bad algo %d", sp->algo);
-  if (sp->model == SG_POTTS && sp->algo != SG_HEATBATH)
-    return fail(SG_E_UNSUPPORTED, "the Potts glass is built for heat bath only");
-  if (sp->model == SG_POTTS && sp->q != 4) return fail(SG_E_UNSUPPORTED, "Potts q must be 4");
+  if (sp->model != SG_ISING && sp->algo != SG_HEATBATH)
+    return fail(SG_E_UNSUPPORTED, "the Potts models are built for heat bath only");
+  if (sp->model != SG_ISING && sp->q != 4) return fail(SG_E_UNSUPPORTED, "Potts q must be 4");
   if (!sg::supported_L(sp->L)) return fail(SG_E_UNSUPPORTED, "L = %d is not built", sp->L);
-  if (sp->model == SG_POTTS && !sg::potts_supported_L(sp->L))
+  if (sp->model != SG_ISING && !sg::potts_supported_L(sp->L))
     return fail(SG_E_UNSUPPORTED, "Potts L = %d is not built (L <= 48)", sp->L);
   if (sp->n_samples < 1 || sp->n_replicas < 1 || sp->n_temps < 1)
     return fail(SG_E_INVALID, "S, R, K must be >= 1");
@@ -146,7 +147,10 @@ static Layout layout(const sg_job_spec *sp) {
   Layout l{};
   uint64_t o = 0;
   l.spins_bytes = sp->model == SG_ISING ? C * g.CS * 4 : C * N;
-  l.J_bytes = (sp->model == SG_ISING ? S * sg::ising_js(sp->L) : S * sg::potts_js(sp->L)) * 4;
+  l.J_bytes = S * 4 *
+              (uint64_t)(sp->model == SG_ISING  ? sg::ising_js(sp->L)
+                         : sp->model == SG_POTTS ? sg::potts_js(sp->L)
+                                                 : sg::gpotts_js(sp->L));
   l.wheels_bytes = (uint64_t)g.M * C * g.NW * 4;
   l.spins = o; o = al(o + l.spins_bytes);
   l.J = o; o = al(o + l.J_bytes);
@@ -203,7 +207,7 @@ static size_t item_lds(const sg_job *j, int G) {
 
 // threads per workgroup of a model's launch for a requested block size
 static int model_tpb(int model, int tpb) {
-  return model == SG_POTTS ? std::min(tpb, sg::POTTS_MAX_TPB) : tpb;
+  return model != SG_ISING ? std::min(tpb, sg::POTTS_MAX_TPB) : tpb;
 }
 
 static int copies_per_item(const sg_job *j, int tpb) {
@@ -368,6 +372,43 @@ static void pack_potts_J(const Geom &g, const int8_t *J, uint32_t *out) {
         }
 }
 
+// Glassy Potts: number (lexicographic order) of every permutation byte, -1 if
+// the byte is not a permutation of (0, 1, 2, 3).
+static void permutation_numbers(int num[256]) {
+  for (int b = 0; b < 256; b++) num[b] = -1;
+  int n = 0;
+  for (int a = 0; a < 4; a++)
+    for (int b = 0; b < 4; b++)
+      for (int c = 0; c < 4; c++)
+        for (int d = 0; d < 4; d++)
+          if (a != b && a != c && a != d && b != c && b != d && c != d)
+            num[a | b << 2 | c << 4 | d << 6] = n++;
+}
+
+// Glassy Potts couplings -> per-site words of six permutation numbers in
+// wheel draw order (see sg_layout.h); P is [3][N] permutation bytes.
+static void pack_gpotts_J(const Geom &g, const uint8_t *P, const int num[256], uint32_t *out) {
+  const int L = g.L;
+  const uint64_t N = (uint64_t)L * L * L;
+  auto idx = [&](int x, int y, int z) { return (uint64_t)((x + L) % L) + L * ((uint64_t)((y + L) % L) + (uint64_t)L * ((z + L) % L)); };
+  for (int p = 0; p < 2; p++)
+    for (int blk = 0; blk < g.NBLK; blk++)
+      for (int kb = 0; kb < g.B; kb++)
+        for (int w = 0; w < g.NW; w++) {
+          const int gr = w / L, z = w % L;
+          const int y = gr * g.RHO + blk * g.RPB + kb / g.H;
+          const int x = 2 * (kb % g.H) + ((p + y + z) & 1);
+          const uint64_t own[3] = {idx(x, y, z), idx(x, y, z), idx(x, y, z)};
+          const uint64_t low[3] = {idx(x - 1, y, z), idx(x, y - 1, z), idx(x, y, z - 1)};
+          uint32_t word = 0;
+          for (int a = 0; a < 3; a++) {
+            word |= (uint32_t)num[P[a * N + own[a]]] << (5 * (2 * a));
+            word |= (uint32_t)num[P[a * N + low[a]]] << (5 * (2 * a + 1));
+          }
+          out[((size_t)(p * g.NBLK + blk) * g.B + kb) * g.NW + w] = word;
+        }
+}
+
 // wheel words (oldest first) of a state that has drawn k0 numbers -> slots
 static void pack_wheels(const sg_job *j, const uint32_t *wh, uint64_t k0, uint32_t *out) {
   const uint64_t M = j->g.M, NW = j->g.NW, C = j->C, stride = C * NW;
@@ -492,8 +533,16 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   const uint64_t N = (uint64_t)spec->L * spec->L * spec->L;
   // validate host inputs
   const uint64_t S = spec->n_samples, R = spec->n_replicas, K = spec->n_temps, C = S * R * K;
-  for (uint64_t i = 0; i < S * 3 * N; i++)
-    if (J[i] != 1 && J[i] != -1) return fail(SG_E_INVALID, "couplings must be +1 or -1");
+  int perm_num[256];
+  permutation_numbers(perm_num);
+  if (spec->model == SG_GPOTTS) {
+    const uint8_t *P = (const uint8_t *)J;
+    for (uint64_t i = 0; i < S * 3 * N; i++)
+      if (perm_num[P[i]] < 0) return fail(SG_E_INVALID, "coupling byte %u is not a permutation", P[i]);
+  } else {
+    for (uint64_t i = 0; i < S * 3 * N; i++)
+      if (J[i] != 1 && J[i] != -1) return fail(SG_E_INVALID, "couplings must be +1 or -1");
+  }
   if (spec->model == SG_ISING) {
     const int8_t *s = (const int8_t *)spins;
     for (uint64_t i = 0; i < C * N; i++)
@@ -545,9 +594,14 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
     HIPCHK(hipMemcpy(j->at<void>(lay.J), jw.data(), lay.J_bytes, hipMemcpyHostToDevice));
   } else {
     std::vector<uint8_t> sp((size_t)C * N);
-    std::vector<uint32_t> jp((size_t)S * sg::potts_js(j->L));
     for (uint64_t c = 0; c < C; c++) pack_potts_spins(j->L, (const uint8_t *)spins + c * N, &sp[c * N]);
-    for (uint64_t s = 0; s < S; s++) pack_potts_J(j->g, J + s * 3 * N, &jp[s * sg::potts_js(j->L)]);
+    std::vector<uint32_t> jp((size_t)lay.J_bytes / 4);
+    if (spec->model == SG_POTTS) {
+      for (uint64_t s = 0; s < S; s++) pack_potts_J(j->g, J + s * 3 * N, &jp[s * sg::potts_js(j->L)]);
+    } else {
+      for (uint64_t s = 0; s < S; s++)
+        pack_gpotts_J(j->g, (const uint8_t *)J + s * 3 * N, perm_num, &jp[s * sg::gpotts_js(j->L)]);
+    }
     HIPCHK(hipMemcpy(j->at<void>(lay.spins), sp.data(), lay.spins_bytes, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(j->at<void>(lay.J), jp.data(), lay.J_bytes, hipMemcpyHostToDevice));
   }
@@ -794,8 +848,8 @@ struct sg_batch {
   // plan
   bool dirty = true;
   int tpb = 0;
-  size_t lds[2][2] = {{0, 0}, {0, 0}};  // per (model, algo) launch
-  std::vector<Work> items[2][2];  // [model][algo]
+  size_t lds[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // per (model, algo) launch
+  std::vector<Work> items[3][2];  // [model][algo]
   Work *d_items = nullptr;
   size_t d_items_cap = 0;
   uint64_t **d_done = nullptr;
@@ -854,7 +908,7 @@ static int plan(sg_batch *b) {
     if (j->g.NW > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
   for (auto &a : b->items)
     for (auto &v : a) v.clear();
-  size_t lds[2][2] = {{0, 0}, {0, 0}}, total = 0;
+  size_t lds[3][2] = {{0, 0}, {0, 0}, {0, 0}}, total = 0;
   for (sg_job *j : b->jobs) {
     const int G = copies_per_item(j, tpb);
     size_t &l = lds[j->sp.model][j->sp.algo];
@@ -900,7 +954,7 @@ static int plan(sg_batch *b) {
   }
   b->run_cap.assign(b->jobs.size(), 0x7FFFFFFF);
   b->tpb = tpb;
-  for (int m = 0; m < 2; m++)
+  for (int m = 0; m < 3; m++)
     for (int a = 0; a < 2; a++) b->lds[m][a] = lds[m][a];
   b->dirty = false;
   return SG_OK;
@@ -957,7 +1011,7 @@ static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs,
   const bool fork = capturing && groups > 1;
   if (fork) HIPCHK(hipEventRecord(b->fork, st));
   int g = 0;
-  for (int m = 0; m < 2; m++)
+  for (int m = 0; m < 3; m++)
     for (int a = 0; a < 2; a++) {
       const auto &v = b->items[m][a];
       if (!v.empty()) {

@@ -548,25 +548,34 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
 // S = sum w_a, t = (r S) >> 32 and sigma = #{a < 3 : w_0 + ... + w_a <= t},
 // which is the sequential search for the first a with t < w_0 + ... + w_a.
 //
+// Glassy Potts model (Eq. 3, GLASSY = true): neighbour j votes for the state
+// a = m_d(sigma_j), m_d = pi for the bond stored at the site (d = x+, y+, z+)
+// and pi^-1 for the bond stored at the neighbour (d = x-, y-, z-).  The LDS
+// table holds for each of the 24 permutations the words sum_v 8 pi(v) << 8v
+// (entries 0..23) and sum_v 8 pi^-1(v) << 8v (entries 24..47); the site's
+// coupling word holds the six permutation numbers, and neighbour j adds
+// 4 << ((word >> 8 sigma_j) & 31): byte a of the sum is c_a = 4 h_a, in [0, 24].
+// The rest (weights, draw, selection) is shared with the +-J glass.
+//
 // Same-colour sites are never neighbours, so the new spins of a row are kept
 // in registers and stored after the row's last draw: every LDS read of the
 // row can be scheduled ahead of any of its stores.
 // ---------------------------------------------------------------------------
-template <int L>
+template <int L, bool GLASSY>
 struct PottsK {
   using G = GC<L>;
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK, H = G::H, RPB = G::RPB,
-                       RHO = G::RHO, NW = G::NW, BQ = potts_bq(L);
+                       RHO = G::RHO, NW = G::NW, BQ = GLASSY ? G::B : potts_bq(L);
   uint8_t *sp;          // LDS bytes of the lane's copy, [y][x][z] (rows at row(y)), 8 sigma
   uint8_t *wp;          // where the lane stores its new spins: sp, or a dummy
                         // region for lanes without a wheel
-  const uint32_t *tab;  // LDS rotation bases of the 64 coupling patterns
+  const uint32_t *tab;  // LDS table: rotation bases (+-J) or vote words (glassy)
   const uint8_t *Wb;    // LDS weight table of the lane's temperature
   rsrc_t rJ;            // coupling patterns of the job
   uint32_t voff;        // byte offset of the lane's pattern words
   bool active;          // the lane serves a wheel
   int z, zp, zm, g;
-  uint32_t nextpat[BQ];  // pattern words of the next block, loaded one block ahead
+  uint32_t nextpat[BQ];  // coupling words of the next block, loaded one block ahead
 
   // LDS byte offset of row y (row groups skewed by 2L bytes)
   static DEV int row(int y) { return y * L * L + (y / RHO) * 2 * L; }
@@ -619,9 +628,14 @@ struct PottsK {
 
     auto request_site = [&](int kb) {
       const int rr = kb / H, j = kb - rr * H, o = 2 * j * L;
-      const uint32_t *r6 = tb + POTTS_TAB_STRIDE * ((pat[kb >> 2] >> (8 * (kb & 3))) & 0xFFu);
+      if constexpr (GLASSY) {
 #pragma unroll
-      for (int d = 0; d < 6; d++) rb[kb][d] = r6[d];
+        for (int d = 0; d < 6; d++) rb[kb][d] = tb[(d & 1) * 24 + ((pat[kb] >> (5 * d)) & 31u)];
+      } else {
+        const uint32_t *r6 = tb + POTTS_TAB_STRIDE * ((pat[kb >> 2] >> (8 * (kb & 3))) & 0xFFu);
+#pragma unroll
+        for (int d = 0; d < 6; d++) rb[kb][d] = r6[d];
+      }
       nb[kb][0] = rd[j == H - 1 ? bxw[rr] : base[rr] + o + L];
       nb[kb][1] = rd[j == 0 ? bxw[rr] : base[rr] + o - L];
       nb[kb][2] = rd[byp[rr] + o];
@@ -630,13 +644,21 @@ struct PottsK {
       nb[kb][5] = rd[base[rr] + o + dzm];
     };
     auto request_weights = [&](int kb) {
-      const uint32_t c = __builtin_rotateright32(rb[kb][0], nb[kb][0]) +
-                         __builtin_rotateright32(rb[kb][1], nb[kb][1]) +
-                         __builtin_rotateright32(rb[kb][2], nb[kb][2]) +
-                         __builtin_rotateright32(rb[kb][3], nb[kb][3]) +
-                         __builtin_rotateright32(rb[kb][4], nb[kb][4]) +
-                         __builtin_rotateright32(rb[kb][5], nb[kb][5]);
-      const uint32_t c0 = c & 0xFFu, c3 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c1 = c >> 24;
+      uint32_t c, c0, c1, c2, c3;
+      if constexpr (GLASSY) {
+        c = 0;
+#pragma unroll
+        for (int d = 0; d < 6; d++) c += 4u << ((rb[kb][d] >> nb[kb][d]) & 31u);
+        c0 = c & 0xFFu, c1 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c3 = c >> 24;
+      } else {
+        c = __builtin_rotateright32(rb[kb][0], nb[kb][0]) +
+            __builtin_rotateright32(rb[kb][1], nb[kb][1]) +
+            __builtin_rotateright32(rb[kb][2], nb[kb][2]) +
+            __builtin_rotateright32(rb[kb][3], nb[kb][3]) +
+            __builtin_rotateright32(rb[kb][4], nb[kb][4]) +
+            __builtin_rotateright32(rb[kb][5], nb[kb][5]);
+        c0 = c & 0xFFu, c3 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c1 = c >> 24;
+      }
       const uint8_t *wm = wt + max(max(c0, c3), max(c2, c1));
       w[kb][0] = *(const uint32_t *)(wm - c0);
       w[kb][1] = *(const uint32_t *)(wm - c1);
@@ -689,18 +711,27 @@ struct PottsK {
         const int nb[6] = {j == H - 1 ? bxw : base + o + L, j == 0 ? bxw : base + o - L,
                            row(yp) + e * L + z + o,         row(ym) + e * L + z + o,
                            base - z + zp + o,               base - z + zm + o};
-        const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * BQ + (kb >> 2)) * NW) * 4u);
-        const uint32_t pat = (pw >> (8 * (kb & 3))) & 0xFFu;
         const uint32_t si = sp[base + o];
-        for (int d = 0; d < 6; d++)
-          if (sp[nb[d]] == si) hsum += ((pat >> d) & 1u) ? -1 : 1;
+        if constexpr (GLASSY) {
+          // the bond to neighbour d scores when sigma_i = m_d(sigma_j)
+          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * BQ + kb) * NW) * 4u);
+          for (int d = 0; d < 6; d++) {
+            const uint32_t vote = tab[(d & 1) * 24 + ((pw >> (5 * d)) & 31u)];
+            hsum += ((vote >> sp[nb[d]]) & 31u) == si;
+          }
+        } else {
+          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * BQ + (kb >> 2)) * NW) * 4u);
+          const uint32_t pat = (pw >> (8 * (kb & 3))) & 0xFFu;
+          for (int d = 0; d < 6; d++)
+            if (sp[nb[d]] == si) hsum += ((pat >> d) & 1u) ? -1 : 1;
+        }
       }
     }
     return hsum;
   }
 };
 
-template <int L>
+template <int L, bool GLASSY>
 DEV void potts_run(const Work &w, uint32_t *lds) {
   using G = GC<L>;
   constexpr int N3 = L * L * L;
@@ -717,9 +748,29 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);       // RHO L^2 bytes if NW % 64 != 0
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
   const uint32_t sbase = (uint32_t)w.copy0 * N3;
-  for (int i = t; i < POTTS_TAB_WORDS; i += nthr) {
-    const int pat = i / POTTS_TAB_STRIDE, d = i - POTTS_TAB_STRIDE * pat;
-    tab[i] = d < 6 && ((pat >> d) & 1) ? 0x04040400u : 4u;
+  if constexpr (GLASSY) {
+    // vote words of the 24 permutations (lexicographic order): pi, then pi^-1
+    for (int i = t; i < 48; i += nthr) {
+      const int k = i % 24;
+      int avail[4] = {0, 1, 2, 3}, pi[4], inv[4];
+      const int digit[3] = {k / 6, (k / 2) % 3, k % 2};
+      int left = 4;
+      for (int v = 0; v < 4; v++) {
+        const int c = v < 3 ? digit[v] : 0;
+        pi[v] = avail[c];
+        for (int u = c; u + 1 < left; u++) avail[u] = avail[u + 1];
+        left--;
+      }
+      for (int v = 0; v < 4; v++) inv[pi[v]] = v;
+      uint32_t word = 0;
+      for (int v = 0; v < 4; v++) word |= (uint32_t)(8 * (i < 24 ? pi[v] : inv[v])) << (8 * v);
+      tab[i] = word;
+    }
+  } else {
+    for (int i = t; i < POTTS_TAB_WORDS; i += nthr) {
+      const int pat = i / POTTS_TAB_STRIDE, d = i - POTTS_TAB_STRIDE * pat;
+      tab[i] = d < 6 && ((pat >> d) & 1) ? 0x04040400u : 4u;
+    }
   }
   // word u of a copy in HBM (rows at y L^2) -> LDS word u + (row group) L / 2
   for (int i = t; i < w.ncopies * (N3 / 4); i += nthr) {
@@ -735,7 +786,7 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   // lanes without a wheel run the blocks of wheel (z = t mod L, row group 0)
   // of the first copy and store into the dummy region (the rows of row group
   // 0 span RHO L^2 bytes); distinct z keep their stores on distinct bytes
-  PottsK<L> k;
+  PottsK<L, GLASSY> k;
   const int cl = active ? t / G::NW : 0;
   const int wl = active ? t - cl * G::NW : t % L;
   const int copy = w.copy0 + cl;
@@ -749,7 +800,7 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   k.zp = k.z + 1 == L ? 0 : k.z + 1;
   k.zm = k.z == 0 ? L - 1 : k.z - 1;
   k.rJ = make_rsrc(w.J, w.J_bytes);
-  k.voff = ((uint32_t)(copy / w.RK) * potts_js(L) + wl) * 4u;
+  k.voff = ((uint32_t)(copy / w.RK) * (GLASSY ? gpotts_js(L) : potts_js(L)) + wl) * 4u;
 
   Drive d;
   d.nsweeps = w.nsweeps_cap;
@@ -772,22 +823,35 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = -(int64_t)Hcnt[i];
 }
 
+template <bool GLASSY>
+DEV void potts_dispatch(const Work &w, uint32_t *lds) {
+  switch (w.L) {
+    case 2: potts_run<2, GLASSY>(w, lds); break;
+    case 4: potts_run<4, GLASSY>(w, lds); break;
+    case 8: potts_run<8, GLASSY>(w, lds); break;
+    case 16: potts_run<16, GLASSY>(w, lds); break;
+    case 24: potts_run<24, GLASSY>(w, lds); break;
+    case 32: potts_run<32, GLASSY>(w, lds); break;
+    case 40: potts_run<40, GLASSY>(w, lds); break;
+    case 48: potts_run<48, GLASSY>(w, lds); break;
+    default: break;
+  }
+}
+
 __global__ __launch_bounds__(POTTS_MAX_TPB) void potts_sweep_kernel(const Work *__restrict__ works,
                                                                     int nsweeps) {
   extern __shared__ uint32_t lds[];
   Work w = works[blockIdx.x];
   w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
-  switch (w.L) {
-    case 2: potts_run<2>(w, lds); break;
-    case 4: potts_run<4>(w, lds); break;
-    case 8: potts_run<8>(w, lds); break;
-    case 16: potts_run<16>(w, lds); break;
-    case 24: potts_run<24>(w, lds); break;
-    case 32: potts_run<32>(w, lds); break;
-    case 40: potts_run<40>(w, lds); break;
-    case 48: potts_run<48>(w, lds); break;
-    default: break;
-  }
+  potts_dispatch<false>(w, lds);
+}
+
+__global__ __launch_bounds__(POTTS_MAX_TPB) void gpotts_sweep_kernel(const Work *__restrict__ works,
+                                                                     int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  potts_dispatch<true>(w, lds);
 }
 // ---------------------------------------------------------------------------
 // Overlap between replica 0 and replica 1 at every temperature.
@@ -1015,7 +1079,9 @@ hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st) {
 hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, int tpb,
                         size_t lds, int nsweeps, hipStream_t st) {
   if (nworks <= 0) return hipSuccess;
-  if (model == 1)
+  if (model == 2)
+    hipLaunchKernelGGL(gpotts_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == 1)
     hipLaunchKernelGGL(potts_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (algo == 0)
     hipLaunchKernelGGL(ising_sweep_kernel<0>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
@@ -1027,6 +1093,9 @@ hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, in
 hipError_t set_max_lds(int bytes) {
   hipError_t e = hipFuncSetAttribute((const void *)potts_sweep_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)gpotts_sweep_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)ising_sweep_kernel<0>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

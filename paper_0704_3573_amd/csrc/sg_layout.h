@@ -76,6 +76,14 @@ SG_HD constexpr int ising_js(int L) { return 2 * geom(L).NWB * 6 * L; }
 SG_HD constexpr int potts_bq(int L) { return (geom(L).B + 3) / 4; }
 SG_HD constexpr int potts_js(int L) { return 2 * geom(L).NBLK * potts_bq(L) * geom(L).NW; }
 
+// Glassy Potts couplings (permutations of 0..3, Eq. 3 of the paper): one
+// word per site, in the draw order of the +-J patterns with one site per
+// word: word ((p * NBLK + blk) * B + k) * NW + wheel.  Bits 5d..5d+4 hold the
+// number (lexicographic order, 0..23) of the permutation on the bond in
+// direction d (x+, x-, y+, y-, z+, z-): for d even the bond stored at the
+// site itself, for d odd the bond stored at the neighbour.
+SG_HD constexpr int gpotts_js(int L) { return 2 * geom(L).NBLK * geom(L).B * geom(L).NW; }
+
 // Potts work items: at most 512 lanes per workgroup (the kernel keeps up to
 // 256 VGPRs per lane).  LDS = the 64-entry rotation-base table (6 words per
 // coupling pattern at an odd stride of 7 words, so that lanes reading

@@ -5,7 +5,7 @@ import numpy as np
 import oracle
 from paper_0704_3573_amd import inputs
 
-MODELS = {"ising": oracle.ISING, "potts": oracle.POTTS}
+MODELS = {"ising": oracle.ISING, "potts": oracle.POTTS, "gpotts": oracle.GPOTTS}
 
 
 def instance(model, L, S=1, R=1, K=1, seed=1, sample0=0):

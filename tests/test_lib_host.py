@@ -30,6 +30,14 @@ def test_wheels_per_copy():
     assert B.wheels_per_copy(12) == 0 and B.wheels_per_copy(72) == 0
 
 
+def test_glassy_potts_job_bytes():
+    # one coupling word per site and sample (six permutation numbers) on top of
+    # the +-J glass's one pattern byte per site
+    g = B.job_bytes(B.Spec(B.GPOTTS, B.HEATBATH, 4, 16, 3, 2, 1, 0))
+    p = B.job_bytes(B.Spec(B.POTTS, B.HEATBATH, 4, 16, 3, 2, 1, 0))
+    assert g - p >= 3 * 3 * 16 ** 3 - 3 * 256
+
+
 def test_job_bytes_and_validation():
     n = B.job_bytes(B.Spec(B.ISING, B.METROPOLIS, 4, 64, 1, 2, 1, 0))
     # two copies of 64^3 bit-packed spins, shared couplings, 512 wheels x 64 slots each
@@ -42,6 +50,10 @@ def test_job_bytes_and_validation():
         (B.Spec(B.ISING, B.METROPOLIS, 4, 8, 0, 1, 1, 0), B.SG_E_INVALID),
         (B.Spec(B.ISING, 7, 4, 8, 1, 1, 1, 0), B.SG_E_INVALID),
         (B.Spec(B.ISING, B.METROPOLIS, 4, 8, 1, 1, 1, -1), B.SG_E_INVALID),
+        (B.Spec(B.GPOTTS, B.METROPOLIS, 4, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.GPOTTS, B.HEATBATH, 3, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.GPOTTS, B.HEATBATH, 4, 56, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(3, B.HEATBATH, 4, 8, 1, 1, 1, 0), B.SG_E_INVALID),
     ):
         with pytest.raises(B.SgError) as e:
             B.job_bytes(spec)
