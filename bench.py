@@ -151,14 +151,17 @@ def cpu_baseline(budget_s=15.0):
                       f"of {C3_PT} sweeps each, {updates:.3g} updates in {elapsed:.1f}s"}
 
 
-def potts_c4(ctx, B, inputs, np, torch, stream, sweeps):
-    """q = 4 +-J Potts glass, L = 16 and 32, 128 samples x 2 replicas, heat
-    bath at T = 0.9: updates/ns over periods of `sweeps` sweeps (one launch
-    each), wall clock and HIP-event kernel time."""
+def potts_c4(ctx, B, inputs, np, torch, stream, sweeps, model="potts"):
+    """q = 4 Potts heat bath, L = 16 and 32, 128 samples x 2 replicas:
+    updates/ns over periods of `sweeps` sweeps (one launch each), wall clock
+    and HIP-event kernel time.  model "potts": the +-J glass at T = 0.9;
+    "gpotts": the glassy (permutation) model of Eq. 3 at beta = 2.4, the
+    paper's 3D Potts temperature."""
     out = {}
+    mid, beta, seed = (B.POTTS, 1 / 0.9, 4000) if model == "potts" else (B.GPOTTS, 2.4, 4100)
     for L in (16, 32):
-        inst = inputs.make_instance("potts", L, 128, 2, 1, seed=4000)
-        job = B.Job(ctx, B.POTTS, B.HEATBATH, L, [1 / 0.9], inst["J"], inst["spins"],
+        inst = inputs.make_instance(model, L, 128, 2, 1, seed=seed)
+        job = B.Job(ctx, mid, B.HEATBATH, L, [beta], inst["J"], inst["spins"],
                     inst["wheels"], n_samples=128, n_replicas=2)
         del inst
         pb = B.Batch(ctx, [job])
@@ -179,11 +182,20 @@ def potts_c4(ctx, B, inputs, np, torch, stream, sweeps):
                         "ms_per_period": round(wall_ms, 3),
                         "kernel_ms_per_period": round(float(np.mean(pk)), 3),
                         "block_threads": pb.block()}
-        log(f"[bench] Potts L={L}: {wall_ms:.2f} ms per {sweeps} sweeps, "
+        log(f"[bench] {model} L={L}: {wall_ms:.2f} ms per {sweeps} sweeps, "
             f"{out[f'L{L}']['value']:.1f} updates/ns")
         del pb, job
-    out["workload"] = (f"q=4 +-J Potts glass, 128 samples x 2 replicas, heat bath T=0.9, "
-                       f"period = {sweeps} sweeps (one launch)")
+    if model == "potts":
+        out["workload"] = (f"q=4 +-J Potts glass, 128 samples x 2 replicas, heat bath T=0.9, "
+                           f"period = {sweeps} sweeps (one launch)")
+    else:
+        out["workload"] = (f"q=4 glassy Potts model (random permutation couplings, Eq. 3), "
+                           f"128 samples x 2 replicas, heat bath beta=2.4, period = {sweeps} "
+                           f"sweeps (one launch)")
+        # the paper's 3D glassy Potts rates (L = 16): 64 ps/spin (LX200),
+        # 125 ps/spin (LX160), 117 ns/spin (PC)
+        out["paper_updates_per_ns"] = {"Virtex4-LX200": 15.625, "Virtex4-LX160": 8.0,
+                                       "PC": round(1 / 117, 5)}
     return out
 
 
@@ -237,6 +249,8 @@ def main():
 
     if args.potts_only:
         log(f"[bench] Potts only: {potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps)}")
+        log("[bench] glassy Potts only: "
+            f"{potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps, 'gpotts')}")
         return
 
     # ------------------------------------------------ batched (headline) --
@@ -313,6 +327,8 @@ def main():
     # ------------------------------------------- q = 4 Potts, heat bath --
     potts = potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps) \
         if args.potts_sweeps > 0 else None
+    glassy = potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps, "gpotts") \
+        if args.potts_sweeps > 0 else None
 
     serving_stats = None
     if args.serving_jobs > 0:
@@ -367,6 +383,7 @@ def main():
         },
         "speedup_batched_over_plain": round(value / plain_value, 2),
         "potts_c4": potts,
+        "glassy_potts": glassy,
         "serving": serving_stats,
         "cpu_baseline": cpu,
         "context": {"paper_fpga_ea_updates_per_ns": {"Virtex4-LX160": 31.25,
