@@ -20,6 +20,7 @@ SRC = os.path.join(HERE, "sg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 ISING, POTTS, GPOTTS = 0, 1, 2  # GPOTTS: glassy (permutation) Potts, Eq. (3)
+ISING_GEN = 3  # Ising-like model of Eq. (2) with dilution and field (RFIM, DAFF)
 METROPOLIS, HEATBATH = 0, 1
 
 _lib = None
@@ -38,7 +39,7 @@ def build(force: bool = True) -> str:
 class Spec(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "model", "algo", "L", "n_samples", "n_replicas", "n_temps",
-        "pt_every", "measure_every", "check_energy", "n_threads")]
+        "pt_every", "measure_every", "check_energy", "n_threads")] + [("field", C.c_double)]
 
 
 def _p(a, t):
@@ -75,11 +76,20 @@ def lib():
         for n in ("or_ising_overlap", "or_potts_overlap"):
             getattr(_lib, n).argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
             getattr(_lib, n).restype = C.c_int64
+        _lib.or_isinggen_update_site.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                                 C.c_double, C.c_double, C.c_int64, C.c_uint32,
+                                                 i64p]
+        _lib.or_isinggen_update_site.restype = C.c_int32
+        for n in ("or_isinggen_bond_energy", "or_isinggen_field_sum"):
+            getattr(_lib, n).argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
+            getattr(_lib, n).restype = C.c_int64
+        _lib.or_isinggen_overlap.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.or_isinggen_overlap.restype = C.c_int64
         _lib.or_wheels_per_copy.argtypes = [C.c_int32]
         _lib.or_wheels_per_copy.restype = C.c_int32
         _lib.or_run.argtypes = [C.POINTER(Spec), C.POINTER(C.c_double), C.c_void_p, C.c_void_p,
                                 u32p, u32p, C.POINTER(C.c_int32), C.c_uint64, C.c_uint64,
-                                i64p, i64p, i64p, u64p]
+                                i64p, i64p, i64p, u64p, i64p]
         _lib.or_run.restype = C.c_int32
     return _lib
 
@@ -160,6 +170,24 @@ def gpotts_fields(L, s, P, i) -> np.ndarray:
     return h
 
 
+def isinggen_update_site(L, algo, s, D, field, beta, i, r):
+    """General Ising-like model: update site i of int8 spins s (D = [5][N]);
+    returns (change of the bond energy, change of the field sum)."""
+    assert s.dtype == np.int8 and D.dtype == np.int8 and s.flags.c_contiguous
+    dM = np.zeros(1, dtype=np.int64)
+    dE = lib().or_isinggen_update_site(L, algo, s.ctypes.data, D.ctypes.data, field, beta, i, r,
+                                       _p(dM, C.c_int64))
+    return int(dE), int(dM[0])
+
+
+def isinggen_terms(L, s, D):
+    """(E_b, M): bond energy and field sum; H = E_b - field * M."""
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    D = np.ascontiguousarray(D, dtype=np.int8)
+    return (int(lib().or_isinggen_bond_energy(L, s.ctypes.data, D.ctypes.data)),
+            int(lib().or_isinggen_field_sum(L, s.ctypes.data, D.ctypes.data)))
+
+
 def _couplings(model, J):
     return np.ascontiguousarray(J, dtype=np.uint8 if model == GPOTTS else np.int8)
 
@@ -191,11 +219,12 @@ class OracleError(RuntimeError):
 
 def run(model, algo, L, betas, J, spins, wheels, ptwheels=None, slot_of_temp=None, *,
         n_samples=1, n_replicas=1, n_sweeps=0, sweeps_done=0, pt_every=0,
-        measure_every=0, check_energy=False, n_threads=1):
+        measure_every=0, check_energy=False, n_threads=1, field=0.0):
     """Run the oracle; arrays are copied, the new state is returned.
 
     Returns a dict with spins, wheels, ptwheels, slot_of_temp, E (final, per
-    slot), E_log [n_meas][C], Q_log [n_meas][S][K] and pt_accepts [S*R][K-1].
+    slot), E_log [n_meas][C], Q_log [n_meas][S][K], pt_accepts [S*R][K-1] and
+    M (final field sum per slot; ISING_GEN, whose E is the bond energy).
     """
     betas = np.ascontiguousarray(betas, dtype=np.float64)
     K = betas.shape[0]
@@ -203,8 +232,9 @@ def run(model, algo, L, betas, J, spins, wheels, ptwheels=None, slot_of_temp=Non
     Cn = S * R * K
     N = L ** 3
     NW = wheels_per_copy(L)
-    J = _couplings(model, J).reshape(S, 3, N)
-    sp = np.array(spins, dtype=np.int8 if model == ISING else np.uint8, copy=True).reshape(Cn, N)
+    J = _couplings(model, J).reshape(S, 5 if model == ISING_GEN else 3, N)
+    sp = np.array(spins, dtype=np.int8 if model in (ISING, ISING_GEN) else np.uint8,
+                  copy=True).reshape(Cn, N)
     wh = np.array(wheels, dtype=np.uint32, copy=True).reshape(Cn, NW, 61)
     if ptwheels is None:
         ptwheels = np.zeros((S * R, 61), dtype=np.uint32)
@@ -214,15 +244,17 @@ def run(model, algo, L, betas, J, spins, wheels, ptwheels=None, slot_of_temp=Non
     sot = np.array(slot_of_temp, dtype=np.int32, copy=True).reshape(S * R, K)
     n_meas = n_sweeps // measure_every if measure_every else 0
     E = np.zeros(Cn, dtype=np.int64)
+    M = np.zeros(Cn, dtype=np.int64)
     E_log = np.zeros((max(n_meas, 1), Cn), dtype=np.int64)
     Q_log = np.zeros((max(n_meas, 1), S, K), dtype=np.int64)
     acc = np.zeros((S * R, max(K - 1, 1)), dtype=np.uint64)
-    spec = Spec(model, algo, L, S, R, K, pt_every, measure_every, int(check_energy), n_threads)
+    spec = Spec(model, algo, L, S, R, K, pt_every, measure_every, int(check_energy), n_threads,
+                float(field))
     rc = lib().or_run(C.byref(spec), _p(betas, C.c_double), J.ctypes.data, sp.ctypes.data,
                       _p(wh, C.c_uint32), _p(pw, C.c_uint32), _p(sot, C.c_int32),
                       sweeps_done, n_sweeps, _p(E, C.c_int64), _p(E_log, C.c_int64),
-                      _p(Q_log, C.c_int64), _p(acc, C.c_uint64))
+                      _p(Q_log, C.c_int64), _p(acc, C.c_uint64), _p(M, C.c_int64))
     if rc != 0:
         raise OracleError(f"or_run failed with code {rc}")
     return {"spins": sp, "wheels": wh, "ptwheels": pw, "slot_of_temp": sot, "E": E,
-            "E_log": E_log[:n_meas], "Q_log": Q_log[:n_meas], "pt_accepts": acc}
+            "E_log": E_log[:n_meas], "Q_log": Q_log[:n_meas], "pt_accepts": acc, "M": M}

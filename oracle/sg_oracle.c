@@ -208,6 +208,71 @@ static int32_t gpotts_update(uint8_t *s, const uint8_t *P, int64_t i, const int6
   return potts_heat_bath(s, i, h, r, W);
 }
 
+/* General Ising-like model, Eq. (2): H = -sum J_ij x_i x_j s_i s_j
+ * - sum h_i x_i s_i with h_i = field * f_i.  For an occupied site the local
+ * field is b + h_i with b = sum_j J_ij x_j s_j (an integer in [-6, 6]).
+ *   Metropolis: dE = 2 s_i (b + h_i) = 2c + 2 field (1 - 2 phi), c = s_i b,
+ *     phi = [s_i f_i = -1]; flip if dE <= 0, else iff r < floor(2^32 exp(-beta dE)).
+ *   Heat bath (Eq. 4 with E(+-1) = -+(b + h_i)): s_i = +1 iff
+ *     r < floor(2^32 / (1 + exp(-2 beta (b + field f_i)))).
+ * Empty sites (x_i = 0) consume their number and keep their value. */
+static int32_t isinggen_update(int32_t algo, int8_t *s, const int8_t *D, int64_t N, double field,
+                               double beta, int64_t i, const int64_t nb[6], const int64_t bond[6],
+                               uint32_t r, int64_t *dM) {
+  const int8_t *x = D + 3 * N, *f = D + 4 * N;
+  *dM = 0;
+  if (!x[i]) return 0;
+  int32_t b = 0;
+  for (int d = 0; d < 6; d++) b += D[bond[d]] * x[nb[d]] * s[nb[d]];
+  int32_t old = s[i], nw;
+  if (algo == OR_METROPOLIS) {
+    int32_t c = old * b;
+    int phi = old * f[i] == -1;
+    double dE = 2.0 * (double)c + 2.0 * field * (phi ? -1.0 : 1.0);
+    uint64_t T = dE <= 0.0 ? ((uint64_t)1 << 32) : scaled_floor(exp(-beta * dE), 32);
+    nw = (uint64_t)r < T ? -old : old;
+  } else {
+    double hl = (double)b + field * (double)f[i];
+    uint64_t T = scaled_floor(1.0 / (1.0 + exp(-2.0 * beta * hl)), 32);
+    nw = (uint64_t)r < T ? 1 : -1;
+  }
+  s[i] = (int8_t)nw;
+  *dM = (int64_t)(nw - old) * f[i];
+  return -(nw - old) * b;
+}
+
+int32_t or_isinggen_update_site(int32_t L, int32_t algo, int8_t *s, const int8_t *D, double field,
+                                double beta, int64_t i, uint32_t r, int64_t *dM) {
+  int64_t nb[6], bond[6];
+  neighbours(L, i, nb, bond);
+  return isinggen_update(algo, s, D, (int64_t)L * L * L, field, beta, i, nb, bond, r, dM);
+}
+
+int64_t or_isinggen_bond_energy(int32_t L, const int8_t *s, const int8_t *D) {
+  int64_t N = (int64_t)L * L * L, E = 0;
+  const int8_t *x = D + 3 * N;
+  for (int64_t i = 0; i < N; i++) {
+    int64_t nb[6], bond[6];
+    neighbours(L, i, nb, bond);
+    for (int d = 0; d < 6; d += 2) E -= (int64_t)D[bond[d]] * x[i] * x[nb[d]] * s[i] * s[nb[d]];
+  }
+  return E;
+}
+
+int64_t or_isinggen_field_sum(int32_t L, const int8_t *s, const int8_t *D) {
+  int64_t N = (int64_t)L * L * L, M = 0;
+  const int8_t *x = D + 3 * N, *f = D + 4 * N;
+  for (int64_t i = 0; i < N; i++) M += (int64_t)x[i] * f[i] * s[i];
+  return M;
+}
+
+int64_t or_isinggen_overlap(int32_t L, const int8_t *a, const int8_t *b, const int8_t *D) {
+  int64_t N = (int64_t)L * L * L, Q = 0;
+  const int8_t *x = D + 3 * N;
+  for (int64_t i = 0; i < N; i++) Q += (int64_t)x[i] * a[i] * b[i];
+  return Q;
+}
+
 int32_t or_ising_update_site(int32_t L, int32_t algo, int8_t *s, const int8_t *J,
                              int64_t i, uint32_t r, const uint64_t *T) {
   int64_t nb[6], bond[6];
@@ -294,7 +359,7 @@ int32_t or_wheels_per_copy(int32_t L) {
 /* ------------------------------------------------------------------ */
 
 static void copy_sweep(const or_spec *sp, void *spins, const int8_t *J, or_wheel *wheels,
-                       const uint64_t *T, int64_t *E) {
+                       const uint64_t *T, double beta, int64_t *E, int64_t *M) {
   int32_t L = sp->L, rho = L < 8 ? L : 8, nG = L / rho;
   for (int p = 0; p < 2; p++)
     for (int g = 0; g < nG; g++)
@@ -311,8 +376,14 @@ static void copy_sweep(const or_spec *sp, void *spins, const int8_t *J, or_wheel
               *E += ising_update(sp->algo, (int8_t *)spins, J, i, nb, bond, r, T);
             else if (sp->model == OR_POTTS)
               *E += potts_update((uint8_t *)spins, J, i, nb, bond, r, T);
-            else
+            else if (sp->model == OR_GPOTTS)
               *E += gpotts_update((uint8_t *)spins, (const uint8_t *)J, i, nb, bond, r, T);
+            else {
+              int64_t dM;
+              *E += isinggen_update(sp->algo, (int8_t *)spins, J, (int64_t)L * L * L, sp->field,
+                                    beta, i, nb, bond, r, &dM);
+              *M += dM;
+            }
           }
       }
 }
@@ -320,8 +391,16 @@ static void copy_sweep(const or_spec *sp, void *spins, const int8_t *J, or_wheel
 static int64_t copy_energy(const or_spec *sp, const void *spins, const int8_t *J) {
   if (sp->model == OR_ISING) return or_ising_energy(sp->L, (const int8_t *)spins, J);
   if (sp->model == OR_POTTS) return or_potts_energy(sp->L, (const uint8_t *)spins, J);
-  return or_gpotts_energy(sp->L, (const uint8_t *)spins, (const uint8_t *)J);
+  if (sp->model == OR_GPOTTS) return or_gpotts_energy(sp->L, (const uint8_t *)spins, (const uint8_t *)J);
+  return or_isinggen_bond_energy(sp->L, (const int8_t *)spins, J);
 }
+
+static int64_t copy_field_sum(const or_spec *sp, const void *spins, const int8_t *J) {
+  return sp->model == OR_ISING_GEN ? or_isinggen_field_sum(sp->L, (const int8_t *)spins, J) : 0;
+}
+
+/* coupling rows per sample: J_x, J_y, J_z (+ x, f for the general model) */
+static int64_t coupling_rows(const or_spec *sp) { return sp->model == OR_ISING_GEN ? 5 : 3; }
 
 static void copy_tables(const or_spec *sp, double beta, uint64_t T[13]) {
   if (sp->model == OR_POTTS || sp->model == OR_GPOTTS)
@@ -339,7 +418,7 @@ typedef struct {
   uint8_t *spins;
   or_wheel *wheels;
   const int32_t *temp_of_slot;
-  int64_t *E;
+  int64_t *E, *M;
   uint64_t nsw;
   int64_t c_begin, c_end;
   int32_t err;
@@ -354,13 +433,15 @@ static void *sweep_worker(void *p) {
   int32_t NW = or_wheels_per_copy(sp->L);
   int64_t RK = (int64_t)sp->n_replicas * sp->n_temps;
   for (int64_t c = a->c_begin; c < a->c_end; c++) {
-    const int8_t *Jc = a->J + (c / RK) * 3 * N;
+    const int8_t *Jc = a->J + (c / RK) * coupling_rows(sp) * N;
     uint8_t *sc = a->spins + c * N;
+    const double beta = a->betas[a->temp_of_slot[c]];
     uint64_t T[13];
-    copy_tables(sp, a->betas[a->temp_of_slot[c]], T);
+    copy_tables(sp, beta, T);
     for (uint64_t t = 0; t < a->nsw; t++) {
-      copy_sweep(sp, sc, Jc, a->wheels + c * NW, T, &a->E[c]);
-      if (sp->check_energy && a->E[c] != copy_energy(sp, sc, Jc)) {
+      copy_sweep(sp, sc, Jc, a->wheels + c * NW, T, beta, &a->E[c], &a->M[c]);
+      if (sp->check_energy &&
+          (a->E[c] != copy_energy(sp, sc, Jc) || a->M[c] != copy_field_sum(sp, sc, Jc))) {
         a->err = OR_ENERGY_MISMATCH;
         return NULL;
       }
@@ -370,7 +451,8 @@ static void *sweep_worker(void *p) {
 }
 
 static int32_t sweep_all(const or_spec *sp, const double *betas, const int8_t *J, uint8_t *spins,
-                         or_wheel *wheels, const int32_t *temp_of_slot, int64_t *E, uint64_t nsw) {
+                         or_wheel *wheels, const int32_t *temp_of_slot, int64_t *E, int64_t *M,
+                         uint64_t nsw) {
   int64_t C = (int64_t)sp->n_samples * sp->n_replicas * sp->n_temps;
   int nt = sp->n_threads > 0 ? sp->n_threads : 1;
   if (nt > C) nt = (int)C;
@@ -378,7 +460,7 @@ static int32_t sweep_all(const or_spec *sp, const double *betas, const int8_t *J
   pthread_t th[256];
   if (nt > 256) nt = 256;
   for (int t = 0; t < nt; t++) {
-    args[t] = (worker_arg){sp, betas, J, spins, wheels, temp_of_slot, E, nsw,
+    args[t] = (worker_arg){sp, betas, J, spins, wheels, temp_of_slot, E, M, nsw,
                            C * t / nt, C * (t + 1) / nt, 0};
   }
   for (int t = 1; t < nt; t++) pthread_create(&th[t], NULL, sweep_worker, &args[t]);
@@ -427,7 +509,6 @@ static void pt_step(const or_spec *sp, const double *betas, or_wheel *ptw, int32
 
 static void measure(const or_spec *sp, const int8_t *J, const uint8_t *spins, const int32_t *sot,
                     const int64_t *E, int64_t *E_log, int64_t *Q_log) {
-  (void)J;
   int64_t N = (int64_t)sp->L * sp->L * sp->L;
   int32_t S = sp->n_samples, R = sp->n_replicas, K = sp->n_temps;
   if (E_log)
@@ -438,10 +519,14 @@ static void measure(const or_spec *sp, const int8_t *J, const uint8_t *spins, co
     for (int k = 0; k < K; k++) {
       int64_t ca = ((int64_t)s * R + 0) * K + sot[((int64_t)s * R + 0) * K + k];
       int64_t cb = ((int64_t)s * R + 1) * K + sot[((int64_t)s * R + 1) * K + k];
-      Q_log[(int64_t)s * K + k] =
-          sp->model == OR_ISING
-              ? or_ising_overlap(sp->L, (const int8_t *)spins + ca * N, (const int8_t *)spins + cb * N)
-              : or_potts_overlap(sp->L, spins + ca * N, spins + cb * N);
+      if (sp->model == OR_ISING)
+        Q_log[(int64_t)s * K + k] =
+            or_ising_overlap(sp->L, (const int8_t *)spins + ca * N, (const int8_t *)spins + cb * N);
+      else if (sp->model == OR_ISING_GEN)
+        Q_log[(int64_t)s * K + k] = or_isinggen_overlap(sp->L, (const int8_t *)spins + ca * N,
+                                                        (const int8_t *)spins + cb * N, J + s * 5 * N);
+      else
+        Q_log[(int64_t)s * K + k] = or_potts_overlap(sp->L, spins + ca * N, spins + cb * N);
     }
 }
 
@@ -450,11 +535,12 @@ static int valid_L(int32_t L) { return L == 2 || L == 4 || (L >= 8 && L % 8 == 0
 int32_t or_run(const or_spec *sp, const double *betas, const int8_t *J, void *spins_v,
                uint32_t *wheels_words, uint32_t *ptwheels_words, int32_t *slot_of_temp,
                uint64_t sweeps_done, uint64_t n_sweeps, int64_t *E_out, int64_t *E_log,
-               int64_t *Q_log, uint64_t *pt_accepts) {
+               int64_t *Q_log, uint64_t *pt_accepts, int64_t *M_out) {
   if (!sp || !valid_L(sp->L) || sp->n_samples < 1 || sp->n_replicas < 1 || sp->n_temps < 1)
     return OR_EINVAL;
-  if (sp->model != OR_ISING && sp->model != OR_POTTS && sp->model != OR_GPOTTS) return OR_EINVAL;
-  if (sp->model != OR_ISING && sp->algo != OR_HEATBATH) return OR_EINVAL;
+  if (sp->model < OR_ISING || sp->model > OR_ISING_GEN) return OR_EINVAL;
+  if ((sp->model == OR_POTTS || sp->model == OR_GPOTTS) && sp->algo != OR_HEATBATH) return OR_EINVAL;
+  if (sp->model == OR_ISING_GEN && (sp->pt_every > 0 || !(sp->field >= 0.0))) return OR_EINVAL;
   uint8_t *spins = (uint8_t *)spins_v;
   int64_t N = (int64_t)sp->L * sp->L * sp->L;
   int32_t NW = or_wheels_per_copy(sp->L);
@@ -466,10 +552,15 @@ int32_t or_run(const or_spec *sp, const double *betas, const int8_t *J, void *sp
   or_wheel *ptw = (or_wheel *)malloc(sizeof(or_wheel) * (chains > 0 ? chains : 1));
   int32_t *tos = (int32_t *)malloc(sizeof(int32_t) * C);
   int64_t *E = (int64_t *)malloc(sizeof(int64_t) * C);
+  int64_t *M = (int64_t *)malloc(sizeof(int64_t) * C);
   for (int64_t w = 0; w < C * NW; w++) or_wheel_load(&wheels[w], wheels_words + w * 61);
   if (sp->pt_every > 0)
     for (int64_t ch = 0; ch < chains; ch++) or_wheel_load(&ptw[ch], ptwheels_words + ch * 61);
-  for (int64_t c = 0; c < C; c++) E[c] = copy_energy(sp, spins + c * N, J + (c / K / sp->n_replicas) * 3 * N);
+  for (int64_t c = 0; c < C; c++) {
+    const int8_t *Jc = J + (c / K / sp->n_replicas) * coupling_rows(sp) * N;
+    E[c] = copy_energy(sp, spins + c * N, Jc);
+    M[c] = copy_field_sum(sp, spins + c * N, Jc);
+  }
 
   int32_t rc = OR_OK;
   uint64_t t = 0, n_meas = 0;
@@ -485,7 +576,7 @@ int32_t or_run(const or_spec *sp, const double *betas, const int8_t *J, void *sp
     }
     for (int64_t ch = 0; ch < chains; ch++)
       for (int k = 0; k < K; k++) tos[ch * K + slot_of_temp[ch * K + k]] = k;
-    rc = sweep_all(sp, betas, J, spins, wheels, tos, E, nsw);
+    rc = sweep_all(sp, betas, J, spins, wheels, tos, E, M, nsw);
     if (rc != OR_OK) break;
     t += nsw;
     if (sp->pt_every > 0 && (sweeps_done + t) % sp->pt_every == 0)
@@ -500,6 +591,8 @@ int32_t or_run(const or_spec *sp, const double *betas, const int8_t *J, void *sp
   if (sp->pt_every > 0)
     for (int64_t ch = 0; ch < chains; ch++) or_wheel_store(&ptw[ch], ptwheels_words + ch * 61);
   if (E_out) memcpy(E_out, E, sizeof(int64_t) * C);
+  if (M_out) memcpy(M_out, M, sizeof(int64_t) * C);
+  free(M);
   free(wheels);
   free(ptw);
   free(tos);

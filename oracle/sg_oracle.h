@@ -21,6 +21,9 @@
  *   Parisi-Rapuano generator, Eq. (5)                       (sec. 3.3)
  *   parallel tempering, named as an add-on                  (sec. 2.2)
  *   Eq. (3)  glassy Potts model with permutation couplings  (sec. 2.1)
+ *   Eq. (2)  Ising-like models with dilution x_i and field h_i, e.g. the
+ *            random-field Ising model (RFIM) and the diluted antiferromagnet
+ *            in a field (DAFF)                               (sec. 2.1)
  * Two Potts models: the +-J glass H = -sum J_ij delta(s_i, s_j) (OR_POTTS)
  * and the glassy model of Eq. (3), H = -sum_<ij> delta(s_i, pi_ij(s_j))
  * (OR_GPOTTS).  For the latter the bond between i and j = i + e_d is stored
@@ -36,7 +39,7 @@
 extern "C" {
 #endif
 
-enum { OR_ISING = 0, OR_POTTS = 1, OR_GPOTTS = 2 };
+enum { OR_ISING = 0, OR_POTTS = 1, OR_GPOTTS = 2, OR_ISING_GEN = 3 };
 enum { OR_METROPOLIS = 0, OR_HEATBATH = 1 };
 
 /* Errors returned by or_run. */
@@ -87,6 +90,20 @@ int32_t or_gpotts_update_site(int32_t L, uint8_t *s, const uint8_t *P, int64_t i
  * number of bonds of i whose term is 1 when s_i = a). */
 void or_gpotts_fields(int32_t L, const uint8_t *s, const uint8_t *P, int64_t i, int32_t h[4]);
 
+/* General Ising-like model of Eq. (2): D = [5][N] int8, rows J_x, J_y, J_z
+ * (+-1, J[d][i] joins i and i + e_d), x (0 = empty site, 1 = spin) and f
+ * (field sign +-1, h_i = field * f_i).  Empty sites are visited (and consume
+ * their number) but never change.  Returns the change of the bond energy
+ * E_b; *dM receives the change of M = sum_i x_i f_i s_i. */
+int32_t or_isinggen_update_site(int32_t L, int32_t algo, int8_t *s, const int8_t *D, double field,
+                                double beta, int64_t i, uint32_t r, int64_t *dM);
+/* Bond energy E_b = -sum_<ij> J_ij x_i x_j s_i s_j and field sum
+ * M = sum_i x_i f_i s_i; H = E_b - field * M. */
+int64_t or_isinggen_bond_energy(int32_t L, const int8_t *s, const int8_t *D);
+int64_t or_isinggen_field_sum(int32_t L, const int8_t *s, const int8_t *D);
+/* Overlap over occupied sites, sum_i x_i s^a_i s^b_i. */
+int64_t or_isinggen_overlap(int32_t L, const int8_t *a, const int8_t *b, const int8_t *D);
+
 /* Energies and overlaps, by direct summation over the 3N bonds / N sites. */
 int64_t or_ising_energy(int32_t L, const int8_t *s, const int8_t *J);
 int64_t or_potts_energy(int32_t L, const uint8_t *s, const int8_t *J);
@@ -98,7 +115,7 @@ int64_t or_potts_overlap(int32_t L, const uint8_t *a, const uint8_t *b);
 int32_t or_wheels_per_copy(int32_t L);
 
 typedef struct {
-  int32_t model;          /* OR_ISING, OR_POTTS or OR_GPOTTS (q = 4)             */
+  int32_t model;          /* OR_ISING, OR_POTTS, OR_GPOTTS (q = 4), OR_ISING_GEN */
   int32_t algo;           /* OR_METROPOLIS or OR_HEATBATH (Potts: heat bath)     */
   int32_t L;              /* even side; 2, 4 or a multiple of 8                  */
   int32_t n_samples;      /* S disorder samples                                  */
@@ -108,19 +125,23 @@ typedef struct {
   int32_t measure_every;  /* sweeps between logged measurements, 0 = none        */
   int32_t check_energy;   /* 1: tracked energy == recomputed energy every sweep  */
   int32_t n_threads;      /* worker threads over copies (<= 0: one)              */
+  double field;           /* OR_ISING_GEN: |h| (h_i = field * f_i); else unused  */
 } or_spec;
 
 /*
  * Run n_sweeps sweeps of every copy.  Copy (slot) c = (s R + r) K + k.
  *   betas         [K]            inverse temperatures, by temperature index
- *   J             [S][3][N]      int8 +-1 (glassy Potts: permutation bytes)
+ *   J             [S][3][N]      int8 +-1 (glassy Potts: permutation bytes;
+ *                                OR_ISING_GEN: [S][5][N], see above)
  *   spins         [C][N]         int8 +-1 (Ising) or uint8 0..3 (Potts), in/out
  *   wheels        [C][NW][61]    oldest first, in/out
  *   ptwheels      [S R][61]      one wheel per chain, in/out (unused if no PT)
  *   slot_of_temp  [S R][K]       slot holding temperature k, in/out
  *   sweeps_done   sweeps already performed (PT after sweeps that are
  *                 multiples of pt_every, counted from the start of the run)
- *   E_out         [C]            final energy of every slot
+ *   E_out         [C]            final energy of every slot (OR_ISING_GEN: E_b)
+ *   M_out         [C]            OR_ISING_GEN: final field sum M of every slot
+ *                                (may be NULL)
  *   E_log         [n_meas][S R][K] energy at each measurement, by chain and
  *                                temperature index (the slot holding it)
  *   Q_log         [n_meas][S][K] replica-0 / replica-1 overlap per
@@ -129,11 +150,13 @@ typedef struct {
  *   pt_accepts    [S R][K-1]     accepted swaps per pair, accumulated
  * Measurements are taken after sweeps measure_every, 2 measure_every, ... of
  * this call, after any parallel-tempering step due at the same sweep.
+ * OR_ISING_GEN runs without parallel tempering (its energy is not an integer
+ * for a non-integer field); its overlap counts occupied sites only.
  */
 int32_t or_run(const or_spec *sp, const double *betas, const int8_t *J, void *spins,
                uint32_t *wheels, uint32_t *ptwheels, int32_t *slot_of_temp,
                uint64_t sweeps_done, uint64_t n_sweeps, int64_t *E_out,
-               int64_t *E_log, int64_t *Q_log, uint64_t *pt_accepts);
+               int64_t *E_log, int64_t *Q_log, uint64_t *pt_accepts, int64_t *M_out);
 
 #ifdef __cplusplus
 }

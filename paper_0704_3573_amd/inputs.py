@@ -20,6 +20,11 @@ Encodings (canonical, host side):
     bond joining i and i + e_d holds the permutation pi of its term
     delta(s_i, pi(s_{i+e_d})) as its images, pi(v) = (byte >> 2v) & 3; element
     n is permutation number (stream output n mod 24) in lexicographic order;
+  * Ising-like models of Eq. 2 (dilution x_i, field h_i = |h| f_i): int8
+    [5][N], rows J_x, J_y, J_z, x, f.  "rfim": J = +1, x = 1, f iid +-1;
+    "daff": J = -1, x iid in {0, 1} (p = 1/2), f = +1; "isinggen": J, x and
+    f all iid (+-1, {0, 1}, +-1).  x and f use the bit rule of the couplings
+    (bit 1 -> x = 0, f = -1) on streams of their own;
   * Ising spins: int8 +-1, same bit rule;  Potts spins: uint8 0..3, two bits
     per site (bits 2k, 2k+1 of the stream word, little end first);
   * wheel seeds: 61 uint32 words per wheel, oldest first, I(-61) .. I(-1),
@@ -39,6 +44,8 @@ TAG_S = 0x53  # 'S' initial spins
 TAG_W = 0x57  # 'W' sweep wheels
 TAG_P = 0x50  # 'P' parallel-tempering wheels
 TAG_Q = 0x51  # 'Q' glassy-Potts permutation couplings
+TAG_X = 0x58  # 'X' dilution
+TAG_F = 0x46  # 'F' field signs
 
 
 def mix64(z):
@@ -96,6 +103,24 @@ def glassy_couplings(seed: int, sample: int, L: int) -> np.ndarray:
     return permutation_bytes()[u.astype(np.int64)].reshape(3, n)
 
 
+def ising_like_couplings(kind: str, seed: int, sample: int, L: int) -> np.ndarray:
+    """int8 [5][L^3]: J_x, J_y, J_z, x, f of one sample of an Ising-like
+    model of Eq. 2 ("rfim", "daff" or "isinggen")."""
+    n = L ** 3
+    out = np.empty((5, n), np.int8)
+    bx = _bits(stream_key(seed, TAG_X, sample), n).astype(np.int8)
+    bf = _bits(stream_key(seed, TAG_F, sample), n).astype(np.int8)
+    if kind == "rfim":
+        out[:3], out[3], out[4] = 1, 1, 1 - 2 * bf
+    elif kind == "daff":
+        out[:3], out[3], out[4] = -1, 1 - bx, 1
+    elif kind == "isinggen":
+        out[:3], out[3], out[4] = couplings(seed, sample, L), 1 - bx, 1 - 2 * bf
+    else:
+        raise ValueError(kind)
+    return out
+
+
 def ising_spins(seed: int, copies, L: int) -> np.ndarray:
     """int8 [len(copies)][L^3] iid +-1 initial spins."""
     copies = np.atleast_1d(np.asarray(copies, dtype=np.uint64))
@@ -145,7 +170,8 @@ def wheels_per_copy(L: int) -> int:
 def make_instance(model: str, L: int, n_samples: int, n_replicas: int,
                   n_temps: int, seed: int, sample0: int = 0):
     """All inputs of one job: couplings, spins, sweep wheels, PT wheels.
-    model: "ising", "potts" (+-J Potts glass) or "gpotts" (glassy Potts).
+    model: "ising", "potts" (+-J Potts glass), "gpotts" (glassy Potts), or an
+    Ising-like model of Eq. 2: "rfim", "daff", "isinggen" (J is then [S][5][N]).
 
     Copy (slot) c = (s * R + r) * K + k for sample s, replica r, slot k.
     Samples are numbered from `sample0` so that one large campaign can be
@@ -153,10 +179,16 @@ def make_instance(model: str, L: int, n_samples: int, n_replicas: int,
     """
     S, R, K = n_samples, n_replicas, n_temps
     C = S * R * K
-    make_J = glassy_couplings if model == "gpotts" else couplings
+    if model == "gpotts":
+        make_J = glassy_couplings
+    elif model in ("rfim", "daff", "isinggen"):
+        def make_J(seed, sample, L):
+            return ising_like_couplings(model, seed, sample, L)
+    else:
+        make_J = couplings
     J = np.stack([make_J(seed, sample0 + s, L) for s in range(S)])
     glob = np.arange(C, dtype=np.uint64) + np.uint64(sample0 * R * K)
-    if model == "ising":
+    if model in ("ising", "rfim", "daff", "isinggen"):
         sp = ising_spins(seed, glob, L)
     elif model in ("potts", "gpotts"):
         sp = potts_spins(seed, glob, L)
