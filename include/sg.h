@@ -5,8 +5,10 @@
  * Method: Belletti et al., "Simulating spin systems on IANUS, an FPGA-based
  * computer" (arXiv 0704.3573).  Single-spin Metropolis and heat-bath dynamics
  * (sec. 2.2, Eq. 4) of the 3D Edwards-Anderson +-J Ising glass (Eq. 2 with
- * x = 1, h = 0, sec. 2.1) and of the q = 4 +-J Potts glass
- * H = -sum J_ij delta(s_i, s_j), updated colour by colour on the bipartite
+ * x = 1, h = 0, sec. 2.1), of the Ising-like models of Eq. 2 with dilution
+ * and field (random-field Ising model, diluted antiferromagnet in a field),
+ * of the q = 4 +-J Potts glass H = -sum J_ij delta(s_i, s_j) and of the
+ * glassy Potts model of Eq. 3, updated colour by colour on the bipartite
  * lattice (sec. 3.1), every site update consuming one Parisi-Rapuano number
  * (sec. 3.3, Eq. 5) compared with an integer threshold.  Parallel tempering,
  * which sec. 2.2 names as an add-on, swaps temperatures between slots.
@@ -60,6 +62,13 @@ extern "C" {
 #define SG_ISING 0
 #define SG_POTTS 1  /* q = 4 +-J Potts glass, H = -sum J_ij delta(s_i, s_j)          */
 #define SG_GPOTTS 2 /* q = 4 glassy Potts model of Eq. (3), permutation couplings */
+/* Ising-like model of Eq. (2): H = -sum_<ij> J_ij x_i x_j s_i s_j
+ * - sum_i h_i x_i s_i with dilution x_i in {0, 1} and field h_i = field * f_i,
+ * f_i = +-1 (RFIM: J = +1, x = 1; DAFF: J = -1, f = +1).  The energy the
+ * library reports for it is the bond part E_b (first sum); the field sum
+ * M = sum_i x_i f_i s_i comes from sg_job_field_sums, and H = E_b - field * M.
+ * Overlaps count occupied sites only.  No parallel tempering. */
+#define SG_ISING_GEN 3
 #define SG_METROPOLIS 0
 #define SG_HEATBATH 1
 
@@ -68,7 +77,7 @@ typedef struct sg_job sg_job;
 typedef struct sg_batch sg_batch;
 
 typedef struct sg_job_spec {
-  int32_t model;      /* SG_ISING, SG_POTTS or SG_GPOTTS                       */
+  int32_t model;      /* SG_ISING, SG_POTTS, SG_GPOTTS or SG_ISING_GEN         */
   int32_t algo;       /* SG_METROPOLIS or SG_HEATBATH (Potts models: heat bath) */
   int32_t q;          /* Potts states, must be 4 (ignored for Ising)            */
   int32_t L;          /* 2, 4, 8, 16, 24, 32, 40, 48, 56, 64 (Potts: <= 48)     */
@@ -76,6 +85,7 @@ typedef struct sg_job_spec {
   int32_t n_replicas; /* R >= 1 (overlaps need R >= 2)                          */
   int32_t n_temps;    /* K >= 1                                                 */
   int32_t pt_every;   /* sweeps between parallel-tempering steps, 0 = none      */
+  double field;       /* SG_ISING_GEN: |h| >= 0, finite; ignored otherwise       */
 } sg_job_spec;
 
 /* Message of the last error on this thread ("" if none). */
@@ -99,7 +109,10 @@ int sg_job_bytes(const sg_job_spec *spec, uint64_t *bytes);
  *                 +-J Potts); for SG_GPOTTS the bytes are read as uint8
  *                 permutations pi of (0, 1, 2, 3), the bond's term being
  *                 delta(s_i, pi(s_{i+e_d})) with pi(v) = (byte >> 2v) & 3;
- *   spins         [C][N] int8 +-1 (Ising) or uint8 0..3 (Potts models);
+ *                 for SG_ISING_GEN [S][5][N] int8: rows J_x, J_y, J_z (+-1),
+ *                 x (0 = empty site, 1 = spin) and f (+-1);
+ *   spins         [C][N] int8 +-1 (Ising models) or uint8 0..3 (Potts models);
+ *                 an empty site keeps its spin (and still consumes its number);
  *   wheels        [C][NW][61];      ptwheels [S*R][61] (may be NULL if
  *                 pt_every == 0);
  *   slot_of_temp  [S*R][K] or NULL (identity);
@@ -129,6 +142,11 @@ int sg_job_measure(sg_job *job, int64_t *E, int64_t *Q, void *stream);
 /* Energy of every slot (copy order), as left by the last sweep or measure. (sync) */
 int sg_job_energies(sg_job *job, int64_t *E_slot, void *stream);
 
+/* SG_ISING_GEN (Eq. 2): field sum M = sum_i x_i f_i s_i of every copy by
+ * chain and temperature index, M[(s*R + r)*K + k], recomputed from the
+ * current spins; SG_E_STATE for other models. (sync) */
+int sg_job_field_sums(sg_job *job, int64_t *M, void *stream);
+
 /* Canonical export of the state. (sync) */
 int sg_job_get_spins(sg_job *job, void *spins_out /* [C][N] */, void *stream);
 int sg_job_get_wheels(sg_job *job, uint32_t *wheels_out /* [C][NW][61] */,
@@ -156,8 +174,8 @@ int sg_batch_create(sg_ctx *ctx, sg_batch **out);
 int sg_batch_add(sg_batch *b, sg_job *job);
 int sg_batch_remove(sg_batch *b, sg_job *job);
 /* Threads per workgroup of the fused launch (multiple of 64, <= 1024;
- * 0 = automatic); the Potts launch uses min(threads, 512).  Results do not
- * depend on it. */
+ * 0 = automatic); the Potts and Ising-like launches use min(threads, 512).
+ * Results do not depend on it. */
 int sg_batch_set_block(sg_batch *b, int32_t threads);
 /* Remaining sweep budget of a job in the batch: a run of n sweeps advances
  * the job by min(n, budget) and lowers the budget by that much

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsg.so")
 
 ISING, POTTS, GPOTTS = 0, 1, 2  # GPOTTS: glassy Potts model (permutation couplings)
+ISING_GEN = 3  # Ising-like model of Eq. 2 with dilution and field (RFIM, DAFF)
 METROPOLIS, HEATBATH = 0, 1
 
 SG_OK, SG_E_INVALID, SG_E_UNSUPPORTED, SG_E_NOMEM, SG_E_HIP, SG_E_STATE = 0, -1, -2, -3, -4, -5
@@ -24,7 +25,7 @@ SG_OK, SG_E_INVALID, SG_E_UNSUPPORTED, SG_E_NOMEM, SG_E_HIP, SG_E_STATE = 0, -1,
 EXPORTS = (
     "sg_last_error", "sg_wheels_per_copy", "sg_ctx_create", "sg_ctx_destroy", "sg_job_bytes",
     "sg_job_create", "sg_job_set_betas", "sg_job_sweep", "sg_job_measure", "sg_job_energies",
-    "sg_job_get_spins", "sg_job_get_wheels", "sg_job_get_perm", "sg_job_get_pt_accepts",
+    "sg_job_field_sums", "sg_job_get_spins", "sg_job_get_wheels", "sg_job_get_perm", "sg_job_get_pt_accepts",
     "sg_job_sweeps_done", "sg_job_debug_rng", "sg_job_destroy", "sg_batch_create",
     "sg_batch_add", "sg_batch_remove", "sg_batch_set_block", "sg_batch_run", "sg_batch_block",
     "sg_batch_set_timing", "sg_batch_sweep_ms", "sg_batch_set_budget", "sg_batch_get_budget",
@@ -40,7 +41,8 @@ class SgError(RuntimeError):
 
 class Spec(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
-        "model", "algo", "q", "L", "n_samples", "n_replicas", "n_temps", "pt_every")]
+        "model", "algo", "q", "L", "n_samples", "n_replicas", "n_temps", "pt_every")] + [
+        ("field", C.c_double)]
 
 
 _lib = None
@@ -66,6 +68,7 @@ def lib():
         L.sg_job_sweep.argtypes = [vp, u64, vp]
         L.sg_job_measure.argtypes = [vp, vp, vp, vp]
         L.sg_job_energies.argtypes = [vp, vp, vp]
+        L.sg_job_field_sums.argtypes = [vp, vp, vp]
         L.sg_job_get_spins.argtypes = [vp, vp, vp]
         L.sg_job_get_wheels.argtypes = [vp, vp, vp, vp]
         L.sg_job_get_perm.argtypes = [vp, vp, vp]
@@ -144,11 +147,11 @@ class Job:
 
     def __init__(self, ctx: Context, model, algo, L, betas, J, spins, wheels, ptwheels=None,
                  *, n_samples=1, n_replicas=1, pt_every=0, slot_of_temp=None, sweeps_done=0,
-                 stream=None, arena=None):
+                 stream=None, arena=None, field=0.0):
         import torch
         betas = np.ascontiguousarray(betas, dtype=np.float64)
         K = betas.shape[0]
-        self.spec = Spec(model, algo, 4, L, n_samples, n_replicas, K, pt_every)
+        self.spec = Spec(model, algo, 4, L, n_samples, n_replicas, K, pt_every, float(field))
         self.model, self.algo, self.L = model, algo, L
         self.S, self.R, self.K = n_samples, n_replicas, K
         self.C = n_samples * n_replicas * K
@@ -158,11 +161,14 @@ class Job:
         if arena is None:
             arena = torch.empty(self.bytes, dtype=torch.uint8, device=f"cuda:{ctx.device}")
         self.arena = arena
-        # +-1 couplings as int8; glassy-Potts permutation bytes as uint8 (same width)
+        # +-1 couplings as int8; glassy-Potts permutation bytes as uint8 (same
+        # width); Ising-like models: rows J_x, J_y, J_z, x, f
+        self.ising_spins = model in (ISING, ISING_GEN)
         J = np.ascontiguousarray(J, dtype=np.uint8 if model == GPOTTS else np.int8)
-        spins = np.ascontiguousarray(spins, dtype=np.int8 if model == ISING else np.uint8)
+        spins = np.ascontiguousarray(spins, dtype=np.int8 if self.ising_spins else np.uint8)
         wheels = np.ascontiguousarray(wheels, dtype=np.uint32)
-        assert J.size == self.S * 3 * self.N and spins.size == self.C * self.N
+        rows = 5 if model == ISING_GEN else 3
+        assert J.size == self.S * rows * self.N and spins.size == self.C * self.N
         assert wheels.size == self.C * self.NW * 61
         pw = None if ptwheels is None else np.ascontiguousarray(ptwheels, dtype=np.uint32)
         if pw is not None:
@@ -205,8 +211,13 @@ class Job:
         _chk(lib().sg_job_energies(self.h, _ptr(E), _stream(stream)))
         return E
 
+    def field_sums(self, stream=None):
+        M = np.zeros(self.C, dtype=np.int64)
+        _chk(lib().sg_job_field_sums(self.h, _ptr(M), _stream(stream)))
+        return M
+
     def spins(self, stream=None):
-        out = np.zeros((self.C, self.N), dtype=np.int8 if self.model == ISING else np.uint8)
+        out = np.zeros((self.C, self.N), dtype=np.int8 if self.ising_spins else np.uint8)
         _chk(lib().sg_job_get_spins(self.h, _ptr(out), _stream(stream)))
         return out
 

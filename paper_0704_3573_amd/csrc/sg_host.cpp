@@ -22,7 +22,8 @@ hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, in
                         int nsweeps, hipStream_t st);
 hipError_t set_max_lds(int bytes);
 hipError_t launch_overlap(const uint32_t *spins, const int32_t *slot_of_temp, int64_t *Q, int model,
-                          int L, int S, int R, int K, int copy_words, hipStream_t st);
+                          int L, int S, int R, int K, int copy_words, const uint32_t *occ,
+                          uint32_t occ_stride, hipStream_t st);
 hipError_t launch_pt(const int64_t *E, int32_t *slot_of_temp, int32_t *temp_of_slot, uint32_t *ptw,
                      const uint64_t *F, const int32_t *sgn, uint64_t *accepts, int chains, int K,
                      hipStream_t st);
@@ -73,6 +74,45 @@ static hipStream_t S_(void *s) { return (hipStream_t)s; }
 // Thresholds of a number r in [0, 2^32): accepted when r < T, probability T / 2^32.
 static uint64_t scaled_floor(double p, int bits) { return (uint64_t)std::floor(std::ldexp(p, bits)); }
 
+// Ising-like models of Eq. 2: thresholds of the classes (k, phi), k = 0..12
+// (see sg_layout.h), and the limits of the certain classes.  Metropolis: a
+// flip of a site with s_i sum_j J x_j s_j = k - 6 changes the energy by
+// dE = 2 (k - 6) + 2 field s_i f_i, phi = [s_i f_i = -1]; accepted when
+// r < floor(2^32 min(1, exp(-beta dE))).  Heat bath: local field
+// k - 6 + field f_i, phi = [f_i = -1]; s = +1 when r < floor(2^32 / (1 +
+// exp(-2 beta h))).  The certain classes (threshold 2^32) must form a prefix
+// (Metropolis) or a suffix (heat bath) of k = 0..12.
+static int gen_threshold_row(int algo, double beta, double field, uint32_t row[sg::THR_WORDS]) {
+  std::memset(row, 0, sizeof(uint32_t) * sg::THR_WORDS);
+  for (int phi = 0; phi < 2; phi++) {
+    uint64_t T[13];
+    for (int k = 0; k < 13; k++) {
+      const double c = (double)(k - 6);
+      if (algo == SG_METROPOLIS) {
+        const double dE = 2.0 * c + 2.0 * field * (phi ? -1.0 : 1.0);
+        T[k] = dE <= 0.0 ? (1ull << 32) : scaled_floor(std::exp(-beta * dE), 32);
+      } else {
+        const double h = c + field * (phi ? -1.0 : 1.0);
+        T[k] = scaled_floor(1.0 / (1.0 + std::exp(-2.0 * beta * h)), 32);
+      }
+    }
+    int lim = 0;
+    if (algo == SG_METROPOLIS) {
+      while (lim < 13 && T[lim] >= (1ull << 32)) lim++;
+      for (int k = lim; k < 13; k++)
+        if (T[k] >= (1ull << 32)) return fail(SG_E_UNSUPPORTED, "non-monotone thresholds");
+    } else {
+      lim = 13;
+      while (lim > 0 && T[lim - 1] >= (1ull << 32)) lim--;
+      for (int k = 0; k < lim; k++)
+        if (T[k] >= (1ull << 32)) return fail(SG_E_UNSUPPORTED, "non-monotone thresholds");
+    }
+    for (int k = 0; k < 13; k++) row[16 * phi + k] = T[k] >= (1ull << 32) ? 0u : (uint32_t)T[k];
+    row[16 * phi + 13] = (uint32_t)lim;
+  }
+  return SG_OK;
+}
+
 // Row of THR_WORDS words for one temperature (see sg_layout.h).
 static void threshold_row(int model, int algo, double beta, uint32_t row[sg::THR_WORDS]) {
   std::memset(row, 0, sizeof(uint32_t) * sg::THR_WORDS);
@@ -114,22 +154,30 @@ struct sg_ctx {
 
 // ------------------------------------------------------------------- job --
 struct Layout {
-  uint64_t spins, J, wheels, ptw, tos, sot, thr, F, sgn, E, Q, acc, done, dbg, works, ptworks, total;
+  uint64_t spins, J, wheels, ptw, tos, sot, thr, F, sgn, E, Q, acc, done, Mf, dbg, works, ptworks, total;
   uint64_t spins_bytes, J_bytes, wheels_bytes;
 };
 
 static uint64_t al(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
+static bool is_potts(int model) { return model == SG_POTTS || model == SG_GPOTTS; }
+
 static int check_spec(const sg_job_spec *sp) {
   if (!sp) return fail(SG_E_INVALID, "spec is NULL");
-  if (sp->model != SG_ISING && sp->model != SG_POTTS && sp->model != SG_GPOTTS)
+  if (sp->model != SG_ISING && sp->model != SG_POTTS && sp->model != SG_GPOTTS && sp->model != SG_ISING_GEN)
     return fail(SG_E_INVALID, "bad model %d", sp->model);
   if (sp->algo != SG_METROPOLIS && sp->algo != SG_HEATBATH) return fail(SG_E_INVALID, "bad algo %d", sp->algo);
-  if (sp->model != SG_ISING && sp->algo != SG_HEATBATH)
+  if (is_potts(sp->model) && sp->algo != SG_HEATBATH)
     return fail(SG_E_UNSUPPORTED, "the Potts models are built for heat bath only");
-  if (sp->model != SG_ISING && sp->q != 4) return fail(SG_E_UNSUPPORTED, "Potts q must be 4");
+  if (is_potts(sp->model) && sp->q != 4) return fail(SG_E_UNSUPPORTED, "Potts q must be 4");
+  if (sp->model == SG_ISING_GEN) {
+    if (!(sp->field >= 0.0) || std::isinf(sp->field))
+      return fail(SG_E_INVALID, "field must be finite and >= 0");
+    if (sp->pt_every > 0 && sp->n_temps > 1)
+      return fail(SG_E_UNSUPPORTED, "no parallel tempering for the Ising-like models");
+  }
   if (!sg::supported_L(sp->L)) return fail(SG_E_UNSUPPORTED, "L = %d is not built", sp->L);
-  if (sp->model != SG_ISING && !sg::potts_supported_L(sp->L))
+  if (is_potts(sp->model) && !sg::potts_supported_L(sp->L))
     return fail(SG_E_UNSUPPORTED, "Potts L = %d is not built (L <= 48)", sp->L);
   if (sp->n_samples < 1 || sp->n_replicas < 1 || sp->n_temps < 1)
     return fail(SG_E_INVALID, "S, R, K must be >= 1");
@@ -146,11 +194,12 @@ static Layout layout(const sg_job_spec *sp) {
   const uint64_t K1 = K > 1 ? K - 1 : 1;
   Layout l{};
   uint64_t o = 0;
-  l.spins_bytes = sp->model == SG_ISING ? C * g.CS * 4 : C * N;
+  l.spins_bytes = is_potts(sp->model) ? C * N : C * g.CS * 4;
   l.J_bytes = S * 4 *
-              (uint64_t)(sp->model == SG_ISING  ? sg::ising_js(sp->L)
-                         : sp->model == SG_POTTS ? sg::potts_js(sp->L)
-                                                 : sg::gpotts_js(sp->L));
+              (uint64_t)(sp->model == SG_ISING       ? sg::ising_js(sp->L)
+                         : sp->model == SG_POTTS     ? sg::potts_js(sp->L)
+                         : sp->model == SG_ISING_GEN ? sg::gen_js(sp->L)
+                                                     : sg::gpotts_js(sp->L));
   l.wheels_bytes = (uint64_t)g.M * C * g.NW * 4;
   l.spins = o; o = al(o + l.spins_bytes);
   l.J = o; o = al(o + l.J_bytes);
@@ -165,6 +214,7 @@ static Layout layout(const sg_job_spec *sp) {
   l.Q = o; o = al(o + S * K * 8);
   l.acc = o; o = al(o + S * R * K1 * 8);
   l.done = o; o = al(o + 8);
+  l.Mf = o; o = al(o + C * 8);
   l.dbg = o; o = al(o + 4096 * 4);
   l.works = o; o = al(o + C * sizeof(Work));
   l.ptworks = o; o = al(o + ((S * R + 63) / 64) * sizeof(PtWork));
@@ -200,6 +250,9 @@ static size_t item_lds(const sg_job *j, int G) {
   // counters, and (when a wave can hold lanes without a wheel) the region
   // those lanes store into
   if (j->sp.model == SG_ISING) return (size_t)(G + 1) * j->g.CS * 4 + (size_t)G * 4;
+  // Ising-like: copies, per-copy threshold tables and two counters, scratch copy
+  if (j->sp.model == SG_ISING_GEN)
+    return (size_t)(G + 1) * j->g.CS * 4 + (size_t)G * (sg::GEN_TAB_STRIDE + 2) * 4;
   const size_t dummy = j->g.NW % 64 ? (size_t)j->g.RHO * j->L * j->L : 0;
   return (size_t)sg::POTTS_TAB_WORDS * 4 + (size_t)G * sg::potts_lds_copy(j->L) +
          (size_t)G * sg::POTTS_W_WORDS * 4 + (size_t)G * 4 + dummy;
@@ -238,6 +291,7 @@ static void make_items(const sg_job *j, int G, std::vector<Work> &out) {
     w.J_bytes = (uint32_t)j->lay.J_bytes;
     w.wheels_bytes = (uint32_t)j->lay.wheels_bytes;
     w.done = j->done_ptr();
+    w.M = j->sp.model == SG_ISING_GEN ? j->at<int64_t>(j->lay.Mf) : nullptr;
     out.push_back(w);
   }
 }
@@ -332,6 +386,44 @@ static void pack_ising_J(const Geom &g, const int8_t *J, uint32_t *out) {
           }
           out[((p * g.NWB + wb) * 6 + d) * L + z] = word;
         }
+}
+
+// Ising-like models: D = [5][N] rows J_x, J_y, J_z, x, f -> the 14 words of
+// every (colour, block-row, plane) and the occupancy words in the spin-copy
+// layout (see sg_layout.h)
+static void pack_gen_J(const Geom &g, const int8_t *D, uint32_t *out) {
+  const int L = g.L;
+  const uint64_t N = (uint64_t)L * L * L;
+  const int8_t *X = D + 3 * N, *F = D + 4 * N;
+  auto idx = [&](int x, int y, int z) {
+    return (uint64_t)((x + L) % L) + L * ((uint64_t)((y + L) % L) + (uint64_t)L * ((z + L) % L));
+  };
+  const int dx[6] = {1, -1, 0, 0, 0, 0}, dy[6] = {0, 0, 1, -1, 0, 0}, dz[6] = {0, 0, 0, 0, 1, -1};
+  for (int p = 0; p < 2; p++)
+    for (int wb = 0; wb < g.NWB; wb++)
+      for (int z = 0; z < L; z++) {
+        uint32_t w[sg::GEN_WORDS] = {};
+        for (int r = 0; r < g.RPB; r++) {
+          const int y = wb * g.RPB + r;
+          const int e = (p + y + z) & 1;
+          for (int j = 0; j < g.H; j++) {
+            const int x = 2 * j + e;
+            const uint32_t bit = 1u << (g.B - 1 - (r * g.H + j));
+            for (int d = 0; d < 6; d++) {
+              if (bond(D, L, x, y, z, d) < 0) w[d] |= bit;
+              if (X[idx(x + dx[d], y + dy[d], z + dz[d])]) w[6 + d] |= bit;
+            }
+            if (X[idx(x, y, z)]) w[12] |= bit;
+            if (F[idx(x, y, z)] < 0) w[13] |= bit;
+          }
+        }
+        for (int d = 0; d < sg::GEN_WORDS; d++)
+          out[((p * g.NWB + wb) * sg::GEN_WORDS + d) * L + z] = w[d];
+      }
+  // occupancy in the spin layout: a copy whose spins are all -1 where occupied
+  std::vector<int8_t> occ((size_t)N);
+  for (uint64_t i = 0; i < N; i++) occ[i] = X[i] ? -1 : 1;
+  pack_ising_spins(g, occ.data(), out + sg::gen_block_js(L));
 }
 
 // Potts: byte per site, order [y][x][z]
@@ -431,11 +523,19 @@ static void unpack_wheels(const sg_job *j, const uint32_t *in, uint64_t k0, uint
     }
 }
 
-static void tables_upload_host(const sg_job *j, std::vector<uint32_t> &thr, std::vector<uint64_t> &F,
-                               std::vector<int32_t> &sgn) {
+static int tables_upload_host(const sg_job *j, std::vector<uint32_t> &thr, std::vector<uint64_t> &F,
+                              std::vector<int32_t> &sgn) {
   const int K = j->K, K1 = K > 1 ? K - 1 : 1;
   thr.assign((size_t)K * sg::THR_WORDS, 0);
-  for (int k = 0; k < K; k++) threshold_row(j->sp.model, j->sp.algo, j->betas[k], &thr[(size_t)k * sg::THR_WORDS]);
+  for (int k = 0; k < K; k++) {
+    uint32_t *row = &thr[(size_t)k * sg::THR_WORDS];
+    if (j->sp.model == SG_ISING_GEN) {
+      const int rc = gen_threshold_row(j->sp.algo, j->betas[k], j->sp.field, row);
+      if (rc) return rc;
+    } else {
+      threshold_row(j->sp.model, j->sp.algo, j->betas[k], row);
+    }
+  }
   F.assign((size_t)K1 * 24, 0);
   sgn.assign((size_t)K1, 0);
   for (int i = 0; i + 1 < K; i++) {
@@ -444,13 +544,15 @@ static void tables_upload_host(const sg_job *j, std::vector<uint32_t> &thr, std:
     for (int b = 0; b < 24; b++)
       F[(size_t)i * 24 + b] = scaled_floor(std::exp(-std::fabs(db) * std::ldexp(1.0, b)), 32);
   }
+  return SG_OK;
 }
 
 static int upload_tables(sg_job *j, hipStream_t st) {
   std::vector<uint32_t> thr;
   std::vector<uint64_t> F;
   std::vector<int32_t> sgn;
-  tables_upload_host(j, thr, F, sgn);
+  const int rc = tables_upload_host(j, thr, F, sgn);
+  if (rc) return rc;
   HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.thr), thr.data(), thr.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.F), F.data(), F.size() * 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.sgn), sgn.data(), sgn.size() * 4, hipMemcpyHostToDevice, st));
@@ -539,11 +641,20 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
     const uint8_t *P = (const uint8_t *)J;
     for (uint64_t i = 0; i < S * 3 * N; i++)
       if (perm_num[P[i]] < 0) return fail(SG_E_INVALID, "coupling byte %u is not a permutation", P[i]);
+  } else if (spec->model == SG_ISING_GEN) {
+    for (uint64_t s = 0; s < S; s++)
+      for (uint64_t r = 0; r < 5; r++)
+        for (uint64_t i = 0; i < N; i++) {
+          const int8_t v = J[(s * 5 + r) * N + i];
+          if (r == 3 ? (v != 0 && v != 1) : (v != 1 && v != -1))
+            return fail(SG_E_INVALID, "row %d of the couplings must be %s", (int)r,
+                        r == 3 ? "0 or 1" : "+1 or -1");
+        }
   } else {
     for (uint64_t i = 0; i < S * 3 * N; i++)
       if (J[i] != 1 && J[i] != -1) return fail(SG_E_INVALID, "couplings must be +1 or -1");
   }
-  if (spec->model == SG_ISING) {
+  if (!is_potts(spec->model)) {
     const int8_t *s = (const int8_t *)spins;
     for (uint64_t i = 0; i < C * N; i++)
       if (s[i] != 1 && s[i] != -1) return fail(SG_E_INVALID, "Ising spins must be +1 or -1");
@@ -584,12 +695,15 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
 
   // pack on the host, upload
   std::vector<uint8_t> buf;
-  if (spec->model == SG_ISING) {
+  if (!is_potts(spec->model)) {
     std::vector<uint32_t> sp((size_t)C * j->g.CS);
     for (uint64_t c = 0; c < C; c++)
       pack_ising_spins(j->g, (const int8_t *)spins + c * N, &sp[c * j->g.CS]);
-    std::vector<uint32_t> jw((size_t)S * sg::ising_js(j->L));
-    for (uint64_t s = 0; s < S; s++) pack_ising_J(j->g, J + s * 3 * N, &jw[s * sg::ising_js(j->L)]);
+    std::vector<uint32_t> jw((size_t)lay.J_bytes / 4);
+    if (spec->model == SG_ISING)
+      for (uint64_t s = 0; s < S; s++) pack_ising_J(j->g, J + s * 3 * N, &jw[s * sg::ising_js(j->L)]);
+    else
+      for (uint64_t s = 0; s < S; s++) pack_gen_J(j->g, J + s * 5 * N, &jw[s * sg::gen_js(j->L)]);
     HIPCHK(hipMemcpy(j->at<void>(lay.spins), sp.data(), lay.spins_bytes, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(j->at<void>(lay.J), jw.data(), lay.J_bytes, hipMemcpyHostToDevice));
   } else {
@@ -711,10 +825,12 @@ int sg_job_measure(sg_job *job, int64_t *E, int64_t *Q, void *stream) {
   if (rc) return rc;
   if (Q) {
     if (job->R < 2) return fail(SG_E_STATE, "overlaps need at least two replicas");
-    const int cw = job->sp.model == SG_ISING ? job->g.CS : (int)(job->N / 4);
+    const int cw = is_potts(job->sp.model) ? (int)(job->N / 4) : job->g.CS;
+    const bool gen = job->sp.model == SG_ISING_GEN;
+    const uint32_t *occ = gen ? job->at<uint32_t>(job->lay.J) + sg::gen_block_js(job->L) : nullptr;
     HIPCHK(sg::launch_overlap(job->at<uint32_t>(job->lay.spins), job->at<int32_t>(job->lay.sot),
                               job->at<int64_t>(job->lay.Q), job->sp.model, job->L, job->S, job->R, job->K, cw,
-                              st));
+                              occ, gen ? (uint32_t)sg::gen_js(job->L) : 0u, st));
   }
   std::vector<int64_t> Es((size_t)job->C);
   std::vector<int32_t> sot((size_t)job->C);
@@ -739,6 +855,25 @@ int sg_job_energies(sg_job *job, int64_t *E_slot, void *stream) {
   return SG_OK;
 }
 
+int sg_job_field_sums(sg_job *job, int64_t *M, void *stream) {
+  GUARD_BEGIN
+  if (!job || !M) return fail(SG_E_INVALID, "NULL argument");
+  if (job->sp.model != SG_ISING_GEN) return fail(SG_E_STATE, "field sums exist for the Ising-like models only");
+  hipStream_t st = S_(stream);
+  int rc = launch_own(job, 0, st);  // recompute from the current spins
+  if (rc) return rc;
+  std::vector<int64_t> Ms((size_t)job->C);
+  std::vector<int32_t> sot((size_t)job->C);
+  HIPCHK(hipMemcpyAsync(Ms.data(), job->at<void>(job->lay.Mf), Ms.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(sot.data(), job->at<void>(job->lay.sot), sot.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int ch = 0; ch < job->chains; ch++)
+    for (int k = 0; k < job->K; k++)
+      M[(size_t)ch * job->K + k] = Ms[(size_t)ch * job->K + sot[(size_t)ch * job->K + k]];
+  return SG_OK;
+  GUARD_END
+}
+
 int sg_job_get_spins(sg_job *job, void *out, void *stream) {
   GUARD_BEGIN
   if (!job || !out) return fail(SG_E_INVALID, "NULL argument");
@@ -747,7 +882,7 @@ int sg_job_get_spins(sg_job *job, void *out, void *stream) {
   HIPCHK(hipMemcpyAsync(raw.data(), job->at<void>(job->lay.spins), raw.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (int c = 0; c < job->C; c++) {
-    if (job->sp.model == SG_ISING)
+    if (!is_potts(job->sp.model))
       unpack_ising_spins(job->g, (const uint32_t *)raw.data() + (size_t)c * job->g.CS, (int8_t *)out + (size_t)c * job->N);
     else
       unpack_potts_spins(job->L, raw.data() + (size_t)c * job->N, (uint8_t *)out + (size_t)c * job->N);
@@ -839,6 +974,9 @@ struct PtTable {
   int n, kmax;
 };
 
+// fused launches of a period: one per (model, algorithm)
+static const int NMODEL = 4, NGROUP = 2 * NMODEL;
+
 struct sg_batch {
   sg_ctx *ctx;
   std::vector<sg_job *> jobs;
@@ -848,8 +986,8 @@ struct sg_batch {
   // plan
   bool dirty = true;
   int tpb = 0;
-  size_t lds[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // per (model, algo) launch
-  std::vector<Work> items[3][2];  // [model][algo]
+  size_t lds[NMODEL][2] = {};  // per (model, algo) launch
+  std::vector<Work> items[NMODEL][2];  // [model][algo]
   Work *d_items = nullptr;
   size_t d_items_cap = 0;
   uint64_t **d_done = nullptr;
@@ -860,8 +998,8 @@ struct sg_batch {
   std::vector<void *> graph_bufs;  // device buffers referenced by captured graphs
   std::map<std::vector<int>, PtTable> pt_cache;
   hipStream_t cap_stream = nullptr;
-  hipStream_t side[3] = {nullptr, nullptr, nullptr};  // parallel branches while capturing
-  hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+  hipStream_t side[NGROUP - 1] = {};  // parallel branches while capturing
+  hipEvent_t fork = nullptr, join[NGROUP - 1] = {};
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the fused sweep launch
 };
@@ -908,7 +1046,7 @@ static int plan(sg_batch *b) {
     if (j->g.NW > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
   for (auto &a : b->items)
     for (auto &v : a) v.clear();
-  size_t lds[3][2] = {{0, 0}, {0, 0}, {0, 0}}, total = 0;
+  size_t lds[NMODEL][2] = {}, total = 0;
   for (sg_job *j : b->jobs) {
     const int G = copies_per_item(j, tpb);
     size_t &l = lds[j->sp.model][j->sp.algo];
@@ -954,7 +1092,7 @@ static int plan(sg_batch *b) {
   }
   b->run_cap.assign(b->jobs.size(), 0x7FFFFFFF);
   b->tpb = tpb;
-  for (int m = 0; m < 3; m++)
+  for (int m = 0; m < NMODEL; m++)
     for (int a = 0; a < 2; a++) b->lds[m][a] = lds[m][a];
   b->dirty = false;
   return SG_OK;
@@ -1011,7 +1149,7 @@ static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs,
   const bool fork = capturing && groups > 1;
   if (fork) HIPCHK(hipEventRecord(b->fork, st));
   int g = 0;
-  for (int m = 0; m < 3; m++)
+  for (int m = 0; m < NMODEL; m++)
     for (int a = 0; a < 2; a++) {
       const auto &v = b->items[m][a];
       if (!v.empty()) {
@@ -1075,7 +1213,7 @@ int sg_batch_create(sg_ctx *ctx, sg_batch **out) {
   b->ctx = ctx;
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-  for (int i = 0; i < 3; i++) {
+  for (int i = 0; i < NGROUP - 1; i++) {
     HIPCHK(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming));
   }
@@ -1240,7 +1378,7 @@ int sg_batch_destroy(sg_batch *b) {
   if (b->d_done) (void)hipFree(b->d_done);
   if (b->d_cap) (void)hipFree(b->d_cap);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  for (int i = 0; i < 3; i++) {
+  for (int i = 0; i < NGROUP - 1; i++) {
     if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
     if (b->join[i]) (void)hipEventDestroy(b->join[i]);
   }

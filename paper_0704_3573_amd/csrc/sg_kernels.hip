@@ -534,6 +534,286 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
 }
 
 // ---------------------------------------------------------------------------
+// Ising-like models of Eq. (2): H = -sum_<ij> J_ij x_i x_j s_i s_j
+// - sum_i h_i x_i s_i with h_i = |h| f_i (random-field Ising model, diluted
+// antiferromagnet in a field, and mixtures).  Copies, wheels and draw order
+// are those of the EA glass; a block's 14 coupling words add the occupancy
+// of the six neighbours, the site's own occupancy and its field sign to the
+// six J words.
+//
+// Class of a site: k = n_e + 2 n_g in 0..12, with n_e the number of empty
+// neighbours and n_g the number of occupied neighbours whose term is +1
+// (Metropolis: J s_i s_j = +1, so k - 6 = s_i sum_j J_ij x_j s_j and a flip
+// costs 2 (k - 6) + 2 h s_i f_i; heat bath: J s_j = +1, so the local field
+// is k - 6 + h f_i), and a sign bit phi (Metropolis: s_i f_i = -1; heat bath:
+// f_i = -1).  k is formed bit-sliced on whole words; each draw is then
+// compared with the threshold of its site's class, read from the copy's LDS
+// table at word k + 16 phi (the update cell of the paper likewise turns its
+// inputs into a small LUT index).  Thresholds are monotone in k, so the
+// classes whose move is certain (threshold 2^32) are k < m_phi (Metropolis)
+// or k >= m_phi (heat bath): a bit-sliced compare with two per-temperature
+// limits, which leaves 32-bit table entries.  Empty sites keep their spin
+// and still consume their number.
+// ---------------------------------------------------------------------------
+
+// k = a < m for bit-sliced 4-bit a and a per-lane constant m given as four
+// all-zero / all-one masks.
+DEV uint32_t lt4(const uint32_t a[4], const uint32_t m[4]) {
+  uint32_t t = ~a[0] & m[0];
+#pragma unroll
+  for (int b = 1; b < 4; b++) t = bfi(a[b] ^ m[b], m[b], t);
+  return t;
+}
+
+// Class planes P[0..3] = k, P[4] = phi of the sites of one block word.
+template <bool MET>
+DEV void gen_classify(uint32_t S, const uint32_t N[6], const uint32_t Jw[GEN_WORDS],
+                      uint32_t P[5]) {
+  uint32_t gd[6], ed[6];
+#pragma unroll
+  for (int d = 0; d < 6; d++) {
+    const uint32_t u = MET ? (S ^ N[d] ^ Jw[d]) : (N[d] ^ Jw[d]);  // 1: term -1
+    gd[d] = bfi(u, 0u, Jw[6 + d]);                                 // occupied, term +1
+    ed[d] = ~Jw[6 + d];                                            // empty
+  }
+  uint32_t g0, g1, g2, e0, e1, e2, c2;
+  count6(gd, g0, g1, g2);
+  count6(ed, e0, e1, e2);
+  // n_e + 2 n_g <= 12: bit 3 receives at most one carry
+  P[0] = e0;
+  P[1] = e1 ^ g0;
+  fadd(e2, g1, e1 & g0, P[2], c2);
+  P[3] = g2 | c2;
+  P[4] = MET ? (S ^ Jw[13]) : Jw[13];
+}
+
+// (a & m) | c with the mask in a scalar register (one instruction).
+DEV uint32_t and_or(uint32_t a, uint32_t m, uint32_t c) {
+  uint32_t r;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(m), "v"(c));
+  return r;
+}
+
+// base + byte n of x (one instruction; n is a compile-time constant).
+DEV uint32_t add_byte(int n, uint32_t base, uint32_t x) {
+  uint32_t r;
+  switch (n) {
+    case 0:
+      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+          : "=v"(r) : "v"(base), "v"(x));
+      break;
+    case 1:
+      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+          : "=v"(r) : "v"(base), "v"(x));
+      break;
+    case 2:
+      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+          : "=v"(r) : "v"(base), "v"(x));
+      break;
+    default:
+      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+          : "=v"(r) : "v"(base), "v"(x));
+      break;
+  }
+  return r;
+}
+
+// LDS words addressed by 32-bit byte offsets.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+DEV uint32_t lds_offset(const uint32_t *p) { return (uint32_t)(uintptr_t)(lds_u32 *)p; }
+
+// Single compare-result insert: acc = 2 acc + c (first: acc = c).
+DEV void ins1(bool first, uint64_t m, uint32_t &acc) {
+  if (first)
+    asm volatile("v_addc_co_u32 %[a], vcc, 0, 0, %[m]" : [a] "=&v"(acc) : [m] "s"(m) : "vcc");
+  else
+    asm volatile("v_addc_co_u32 %[a], vcc, %[a], %[a], %[m]" : [a] "+v"(acc) : [m] "s"(m) : "vcc");
+}
+
+template <int L, int ALGO>
+struct GenK {
+  using G = GC<L>;
+  static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK, NWB = G::NWB;
+  IsingLane ln;                // spins, couplings and position of the lane
+  const uint32_t *tab;         // LDS threshold table of the lane's copy
+  uint32_t m0[4], m1[4];       // limits of the certain classes (lane masks)
+  uint32_t nextJ[GEN_WORDS];   // coupling words of the next block
+
+  DEV void load(int p, int blk, uint32_t Jw[GEN_WORDS]) const {
+    const uint32_t voff = ln.joff + (uint32_t)(ln.g * NBLK * GEN_WORDS * L) * 4u;
+    const uint32_t s0 =
+        __builtin_amdgcn_readfirstlane((uint32_t)((p * NWB + blk) * GEN_WORDS * L) * 4u);
+#pragma unroll
+    for (int d = 0; d < GEN_WORDS; d++) Jw[d] = bload(ln.rJ, voff, s0 + d * L * 4);
+  }
+  DEV void fetch(int p, int blk) { load(p, blk, nextJ); }
+
+  template <int VI>
+  DEV void block(uint32_t (&ring)[M], int p, int blk) {
+    uint32_t Jw[GEN_WORDS];
+#pragma unroll
+    for (int d = 0; d < GEN_WORDS; d++) Jw[d] = nextJ[d];
+    if (blk + 1 < NBLK)
+      fetch(p, blk + 1);
+    else
+      fetch(p ^ 1, 0);
+    uint32_t S, N[6];
+    uint32_t *own;
+    ising_neighbours<L>(ln, p, blk, S, N, own);
+    uint32_t P[5];
+    gen_classify<ALGO == 0>(S, N, Jw, P);
+    const uint32_t lo = lt4(P, m0), hi = lt4(P, m1);
+    const uint32_t cert = ALGO == 0 ? bfi(P[4], hi, lo) : ~bfi(P[4], hi, lo);
+
+    // threshold of every site: the five class planes are transposed into
+    // bytes, byte j of word w holding 4 (k + 16 phi) of the site at bit
+    // q = w + 8 j, so each site's table address is one byte-select add
+    uint32_t Kw[8];
+#pragma unroll
+    for (int w = 0; w < 8; w++) {
+      Kw[w] = 0;
+#pragma unroll
+      for (int b = 0; b < 5; b++) {
+        const int sh = b + 2 - w;
+        const uint32_t v = sh >= 0 ? P[b] << sh : P[b] >> -sh;
+        Kw[w] = and_or(v, 0x01010101u << (b + 2), Kw[w]);
+      }
+    }
+    const uint32_t tbase = lds_offset(tab);
+    uint32_t T[B];
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+      const int q = B - 1 - i;  // bit of the i-th draw's site
+      T[i] = *(const lds_u32 *)(uintptr_t)add_byte(q >> 3, tbase, Kw[q & 7]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // draws: r = I(k) xor I(k-61), compare with the site's threshold, shift
+    // the result into acc; each compare mask is read three or more
+    // instructions after it was written (the last one after a wait)
+    static_assert(B >= 2, "the draw pipeline needs two draws per block");
+    uint32_t acc = 0, r;
+    uint64_t m[B];
+    auto s1 = [&](int i) {
+      const int k = VI * B + i;  // static after unrolling
+      met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
+             T[i], r, m[i]);
+    };
+    s1(0);
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+      if (i + 1 < B)
+        s1(i + 1);
+      else
+        asm volatile("s_nop 1");
+      ins1(i == 0, m[i], acc);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    const uint32_t X = Jw[12];
+    if constexpr (ALGO == 0)
+      *own = S ^ (X & (cert | acc));  // X is zero above the block's B bits
+    else
+      *own = bfi(X, ~(cert | acc), S) & G::MB;
+  }
+
+  // bond energy of the lane's colour-0 sites (every bond has one colour-0
+  // end: E_b = -sum over them of x_i (k_i - 6)) and field sum of all its sites
+  DEV void terms(int &Eb, int &Mf) const {
+    Eb = 0;
+    Mf = 0;
+    for (int p = 0; p < 2; p++)
+      for (int blk = 0; blk < NBLK; blk++) {
+        uint32_t Jw[GEN_WORDS], S, N[6], P[5];
+        uint32_t *own;
+        load(p, blk, Jw);
+        ising_neighbours<L>(ln, p, blk, S, N, own);
+        const uint32_t X = Jw[12];
+        Mf += __popc(X) - 2 * __popc((S ^ Jw[13]) & X);
+        if (p == 0) {
+          gen_classify<true>(S, N, Jw, P);
+          Eb -= __popc(P[0] & X) + 2 * __popc(P[1] & X) + 4 * __popc(P[2] & X) +
+                8 * __popc(P[3] & X) - 6 * __popc(X);
+        }
+      }
+  }
+};
+
+template <int L, int ALGO>
+DEV void gen_run(const Work &w, uint32_t *lds) {
+  using G = GC<L>;
+  const int t = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int lanes = w.ncopies * G::NW;
+  const bool active = t < lanes;
+  uint32_t *tabs = lds + w.ncopies * G::CS;                  // [ncopies][GEN_TAB_STRIDE]
+  int *Ecnt = (int *)(tabs + w.ncopies * GEN_TAB_STRIDE);    // [ncopies]
+  int *Mcnt = Ecnt + w.ncopies;                              // [ncopies]
+  uint32_t *scratch_copy = (uint32_t *)(Mcnt + w.ncopies);   // CS words
+  const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
+
+  const uint32_t sbase = (uint32_t)w.copy0 * G::CS * 4u;
+  for (int i = t; i < w.ncopies * G::CS; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
+  for (int i = t; i < w.ncopies * 32; i += nthr) {
+    const int c = i >> 5, e = i & 31;
+    tabs[c * GEN_TAB_STRIDE + e] = w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + e];
+  }
+  for (int i = t; i < 2 * w.ncopies; i += nthr) Ecnt[i] = 0;
+
+  // lanes without a wheel serve wheel (z = t mod L, row group 0) of the
+  // scratch copy with the first copy's table
+  GenK<L, ALGO> k;
+  IsingLane &ln = k.ln;
+  const int cl = active ? t / G::NW : 0;
+  const int wl = active ? t - cl * G::NW : t % L;
+  const int copy = w.copy0 + cl;
+  ln.sp = active ? lds + cl * G::CS : scratch_copy;
+  ln.g = wl / L;
+  ln.z = wl - ln.g * L;
+  ln.zp = ln.z + 1 == L ? 0 : ln.z + 1;
+  ln.zm = ln.z == 0 ? L - 1 : ln.z - 1;
+  ln.rJ = make_rsrc(w.J, w.J_bytes);
+  ln.joff = ((uint32_t)(copy / w.RK) * gen_js(L) + ln.z) * 4u;
+  k.tab = tabs + cl * GEN_TAB_STRIDE;
+  uint32_t lim0 = 0, lim1 = 0;
+  if (active) {
+    const uint32_t *tr = w.thr + w.temp_of_slot[copy] * THR_WORDS;
+    lim0 = tr[13];
+    lim1 = tr[29];
+  }
+#pragma unroll
+  for (int b = 0; b < 4; b++) {
+    k.m0[b] = (lim0 >> b) & 1u ? ~0u : 0u;
+    k.m1[b] = (lim1 >> b) & 1u ? ~0u : 0u;
+  }
+
+  Drive d;
+  d.nsweeps = w.nsweeps_cap;
+  d.active = active;
+  d.rwh = make_rsrc(w.wheels, w.wheels_bytes);
+  d.wstride = (uint32_t)w.C * G::NW * 4u;
+  d.widx = ((uint32_t)copy * G::NW + wl) * 4u;
+  d.kmod = (int)__builtin_amdgcn_readfirstlane((uint32_t)((*w.done * (uint64_t)(G::RHO * L)) % G::M));
+  __syncthreads();
+  k.fetch(0, 0);
+  drive(k, d);
+
+  if (active) {
+    int Eb, Mf;
+    k.terms(Eb, Mf);
+    atomicAdd(&Ecnt[cl], Eb);
+    atomicAdd(&Mcnt[cl], Mf);
+  }
+  __syncthreads();
+  if (w.nsweeps_cap > 0)
+    for (int i = t; i < w.ncopies * G::CS; i += nthr) bstore(rsp, lds[i], i * 4, sbase);
+  for (int i = t; i < w.ncopies; i += nthr) {
+    w.E[w.copy0 + i] = Ecnt[i];
+    w.M[w.copy0 + i] = Mcnt[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // q = 4 +-J Potts heat bath.  One lane per wheel; each draw updates one site.
 //
 // Local field bytes.  With n- the number of J = -1 bonds of site i,
@@ -856,13 +1136,17 @@ __global__ __launch_bounds__(POTTS_MAX_TPB) void gpotts_sweep_kernel(const Work 
 // ---------------------------------------------------------------------------
 // Overlap between replica 0 and replica 1 at every temperature.
 //   Ising: Q = N - 2 popcount(a xor b) over the packed words (pads are zero);
+//   Ising-like models: over occupied sites, Q = sum popcount(X) -
+//   2 popcount((a xor b) and X) with X the sample's occupancy words;
 //   Potts: C = number of equal site bytes.
 // grid = S * K, one workgroup per (sample, temperature).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void overlap_kernel(const uint32_t *__restrict__ spins,
                                                       const int32_t *__restrict__ slot_of_temp,
                                                       int64_t *__restrict__ Q, int model, int L,
-                                                      int R, int K, int copy_words) {
+                                                      int R, int K, int copy_words,
+                                                      const uint32_t *__restrict__ occ,
+                                                      uint32_t occ_stride) {
   __shared__ int part[256];
   const int sk = blockIdx.x;
   const int s = sk / K, k = sk - s * K;
@@ -870,10 +1154,13 @@ __global__ __launch_bounds__(256) void overlap_kernel(const uint32_t *__restrict
   const int cb = (s * R + 1) * K + slot_of_temp[(s * R + 1) * K + k];
   const uint32_t *a = spins + (size_t)ca * copy_words;
   const uint32_t *b = spins + (size_t)cb * copy_words;
+  const uint32_t *X = occ ? occ + (size_t)s * occ_stride : nullptr;
   int acc = 0;
   for (int i = threadIdx.x; i < copy_words; i += blockDim.x) {
     const uint32_t x = a[i] ^ b[i];
-    if (model == 0) {
+    if (X) {
+      acc += __popc(X[i]) - 2 * __popc(x & X[i]);
+    } else if (model == 0) {
       acc += __popc(x);
     } else {
       // count equal bytes: a byte of x is zero iff the two sites agree
@@ -889,7 +1176,7 @@ __global__ __launch_bounds__(256) void overlap_kernel(const uint32_t *__restrict
   }
   if (threadIdx.x == 0) {
     const int64_t N = (int64_t)L * L * L;
-    Q[sk] = model == 0 ? N - 2 * (int64_t)part[0] : (int64_t)part[0];
+    Q[sk] = model == 0 && !X ? N - 2 * (int64_t)part[0] : (int64_t)part[0];
   }
 }
 
@@ -1052,6 +1339,30 @@ __global__ __launch_bounds__(1024) void ising_sweep_kernel(const Work *__restric
 template __global__ void ising_sweep_kernel<0>(const Work *, int);
 template __global__ void ising_sweep_kernel<1>(const Work *, int);
 
+template <int ALGO>
+__global__ __launch_bounds__(POTTS_MAX_TPB) void gen_sweep_kernel(const Work *__restrict__ works,
+                                                                  int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  switch (w.L) {
+    case 2: gen_run<2, ALGO>(w, lds); break;
+    case 4: gen_run<4, ALGO>(w, lds); break;
+    case 8: gen_run<8, ALGO>(w, lds); break;
+    case 16: gen_run<16, ALGO>(w, lds); break;
+    case 24: gen_run<24, ALGO>(w, lds); break;
+    case 32: gen_run<32, ALGO>(w, lds); break;
+    case 40: gen_run<40, ALGO>(w, lds); break;
+    case 48: gen_run<48, ALGO>(w, lds); break;
+    case 56: gen_run<56, ALGO>(w, lds); break;
+    case 64: gen_run<64, ALGO>(w, lds); break;
+    default: break;
+  }
+}
+
+template __global__ void gen_sweep_kernel<0>(const Work *, int);
+template __global__ void gen_sweep_kernel<1>(const Work *, int);
+
 }  // namespace sg
 
 // ---------------------------------------------------------------------------
@@ -1079,7 +1390,11 @@ hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st) {
 hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, int tpb,
                         size_t lds, int nsweeps, hipStream_t st) {
   if (nworks <= 0) return hipSuccess;
-  if (model == 2)
+  if (model == 3 && algo == 0)
+    hipLaunchKernelGGL(gen_sweep_kernel<0>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == 3)
+    hipLaunchKernelGGL(gen_sweep_kernel<1>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == 2)
     hipLaunchKernelGGL(gpotts_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == 1)
     hipLaunchKernelGGL(potts_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
@@ -1097,6 +1412,12 @@ hipError_t set_max_lds(int bytes) {
   e = hipFuncSetAttribute((const void *)gpotts_sweep_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)gen_sweep_kernel<0>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)gen_sweep_kernel<1>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)ising_sweep_kernel<0>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
@@ -1105,10 +1426,11 @@ hipError_t set_max_lds(int bytes) {
 }
 
 hipError_t launch_overlap(const uint32_t *spins, const int32_t *slot_of_temp, int64_t *Q, int model,
-                          int L, int S, int R, int K, int copy_words, hipStream_t st) {
+                          int L, int S, int R, int K, int copy_words, const uint32_t *occ,
+                          uint32_t occ_stride, hipStream_t st) {
   if (S * K <= 0) return hipSuccess;
   hipLaunchKernelGGL(overlap_kernel, dim3(S * K), dim3(256), 0, st, spins, slot_of_temp, Q, model,
-                     L, R, K, copy_words);
+                     L, R, K, copy_words, occ, occ_stride);
   return hipGetLastError();
 }
 

@@ -101,10 +101,29 @@ constexpr int POTTS_TAB_WORDS = 64 * POTTS_TAB_STRIDE;
 constexpr int POTTS_W_WORDS = 8;
 SG_HD constexpr int potts_lds_copy(int L) { return (L * L * L + 2 * geom(L).NG * L + 3) / 4 * 4; }
 
-// Per-temperature threshold row: 16 words.  Ising Metropolis uses [0..2],
+// Ising-like models of Eq. (2) of the paper (dilution x_i, field h_i =
+// |h| f_i): spins as for the EA glass.  Per (colour p, block-row wb, plane z)
+// 14 words in the site order of the spin words, laid out [p][wb][d][z]:
+//   d = 0..5   bit 1 <-> J = -1 on the bond in direction x+, x-, y+, y-, z+, z-
+//   d = 6..11  bit 1 <-> the neighbour in that direction is occupied
+//   d = 12     bit 1 <-> the site is occupied (x_i = 1)
+//   d = 13     bit 1 <-> f_i = -1
+// followed, per sample, by the occupancy bits of every site in the spin-copy
+// layout (CS words, pads zero) for the overlap.
+constexpr int GEN_WORDS = 14;
+SG_HD constexpr int gen_block_js(int L) { return 2 * geom(L).NWB * GEN_WORDS * L; }
+SG_HD constexpr int gen_js(int L) { return gen_block_js(L) + geom(L).CS; }
+// LDS threshold table of a copy: 32 words at an odd stride (bank spread).
+constexpr int GEN_TAB_STRIDE = 33;
+
+// Per-temperature threshold row: 32 words.  Ising Metropolis uses [0..2],
 // heat bath [0..6], Potts [0..12]; a threshold equal to 2^32 is stored as
-// 0xFFFFFFFF with bit n of word 15 set ("always").
-constexpr int THR_WORDS = 16;
+// 0xFFFFFFFF with bit n of word 15 set ("always").  Ising-like models: word
+// k + 16 phi holds the threshold of class (k, phi), k = 0..12, and words 13
+// and 29 the limits m_0, m_1 of the classes whose move is certain (Metropolis:
+// k < m_phi flips; heat bath: k >= m_phi sets s = +1); those classes' words
+// are 0.
+constexpr int THR_WORDS = 32;
 
 // One work item of a sweep launch: G complete copies of one job, served by
 // G * NW lanes of one workgroup.
@@ -120,6 +139,7 @@ struct Work {
   uint32_t spins_bytes, J_bytes, wheels_bytes;  // extents (buffer range checks)
   uint32_t pad;
   const uint64_t *done;          // sweeps already performed by the job (device)
+  int64_t *M;                    // [C] field sum per slot (Ising-like models), else null
 };
 
 // Parallel-tempering work of one workgroup: up to 64 chains of one job.

@@ -38,6 +38,18 @@ def test_glassy_potts_job_bytes():
     assert g - p >= 3 * 3 * 16 ** 3 - 3 * 256
 
 
+def test_ising_like_job_bytes():
+    # 14 coupling words per (colour, block row, plane) and the occupancy copy,
+    # on top of the EA glass's 6 words; one field sum per copy
+    for L in (8, 16, 64):
+        g = B.job_bytes(B.Spec(B.ISING_GEN, B.METROPOLIS, 4, L, 2, 2, 1, 0, 1.5))
+        e = B.job_bytes(B.Spec(B.ISING, B.METROPOLIS, 4, L, 2, 2, 1, 0))
+        assert g - e >= 2 * (8 * L ** 3 // 8 + L ** 3 // 8)
+    # no parallel tempering, but several temperatures without it are fine
+    assert B.job_bytes(B.Spec(B.ISING_GEN, B.HEATBATH, 4, 8, 1, 2, 4, 0, 0.0)) > 0
+    assert B.job_bytes(B.Spec(B.ISING_GEN, B.HEATBATH, 4, 8, 1, 2, 1, 10, 0.0)) > 0
+
+
 def test_job_bytes_and_validation():
     n = B.job_bytes(B.Spec(B.ISING, B.METROPOLIS, 4, 64, 1, 2, 1, 0))
     # two copies of 64^3 bit-packed spins, shared couplings, 512 wheels x 64 slots each
@@ -53,7 +65,12 @@ def test_job_bytes_and_validation():
         (B.Spec(B.GPOTTS, B.METROPOLIS, 4, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
         (B.Spec(B.GPOTTS, B.HEATBATH, 3, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
         (B.Spec(B.GPOTTS, B.HEATBATH, 4, 56, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
-        (B.Spec(3, B.HEATBATH, 4, 8, 1, 1, 1, 0), B.SG_E_INVALID),
+        (B.Spec(4, B.HEATBATH, 4, 8, 1, 1, 1, 0), B.SG_E_INVALID),
+        (B.Spec(B.ISING_GEN, B.METROPOLIS, 4, 8, 1, 1, 1, 0, -0.5), B.SG_E_INVALID),
+        (B.Spec(B.ISING_GEN, B.HEATBATH, 4, 8, 1, 1, 1, 0, float("inf")), B.SG_E_INVALID),
+        (B.Spec(B.ISING_GEN, B.HEATBATH, 4, 8, 1, 1, 1, 0, float("nan")), B.SG_E_INVALID),
+        (B.Spec(B.ISING_GEN, B.METROPOLIS, 4, 8, 1, 2, 4, 10, 1.0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.ISING_GEN, B.METROPOLIS, 4, 12, 1, 1, 1, 0, 1.0), B.SG_E_UNSUPPORTED),
     ):
         with pytest.raises(B.SgError) as e:
             B.job_bytes(spec)
