@@ -33,6 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # operation for the bit-sliced six-bond count and flip (36 word operations
 # per 32 sites)
 ALG_OPS_PER_UPDATE = 4
+# Ising-like models (Eq. 2): the same plus one operation forming the site's
+# threshold-table index (the paper's update cell reads a LUT in the same way)
+GEN_ALG_OPS_PER_UPDATE = 5
 C3_LS = (16, 24, 32, 48)
 C3_SAMPLES_PER_L, C3_R, C3_K, C3_PT = 64, 2, 32, 10
 
@@ -199,6 +202,55 @@ def potts_c4(ctx, B, inputs, np, torch, stream, sweeps, model="potts"):
     return out
 
 
+def ising_like(ctx, B, inputs, np, torch, stream, sweeps):
+    """Ising-like models of Eq. 2, Metropolis, no parallel tempering: the
+    random-field Ising model (J = +1, h_i = +-1.5) and the diluted
+    antiferromagnet in a field (J = -1, h = 1.0, each site occupied with
+    probability 1/2), at L = 32 (64 samples x 2 replicas x 16 temperatures)
+    and L = 64 (16 samples x 2 replicas x 8 temperatures), T = 1.0 .. 4.0.
+    Updates/ns over periods of `sweeps` sweeps (one launch each), wall clock
+    and HIP-event kernel time; empty sites count as visited sites."""
+    out = {}
+    for kind, h, seed in (("rfim", 1.5, 4300), ("daff", 1.0, 4400)):
+        for L, S, K in ((32, 64, 16), (64, 16, 8)):
+            betas = [1.0 / (1.0 + 3.0 * k / (K - 1)) for k in range(K)]
+            inst = inputs.make_instance(kind, L, S, 2, K, seed=seed)
+            job = B.Job(ctx, B.ISING_GEN, B.METROPOLIS, L, betas, inst["J"], inst["spins"],
+                        inst["wheels"], n_samples=S, n_replicas=2, field=h)
+            del inst
+            pb = B.Batch(ctx, [job])
+            pb.run(sweeps, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                pb.run(sweeps, stream)
+            torch.cuda.synchronize()
+            wall_ms = (time.perf_counter() - t0) * 1e3 / 3
+            pb.set_timing(True)
+            pk = []
+            for _ in range(3):
+                pb.run(sweeps, stream)
+                pk.append(pb.sweep_ms())
+            kms = float(np.mean(pk))
+            ups = job.C * job.N * sweeps
+            key = f"{kind}_L{L}"
+            out[key] = {"value": round(ups / (wall_ms * 1e6), 3), "unit": "spin updates/ns",
+                        "copies": job.C, "ms_per_period": round(wall_ms, 3),
+                        "kernel_ms_per_period": round(kms, 3),
+                        "kernel_updates_per_ns": round(ups / (kms * 1e6), 3),
+                        "alu_frac": round(ups * GEN_ALG_OPS_PER_UPDATE / (kms * 1e-3) / 1e12
+                                          / VALU_PEAK_TOPS, 4),
+                        "block_threads": pb.block()}
+            log(f"[bench] {kind} L={L}: {wall_ms:.2f} ms per {sweeps} sweeps, "
+                f"{out[key]['value']:.1f} updates/ns")
+            del pb, job
+    out["workload"] = (f"Ising-like models of Eq. 2, Metropolis: RFIM |h|=1.5 and DAFF h=1.0 "
+                       f"(occupation 1/2); L=32: 64 samples x 2 replicas x 16 temperatures, "
+                       f"L=64: 16 x 2 x 8, T=1.0..4.0; period = {sweeps} sweeps (one launch)")
+    out["alg_ops_per_update"] = GEN_ALG_OPS_PER_UPDATE
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +264,10 @@ def main():
                     help="jobs in the serving stream (0 = skip the serving measurement)")
     ap.add_argument("--potts-sweeps", type=int, default=200,
                     help="sweeps per timed Potts period (0 = skip the Potts measurement)")
+    ap.add_argument("--gen-sweeps", type=int, default=50,
+                    help="sweeps per timed Ising-like (RFIM, DAFF) period (0 = skip)")
+    ap.add_argument("--gen-only", action="store_true",
+                    help="time only the Ising-like workload (profiling runs)")
     ap.add_argument("--no-tune", action="store_true", help="skip the block-size autotuner")
     ap.add_argument("--block", type=int, default=0,
                     help="force the fused launch's threads per workgroup (skips the tuner)")
@@ -246,6 +302,10 @@ def main():
         return
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
+
+    if args.gen_only:
+        log(f"[bench] Ising-like only: {ising_like(ctx, B, inputs, np, torch, stream, args.gen_sweeps)}")
+        return
 
     if args.potts_only:
         log(f"[bench] Potts only: {potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps)}")
@@ -330,6 +390,9 @@ def main():
     glassy = potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps, "gpotts") \
         if args.potts_sweeps > 0 else None
 
+    isinglike = ising_like(ctx, B, inputs, np, torch, stream, args.gen_sweeps) \
+        if args.gen_sweeps > 0 else None
+
     serving_stats = None
     if args.serving_jobs > 0:
         serving_stats = serving_bench(ctx, args.serving_jobs)
@@ -384,6 +447,7 @@ def main():
         "speedup_batched_over_plain": round(value / plain_value, 2),
         "potts_c4": potts,
         "glassy_potts": glassy,
+        "ising_like": isinglike,
         "serving": serving_stats,
         "cpu_baseline": cpu,
         "context": {"paper_fpga_ea_updates_per_ns": {"Virtex4-LX160": 31.25,
