@@ -251,6 +251,58 @@ def ising_like(ctx, B, inputs, np, torch, stream, sweeps):
     return out
 
 
+def equilibration(ctx, B, inputs, np, torch, stream, n_meas):
+    """Equilibration analysis of sec. 4.1 on a measured run: EA glass L = 16,
+    16 samples x 2 replicas x 8 temperatures T = 0.7 .. 1.6, Metropolis, PT
+    every 10 sweeps, overlaps measured after every PT period (n_meas
+    measurements); q^2 log2 bins and P(q) asymmetry from the library's
+    analysis module, and the cost of measuring (run time with the
+    measurements vs the same sweeps without)."""
+    from paper_0704_3573_amd import analysis as A
+    L, S, K, every = 16, 16, 8, 10
+    temps = np.linspace(0.7, 1.6, K)
+    inst = inputs.make_instance("ising", L, S, 2, K, seed=4500)
+    mk = lambda: B.Job(ctx, B.ISING, B.METROPOLIS, L, 1.0 / temps, inst["J"], inst["spins"],
+                       inst["wheels"], inst["ptwheels"], n_samples=S, n_replicas=2,
+                       pt_every=every)
+    job = mk()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_meas):
+        job.sweep(every, stream)
+    torch.cuda.synchronize()
+    bare_s = time.perf_counter() - t0
+    del job
+    job = mk()
+    Qs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_meas):
+        job.sweep(every, stream)
+        Qs.append(job.measure(stream)[1])
+    meas_s = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    Q = A.stack_measurements(Qs, S, K)
+    N = A.sites_per_sample(A.ISING, L, inst["J"])
+    means, errs = A.log2_binning(A.ISING, Q, N)
+    asym = A.pq_asymmetry(A.pq_counts(A.ISING, Q, N, start=n_meas // 2), bands=16)
+    analysis_ms = (time.perf_counter() - t1) * 1e3
+    ups = n_meas * every * job.C * job.N
+    out = {"workload": f"EA +-J L={L}, {S} samples x 2 replicas x {K} temperatures "
+                       f"T=0.7..1.6, Metropolis, PT every {every} sweeps, overlaps after every "
+                       f"period, {n_meas} measurements ({n_meas * every} sweeps)",
+           "updates_per_ns_with_measurements": round(ups / (meas_s * 1e9), 3),
+           "updates_per_ns_without": round(ups / (bare_s * 1e9), 3),
+           "measurement_overhead": round(meas_s / bare_s - 1.0, 4),
+           "analysis_ms": round(analysis_ms, 3),
+           "q2_log2_bins_T0.7": [round(float(x), 5) for x in means[::-1, 0]],
+           "q2_log2_bins_T1.6": [round(float(x), 5) for x in means[::-1, -1]],
+           "q2_log2_bins_order": "sixteenth, eighth, quarter, last half",
+           "pq_asymmetry_last_half_16_bands": [round(float(x), 4) for x in asym]}
+    log(f"[bench] equilibration: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +320,8 @@ def main():
                     help="sweeps per timed Ising-like (RFIM, DAFF) period (0 = skip)")
     ap.add_argument("--gen-only", action="store_true",
                     help="time only the Ising-like workload (profiling runs)")
+    ap.add_argument("--eq-meas", type=int, default=256,
+                    help="measurements of the equilibration-analysis run (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="skip the block-size autotuner")
     ap.add_argument("--block", type=int, default=0,
                     help="force the fused launch's threads per workgroup (skips the tuner)")
@@ -393,6 +447,9 @@ def main():
     isinglike = ising_like(ctx, B, inputs, np, torch, stream, args.gen_sweeps) \
         if args.gen_sweeps > 0 else None
 
+    eq = equilibration(ctx, B, inputs, np, torch, stream, args.eq_meas) \
+        if args.eq_meas > 0 else None
+
     serving_stats = None
     if args.serving_jobs > 0:
         serving_stats = serving_bench(ctx, args.serving_jobs)
@@ -448,6 +505,7 @@ def main():
         "potts_c4": potts,
         "glassy_potts": glassy,
         "ising_like": isinglike,
+        "equilibration": eq,
         "serving": serving_stats,
         "cpu_baseline": cpu,
         "context": {"paper_fpga_ea_updates_per_ns": {"Virtex4-LX160": 31.25,
