@@ -20,6 +20,7 @@ SRC = os.path.join(HERE, "sg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 ISING, POTTS, GPOTTS = 0, 1, 2  # GPOTTS: glassy (permutation) Potts, Eq. (3)
+GPOTTS4 = 4  # glassy Potts model on the 4D hypercubic lattice
 ISING_GEN = 3  # Ising-like model of Eq. (2) with dilution and field (RFIM, DAFF)
 METROPOLIS, HEATBATH = 0, 1
 
@@ -70,7 +71,14 @@ def lib():
         _lib.or_gpotts_update_site.restype = C.c_int32
         _lib.or_gpotts_fields.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                           C.POINTER(C.c_int32)]
-        for n in ("or_ising_energy", "or_potts_energy", "or_gpotts_energy"):
+        _lib.or_gpotts4_update_site.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                                C.c_uint32, u64p]
+        _lib.or_gpotts4_update_site.restype = C.c_int32
+        _lib.or_gpotts4_fields.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                           C.POINTER(C.c_int32)]
+        _lib.or_wheels_per_copy_4d.argtypes = [C.c_int32]
+        _lib.or_wheels_per_copy_4d.restype = C.c_int32
+        for n in ("or_ising_energy", "or_potts_energy", "or_gpotts_energy", "or_gpotts4_energy"):
             getattr(_lib, n).argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
             getattr(_lib, n).restype = C.c_int64
         for n in ("or_ising_overlap", "or_potts_overlap"):
@@ -170,6 +178,23 @@ def gpotts_fields(L, s, P, i) -> np.ndarray:
     return h
 
 
+def gpotts4_update_site(L, s, P, i, r, W) -> int:
+    """4D glassy Potts: update site i of uint8 spins s (L^4) with P [4][N]."""
+    W = np.ascontiguousarray(W, dtype=np.uint64)
+    assert s.dtype == np.uint8 and P.dtype == np.uint8 and s.flags.c_contiguous
+    return int(lib().or_gpotts4_update_site(L, s.ctypes.data, P.ctypes.data, i, r,
+                                            _p(W, C.c_uint64)))
+
+
+def gpotts4_fields(L, s, P, i) -> np.ndarray:
+    """Local fields h_a (a = 0..3) of site i of the 4D glassy Potts model."""
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    P = np.ascontiguousarray(P, dtype=np.uint8)
+    h = np.zeros(4, dtype=np.int32)
+    lib().or_gpotts4_fields(L, s.ctypes.data, P.ctypes.data, i, _p(h, C.c_int32))
+    return h
+
+
 def isinggen_update_site(L, algo, s, D, field, beta, i, r):
     """General Ising-like model: update site i of int8 spins s (D = [5][N]);
     returns (change of the bond energy, change of the field sum)."""
@@ -189,14 +214,14 @@ def isinggen_terms(L, s, D):
 
 
 def _couplings(model, J):
-    return np.ascontiguousarray(J, dtype=np.uint8 if model == GPOTTS else np.int8)
+    return np.ascontiguousarray(J, dtype=np.uint8 if model in (GPOTTS, GPOTTS4) else np.int8)
 
 
 def energy(model, L, s, J) -> int:
     s = np.ascontiguousarray(s)
     J = _couplings(model, J)
     f = {ISING: lib().or_ising_energy, POTTS: lib().or_potts_energy,
-         GPOTTS: lib().or_gpotts_energy}[model]
+         GPOTTS: lib().or_gpotts_energy, GPOTTS4: lib().or_gpotts4_energy}[model]
     return int(f(L, s.ctypes.data, J.ctypes.data))
 
 
@@ -207,7 +232,9 @@ def overlap(model, L, a, b) -> int:
     return int(f(L, a.ctypes.data, b.ctypes.data))
 
 
-def wheels_per_copy(L: int) -> int:
+def wheels_per_copy(L: int, model: int = ISING) -> int:
+    if model == GPOTTS4:
+        return int(lib().or_wheels_per_copy_4d(L))
     return int(lib().or_wheels_per_copy(L))
 
 
@@ -230,9 +257,10 @@ def run(model, algo, L, betas, J, spins, wheels, ptwheels=None, slot_of_temp=Non
     K = betas.shape[0]
     S, R = n_samples, n_replicas
     Cn = S * R * K
-    N = L ** 3
-    NW = wheels_per_copy(L)
-    J = _couplings(model, J).reshape(S, 5 if model == ISING_GEN else 3, N)
+    dim = 4 if model == GPOTTS4 else 3
+    N = L ** dim
+    NW = wheels_per_copy(L, model)
+    J = _couplings(model, J).reshape(S, {ISING_GEN: 5, GPOTTS4: 4}.get(model, 3), N)
     sp = np.array(spins, dtype=np.int8 if model in (ISING, ISING_GEN) else np.uint8,
                   copy=True).reshape(Cn, N)
     wh = np.array(wheels, dtype=np.uint32, copy=True).reshape(Cn, NW, 61)

@@ -186,10 +186,10 @@ static int32_t potts_update(uint8_t *s, const int8_t *J, int64_t i, const int64_
  *   bond to j = i - e_d (stored at j):   s_i = a scores iff pi(a) = s_j. */
 static int perm_image(uint8_t P, int v) { return (P >> (2 * v)) & 3; }
 
-static void gpotts_fields(const uint8_t *s, const uint8_t *P, const int64_t nb[6],
-                          const int64_t bond[6], int32_t h[4]) {
+static void gpotts_fields_n(int nd, const uint8_t *s, const uint8_t *P, const int64_t *nb,
+                            const int64_t *bond, int32_t h[4]) {
   for (int a = 0; a < 4; a++) h[a] = 0;
-  for (int d = 0; d < 6; d++) {
+  for (int d = 0; d < nd; d++) {
     uint8_t pi = P[bond[d]];
     int sj = s[nb[d]];
     if ((d & 1) == 0) {
@@ -201,11 +201,68 @@ static void gpotts_fields(const uint8_t *s, const uint8_t *P, const int64_t nb[6
   }
 }
 
+static void gpotts_fields(const uint8_t *s, const uint8_t *P, const int64_t nb[6],
+                          const int64_t bond[6], int32_t h[4]) {
+  gpotts_fields_n(6, s, P, nb, bond, h);
+}
+
 static int32_t gpotts_update(uint8_t *s, const uint8_t *P, int64_t i, const int64_t nb[6],
                              const int64_t bond[6], uint32_t r, const uint64_t W[13]) {
   int32_t h[4];
   gpotts_fields(s, P, nb, bond, h);
   return potts_heat_bath(s, i, h, r, W);
+}
+
+/* ------------------------------------------------------------------ */
+/* 4D glassy Potts (Eq. 3 on the hypercubic lattice, sec. 4.2): periodic */
+/* L^4, i = x + L (y + L (z + L u)); P[d][i] (d = x, y, z, u) is the bond */
+/* between i and i + e_d, stored at i as for 3D.  Neighbour d = 2a is    */
+/* i + e_a (bond stored at i), d = 2a + 1 is i - e_a (stored there).     */
+/* ------------------------------------------------------------------ */
+static void neighbours4(int32_t L, int64_t x, int64_t y, int64_t z, int64_t u, int64_t nb[8],
+                        int64_t bond[8]) {
+  int64_t N = (int64_t)L * L * L * L;
+  int64_t c[4] = {x, y, z, u}, stride[4] = {1, L, (int64_t)L * L, (int64_t)L * L * L};
+  int64_t i = x + stride[1] * y + stride[2] * z + stride[3] * u;
+  for (int a = 0; a < 4; a++) {
+    int64_t up = c[a] + 1 == L ? 0 : c[a] + 1, dn = c[a] == 0 ? L - 1 : c[a] - 1;
+    nb[2 * a] = i + (up - c[a]) * stride[a];
+    nb[2 * a + 1] = i + (dn - c[a]) * stride[a];
+    bond[2 * a] = a * N + i;
+    bond[2 * a + 1] = a * N + nb[2 * a + 1];
+  }
+}
+
+static void neighbours4_i(int32_t L, int64_t i, int64_t nb[8], int64_t bond[8]) {
+  int64_t L2 = (int64_t)L * L;
+  neighbours4(L, i % L, (i / L) % L, (i / L2) % L, i / (L2 * L), nb, bond);
+}
+
+int32_t or_gpotts4_update_site(int32_t L, uint8_t *s, const uint8_t *P, int64_t i, uint32_t r,
+                               const uint64_t W[13]) {
+  int64_t nb[8], bond[8];
+  int32_t h[4];
+  neighbours4_i(L, i, nb, bond);
+  gpotts_fields_n(8, s, P, nb, bond, h);
+  return potts_heat_bath(s, i, h, r, W);
+}
+
+void or_gpotts4_fields(int32_t L, const uint8_t *s, const uint8_t *P, int64_t i, int32_t h[4]) {
+  int64_t nb[8], bond[8];
+  neighbours4_i(L, i, nb, bond);
+  gpotts_fields_n(8, s, P, nb, bond, h);
+}
+
+/* each of the 4N bonds once, as the term stored at its lower site */
+int64_t or_gpotts4_energy(int32_t L, const uint8_t *s, const uint8_t *P) {
+  int64_t N = (int64_t)L * L * L * L, E = 0;
+  for (int64_t i = 0; i < N; i++) {
+    int64_t nb[8], bond[8];
+    neighbours4_i(L, i, nb, bond);
+    for (int d = 0; d < 8; d += 2)
+      if (s[i] == perm_image(P[bond[d]], s[nb[d]])) E -= 1;
+  }
+  return E;
 }
 
 /* General Ising-like model, Eq. (2): H = -sum J_ij x_i x_j s_i s_j
@@ -350,6 +407,43 @@ int32_t or_wheels_per_copy(int32_t L) {
   return L * (L / rho);
 }
 
+/* 4D: one wheel per (z, u, group of rho rows), index (g L + u) L + z */
+int32_t or_wheels_per_copy_4d(int32_t L) { return L * or_wheels_per_copy(L); }
+
+static int32_t is_4d(const or_spec *sp) { return sp->model == OR_GPOTTS4; }
+static int64_t sites_of(const or_spec *sp) {
+  int64_t N = (int64_t)sp->L * sp->L * sp->L;
+  return is_4d(sp) ? N * sp->L : N;
+}
+static int32_t wheels_of(const or_spec *sp) {
+  return is_4d(sp) ? or_wheels_per_copy_4d(sp->L) : or_wheels_per_copy(sp->L);
+}
+
+/* 4D sweep: colour p = (x + y + z + u) mod 2, even colour first; wheel
+ * (g L + u) L + z serves rows y = g rho .. g rho + rho - 1 of the (z, u)
+ * plane, one number per visited site, colour, then row, then increasing x. */
+static void copy_sweep_4d(const or_spec *sp, uint8_t *spins, const uint8_t *P, or_wheel *wheels,
+                          const uint64_t *W, int64_t *E) {
+  int32_t L = sp->L, rho = L < 8 ? L : 8, nG = L / rho;
+  for (int p = 0; p < 2; p++)
+    for (int g = 0; g < nG; g++)
+      for (int u = 0; u < L; u++)
+        for (int z = 0; z < L; z++) {
+          or_wheel *w = &wheels[((int64_t)g * L + u) * L + z];
+          for (int y = g * rho; y < g * rho + rho; y++)
+            for (int x = 0; x < L; x++) {
+              if (((x + y + z + u) & 1) != p) continue;
+              uint32_t r = or_wheel_next(w);
+              int64_t i = x + (int64_t)L * (y + (int64_t)L * (z + (int64_t)L * u));
+              int64_t nb[8], bond[8];
+              int32_t h[4];
+              neighbours4(L, x, y, z, u, nb, bond);
+              gpotts_fields_n(8, spins, P, nb, bond, h);
+              *E += potts_heat_bath(spins, i, h, r, W);
+            }
+        }
+}
+
 /* ------------------------------------------------------------------ */
 /* One sweep of one copy.  Colour p = (x + y + z) mod 2; the even colour */
 /* is updated first (sec. 3.1: all sites of one colour, then the other). */
@@ -389,6 +483,7 @@ static void copy_sweep(const or_spec *sp, void *spins, const int8_t *J, or_wheel
 }
 
 static int64_t copy_energy(const or_spec *sp, const void *spins, const int8_t *J) {
+  if (sp->model == OR_GPOTTS4) return or_gpotts4_energy(sp->L, (const uint8_t *)spins, (const uint8_t *)J);
   if (sp->model == OR_ISING) return or_ising_energy(sp->L, (const int8_t *)spins, J);
   if (sp->model == OR_POTTS) return or_potts_energy(sp->L, (const uint8_t *)spins, J);
   if (sp->model == OR_GPOTTS) return or_gpotts_energy(sp->L, (const uint8_t *)spins, (const uint8_t *)J);
@@ -400,10 +495,12 @@ static int64_t copy_field_sum(const or_spec *sp, const void *spins, const int8_t
 }
 
 /* coupling rows per sample: J_x, J_y, J_z (+ x, f for the general model) */
-static int64_t coupling_rows(const or_spec *sp) { return sp->model == OR_ISING_GEN ? 5 : 3; }
+static int64_t coupling_rows(const or_spec *sp) {
+  return sp->model == OR_ISING_GEN ? 5 : (sp->model == OR_GPOTTS4 ? 4 : 3);
+}
 
 static void copy_tables(const or_spec *sp, double beta, uint64_t T[13]) {
-  if (sp->model == OR_POTTS || sp->model == OR_GPOTTS)
+  if (sp->model == OR_POTTS || sp->model == OR_GPOTTS || sp->model == OR_GPOTTS4)
     or_tables_potts(beta, T);
   else if (sp->algo == OR_METROPOLIS)
     or_tables_metropolis(beta, T);
@@ -429,8 +526,8 @@ typedef struct {
 static void *sweep_worker(void *p) {
   worker_arg *a = (worker_arg *)p;
   const or_spec *sp = a->sp;
-  int64_t N = (int64_t)sp->L * sp->L * sp->L;
-  int32_t NW = or_wheels_per_copy(sp->L);
+  int64_t N = sites_of(sp);
+  int32_t NW = wheels_of(sp);
   int64_t RK = (int64_t)sp->n_replicas * sp->n_temps;
   for (int64_t c = a->c_begin; c < a->c_end; c++) {
     const int8_t *Jc = a->J + (c / RK) * coupling_rows(sp) * N;
@@ -439,7 +536,10 @@ static void *sweep_worker(void *p) {
     uint64_t T[13];
     copy_tables(sp, beta, T);
     for (uint64_t t = 0; t < a->nsw; t++) {
-      copy_sweep(sp, sc, Jc, a->wheels + c * NW, T, beta, &a->E[c], &a->M[c]);
+      if (is_4d(sp))
+        copy_sweep_4d(sp, sc, (const uint8_t *)Jc, a->wheels + c * NW, T, &a->E[c]);
+      else
+        copy_sweep(sp, sc, Jc, a->wheels + c * NW, T, beta, &a->E[c], &a->M[c]);
       if (sp->check_energy &&
           (a->E[c] != copy_energy(sp, sc, Jc) || a->M[c] != copy_field_sum(sp, sc, Jc))) {
         a->err = OR_ENERGY_MISMATCH;
@@ -509,7 +609,7 @@ static void pt_step(const or_spec *sp, const double *betas, or_wheel *ptw, int32
 
 static void measure(const or_spec *sp, const int8_t *J, const uint8_t *spins, const int32_t *sot,
                     const int64_t *E, int64_t *E_log, int64_t *Q_log) {
-  int64_t N = (int64_t)sp->L * sp->L * sp->L;
+  int64_t N = sites_of(sp);
   int32_t S = sp->n_samples, R = sp->n_replicas, K = sp->n_temps;
   if (E_log)
     for (int64_t ch = 0; ch < (int64_t)S * R; ch++)
@@ -525,8 +625,11 @@ static void measure(const or_spec *sp, const int8_t *J, const uint8_t *spins, co
       else if (sp->model == OR_ISING_GEN)
         Q_log[(int64_t)s * K + k] = or_isinggen_overlap(sp->L, (const int8_t *)spins + ca * N,
                                                         (const int8_t *)spins + cb * N, J + s * 5 * N);
-      else
-        Q_log[(int64_t)s * K + k] = or_potts_overlap(sp->L, spins + ca * N, spins + cb * N);
+      else {
+        int64_t Q = 0; /* Potts models: number of equal sites */
+        for (int64_t i = 0; i < N; i++) Q += spins[ca * N + i] == spins[cb * N + i];
+        Q_log[(int64_t)s * K + k] = Q;
+      }
     }
 }
 
@@ -538,12 +641,14 @@ int32_t or_run(const or_spec *sp, const double *betas, const int8_t *J, void *sp
                int64_t *Q_log, uint64_t *pt_accepts, int64_t *M_out) {
   if (!sp || !valid_L(sp->L) || sp->n_samples < 1 || sp->n_replicas < 1 || sp->n_temps < 1)
     return OR_EINVAL;
-  if (sp->model < OR_ISING || sp->model > OR_ISING_GEN) return OR_EINVAL;
-  if ((sp->model == OR_POTTS || sp->model == OR_GPOTTS) && sp->algo != OR_HEATBATH) return OR_EINVAL;
+  if (sp->model < OR_ISING || sp->model > OR_GPOTTS4) return OR_EINVAL;
+  if ((sp->model == OR_POTTS || sp->model == OR_GPOTTS || sp->model == OR_GPOTTS4) &&
+      sp->algo != OR_HEATBATH)
+    return OR_EINVAL;
   if (sp->model == OR_ISING_GEN && (sp->pt_every > 0 || !(sp->field >= 0.0))) return OR_EINVAL;
   uint8_t *spins = (uint8_t *)spins_v;
-  int64_t N = (int64_t)sp->L * sp->L * sp->L;
-  int32_t NW = or_wheels_per_copy(sp->L);
+  int64_t N = sites_of(sp);
+  int32_t NW = wheels_of(sp);
   int32_t K = sp->n_temps;
   int64_t chains = (int64_t)sp->n_samples * sp->n_replicas;
   int64_t C = chains * K;

@@ -21,6 +21,7 @@
  *   Parisi-Rapuano generator, Eq. (5)                       (sec. 3.3)
  *   parallel tempering, named as an add-on                  (sec. 2.2)
  *   Eq. (3)  glassy Potts model with permutation couplings  (sec. 2.1)
+ *            also on the 4D hypercubic lattice (OR_GPOTTS4)  (sec. 4.2)
  *   Eq. (2)  Ising-like models with dilution x_i and field h_i, e.g. the
  *            random-field Ising model (RFIM) and the diluted antiferromagnet
  *            in a field (DAFF)                               (sec. 2.1)
@@ -39,7 +40,7 @@
 extern "C" {
 #endif
 
-enum { OR_ISING = 0, OR_POTTS = 1, OR_GPOTTS = 2, OR_ISING_GEN = 3 };
+enum { OR_ISING = 0, OR_POTTS = 1, OR_GPOTTS = 2, OR_ISING_GEN = 3, OR_GPOTTS4 = 4 };
 enum { OR_METROPOLIS = 0, OR_HEATBATH = 1 };
 
 /* Errors returned by or_run. */
@@ -89,6 +90,18 @@ int32_t or_gpotts_update_site(int32_t L, uint8_t *s, const uint8_t *P, int64_t i
 /* Local fields h_a, a = 0..3, of site i of the glassy Potts model (the
  * number of bonds of i whose term is 1 when s_i = a). */
 void or_gpotts_fields(int32_t L, const uint8_t *s, const uint8_t *P, int64_t i, int32_t h[4]);
+
+/* 4D glassy Potts: periodic L^4, i = x + L (y + L (z + L u)), P = [4][N]
+ * permutation bytes, P[d][i] on the bond i -> i + e_d (d = x, y, z, u),
+ * term delta(s_i, pi(s_{i+e_d})) as in 3D; eight neighbours, h_a in 0..8.
+ * Sweep order: colour (x + y + z + u) mod 2, even first; wheel
+ * (g L + u) L + z serves rows g rho .. g rho + rho - 1 of the (z, u) plane,
+ * rows ascending, x ascending (or_wheels_per_copy_4d(L) = L^3 / rho wheels). */
+int32_t or_gpotts4_update_site(int32_t L, uint8_t *s, const uint8_t *P, int64_t i, uint32_t r,
+                               const uint64_t W[13]);
+void or_gpotts4_fields(int32_t L, const uint8_t *s, const uint8_t *P, int64_t i, int32_t h[4]);
+int64_t or_gpotts4_energy(int32_t L, const uint8_t *s, const uint8_t *P);
+int32_t or_wheels_per_copy_4d(int32_t L);
 
 /* General Ising-like model of Eq. (2): D = [5][N] int8, rows J_x, J_y, J_z
  * (+-1, J[d][i] joins i and i + e_d), x (0 = empty site, 1 = spin) and f

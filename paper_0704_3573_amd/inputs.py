@@ -20,6 +20,10 @@ Encodings (canonical, host side):
     bond joining i and i + e_d holds the permutation pi of its term
     delta(s_i, pi(s_{i+e_d})) as its images, pi(v) = (byte >> 2v) & 3; element
     n is permutation number (stream output n mod 24) in lexicographic order;
+  * the 4D glassy Potts model ("gpotts4"): hypercubic lattice of side L,
+    site i = x + L*(y + L*(z + L*u)), N = L^4, couplings uint8 [4][N] (d = x,
+    y, z, u) on a stream of their own, spins as for Potts; one sweep wheel per
+    (z, u, group of rho rows), L * L * L / rho per copy;
   * Ising-like models of Eq. 2 (dilution x_i, field h_i = |h| f_i): int8
     [5][N], rows J_x, J_y, J_z, x, f.  "rfim": J = +1, x = 1, f iid +-1;
     "daff": J = -1, x iid in {0, 1} (p = 1/2), f = +1; "isinggen": J, x and
@@ -96,11 +100,13 @@ def permutation_bytes() -> np.ndarray:
                      for p in itertools.permutations(range(4))], dtype=np.uint8)
 
 
-def glassy_couplings(seed: int, sample: int, L: int) -> np.ndarray:
-    """uint8 [3][L^3] iid uniform random permutations, one per bond."""
-    n = L ** 3
-    u = stream(stream_key(seed, TAG_Q, sample), 3 * n) % np.uint64(24)
-    return permutation_bytes()[u.astype(np.int64)].reshape(3, n)
+def glassy_couplings(seed: int, sample: int, L: int, dim: int = 3) -> np.ndarray:
+    """uint8 [dim][L^dim] iid uniform random permutations, one per bond
+    (3D and 4D draw from different streams)."""
+    n = L ** dim
+    key = stream_key(seed, TAG_Q, sample) if dim == 3 else stream_key(seed, TAG_Q, sample, dim)
+    u = stream(key, dim * n) % np.uint64(24)
+    return permutation_bytes()[u.astype(np.int64)].reshape(dim, n)
 
 
 def ising_like_couplings(kind: str, seed: int, sample: int, L: int) -> np.ndarray:
@@ -128,13 +134,14 @@ def ising_spins(seed: int, copies, L: int) -> np.ndarray:
     return (1 - 2 * b.astype(np.int8))
 
 
-def potts_spins(seed: int, copies, L: int, q: int = 4) -> np.ndarray:
-    """uint8 [len(copies)][L^3] iid initial Potts states in 0..3 (q = 4)."""
+def potts_spins(seed: int, copies, L: int, q: int = 4, dim: int = 3) -> np.ndarray:
+    """uint8 [len(copies)][L^dim] iid initial Potts states in 0..3 (q = 4)."""
     if q != 4:
         raise ValueError("only q = 4 has a two-bit encoding")
     copies = np.atleast_1d(np.asarray(copies, dtype=np.uint64))
-    b = _bits(stream_key(seed, TAG_S, copies), 2 * L ** 3)
-    b = b.reshape(b.shape[:-1] + (L ** 3, 2))
+    n = L ** dim
+    b = _bits(stream_key(seed, TAG_S, copies), 2 * n)
+    b = b.reshape(b.shape[:-1] + (n, 2))
     return (b[..., 0] | (b[..., 1] << 1)).astype(np.uint8)
 
 
@@ -162,16 +169,18 @@ def rho(L: int) -> int:
     return min(8, L)
 
 
-def wheels_per_copy(L: int) -> int:
-    """One wheel per (z, group of rho rows): L * L / rho."""
-    return L * (L // rho(L))
+def wheels_per_copy(L: int, dim: int = 3) -> int:
+    """One wheel per (z, group of rho rows): L * L / rho; in 4D one per
+    (z, u, group of rho rows): L^3 / rho."""
+    return L ** (dim - 2) * (L // rho(L))
 
 
 def make_instance(model: str, L: int, n_samples: int, n_replicas: int,
                   n_temps: int, seed: int, sample0: int = 0):
     """All inputs of one job: couplings, spins, sweep wheels, PT wheels.
-    model: "ising", "potts" (+-J Potts glass), "gpotts" (glassy Potts), or an
-    Ising-like model of Eq. 2: "rfim", "daff", "isinggen" (J is then [S][5][N]).
+    model: "ising", "potts" (+-J Potts glass), "gpotts" (glassy Potts),
+    "gpotts4" (glassy Potts in 4D, J [S][4][L^4]), or an Ising-like model of
+    Eq. 2: "rfim", "daff", "isinggen" (J is then [S][5][N]).
 
     Copy (slot) c = (s * R + r) * K + k for sample s, replica r, slot k.
     Samples are numbered from `sample0` so that one large campaign can be
@@ -179,8 +188,12 @@ def make_instance(model: str, L: int, n_samples: int, n_replicas: int,
     """
     S, R, K = n_samples, n_replicas, n_temps
     C = S * R * K
+    dim = 4 if model == "gpotts4" else 3
     if model == "gpotts":
         make_J = glassy_couplings
+    elif model == "gpotts4":
+        def make_J(seed, sample, L):
+            return glassy_couplings(seed, sample, L, dim=4)
     elif model in ("rfim", "daff", "isinggen"):
         def make_J(seed, sample, L):
             return ising_like_couplings(model, seed, sample, L)
@@ -190,11 +203,11 @@ def make_instance(model: str, L: int, n_samples: int, n_replicas: int,
     glob = np.arange(C, dtype=np.uint64) + np.uint64(sample0 * R * K)
     if model in ("ising", "rfim", "daff", "isinggen"):
         sp = ising_spins(seed, glob, L)
-    elif model in ("potts", "gpotts"):
-        sp = potts_spins(seed, glob, L)
+    elif model in ("potts", "gpotts", "gpotts4"):
+        sp = potts_spins(seed, glob, L, dim=dim)
     else:
         raise ValueError(model)
-    wh = wheel_seeds(seed, glob, wheels_per_copy(L))
+    wh = wheel_seeds(seed, glob, wheels_per_copy(L, dim))
     chains = np.arange(S * R, dtype=np.uint64) + np.uint64(sample0 * R)
     pw = pt_wheel_seeds(seed, chains)
     return {"J": np.ascontiguousarray(J), "spins": np.ascontiguousarray(sp),
