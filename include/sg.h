@@ -69,6 +69,13 @@ extern "C" {
  * M = sum_i x_i f_i s_i comes from sg_job_field_sums, and H = E_b - field * M.
  * Overlaps count occupied sites only.  No parallel tempering. */
 #define SG_ISING_GEN 3
+/* q = 4 glassy Potts model of Eq. (3) on the 4D hypercubic lattice (the
+ * paper's 4D runs, sec. 4.2): side L in {2, 4, 8, 16}, site
+ * i = x + L*(y + L*(z + L*u)), N = L^4, couplings [S][4][N] permutation
+ * bytes (d = x, y, z, u), heat bath; one sweep wheel per (z, u, group of
+ * min(8, L) rows), index (g*L + u)*L + z, drawing in the 3D order (colour
+ * (x+y+z+u) mod 2, rows, x): sg_model_wheels_per_copy(SG_GPOTTS4, L) wheels. */
+#define SG_GPOTTS4 4
 #define SG_METROPOLIS 0
 #define SG_HEATBATH 1
 
@@ -77,7 +84,7 @@ typedef struct sg_job sg_job;
 typedef struct sg_batch sg_batch;
 
 typedef struct sg_job_spec {
-  int32_t model;      /* SG_ISING, SG_POTTS, SG_GPOTTS or SG_ISING_GEN         */
+  int32_t model;      /* SG_ISING, SG_POTTS, SG_GPOTTS, SG_ISING_GEN, SG_GPOTTS4 */
   int32_t algo;       /* SG_METROPOLIS or SG_HEATBATH (Potts models: heat bath) */
   int32_t q;          /* Potts states, must be 4 (ignored for Ising)            */
   int32_t L;          /* 2, 4, 8, 16, 24, 32, 40, 48, 56, 64 (Potts: <= 48)     */
@@ -93,6 +100,9 @@ const char *sg_last_error(void);
 
 /* Number of sweep wheels per copy for side L (0 if L is not supported). */
 int32_t sg_wheels_per_copy(int32_t L);
+/* The same for a model: SG_GPOTTS4 has one wheel per (z, u, row group),
+ * L^3 / min(8, L); every other model as sg_wheels_per_copy(L). */
+int32_t sg_model_wheels_per_copy(int32_t model, int32_t L);
 
 /* Bind a context to HIP device `device`. */
 int sg_ctx_create(int device, sg_ctx **out);
@@ -110,7 +120,8 @@ int sg_job_bytes(const sg_job_spec *spec, uint64_t *bytes);
  *                 permutations pi of (0, 1, 2, 3), the bond's term being
  *                 delta(s_i, pi(s_{i+e_d})) with pi(v) = (byte >> 2v) & 3;
  *                 for SG_ISING_GEN [S][5][N] int8: rows J_x, J_y, J_z (+-1),
- *                 x (0 = empty site, 1 = spin) and f (+-1);
+ *                 x (0 = empty site, 1 = spin) and f (+-1); for SG_GPOTTS4
+ *                 [S][4][L^4] permutation bytes as for SG_GPOTTS;
  *   spins         [C][N] int8 +-1 (Ising models) or uint8 0..3 (Potts models);
  *                 an empty site keeps its spin (and still consumes its number);
  *   wheels        [C][NW][61];      ptwheels [S*R][61] (may be NULL if

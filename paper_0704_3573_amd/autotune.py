@@ -28,7 +28,7 @@ def signature(jobs) -> str:
 
 
 def candidates(jobs):
-    lo = max(B.wheels_per_copy(j.L) for j in jobs)
+    lo = max(j.NW for j in jobs)
     lo = (lo + 63) // 64 * 64
     return list(range(lo, 1025, 64))
 

@@ -17,13 +17,14 @@ LIB_PATH = os.path.join(HERE, "libsg.so")
 
 ISING, POTTS, GPOTTS = 0, 1, 2  # GPOTTS: glassy Potts model (permutation couplings)
 ISING_GEN = 3  # Ising-like model of Eq. 2 with dilution and field (RFIM, DAFF)
+GPOTTS4 = 4  # glassy Potts model on the 4D hypercubic lattice
 METROPOLIS, HEATBATH = 0, 1
 
 SG_OK, SG_E_INVALID, SG_E_UNSUPPORTED, SG_E_NOMEM, SG_E_HIP, SG_E_STATE = 0, -1, -2, -3, -4, -5
 
 # every symbol declared in include/sg.h
 EXPORTS = (
-    "sg_last_error", "sg_wheels_per_copy", "sg_ctx_create", "sg_ctx_destroy", "sg_job_bytes",
+    "sg_last_error", "sg_wheels_per_copy", "sg_model_wheels_per_copy", "sg_ctx_create", "sg_ctx_destroy", "sg_job_bytes",
     "sg_job_create", "sg_job_set_betas", "sg_job_sweep", "sg_job_measure", "sg_job_energies",
     "sg_job_field_sums", "sg_job_get_spins", "sg_job_get_wheels", "sg_job_get_perm", "sg_job_get_pt_accepts",
     "sg_job_sweeps_done", "sg_job_debug_rng", "sg_job_destroy", "sg_batch_create",
@@ -59,6 +60,8 @@ def lib():
         L.sg_last_error.restype = C.c_char_p
         L.sg_wheels_per_copy.argtypes = [i32]
         L.sg_wheels_per_copy.restype = i32
+        L.sg_model_wheels_per_copy.argtypes = [i32, i32]
+        L.sg_model_wheels_per_copy.restype = i32
         L.sg_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
         L.sg_ctx_destroy.argtypes = [vp]
         L.sg_job_bytes.argtypes = [C.POINTER(Spec), C.POINTER(u64)]
@@ -88,7 +91,7 @@ def lib():
         L.sg_batch_get_budget.argtypes = [vp, vp, C.POINTER(u64)]
         L.sg_batch_destroy.argtypes = [vp]
         for n in EXPORTS:
-            if n not in ("sg_last_error", "sg_wheels_per_copy"):
+            if n not in ("sg_last_error", "sg_wheels_per_copy", "sg_model_wheels_per_copy"):
                 getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -109,8 +112,8 @@ def _stream(stream):
     return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
 
 
-def wheels_per_copy(L: int) -> int:
-    return int(lib().sg_wheels_per_copy(L))
+def wheels_per_copy(L: int, model: int = ISING) -> int:
+    return int(lib().sg_model_wheels_per_copy(model, L))
 
 
 def job_bytes(spec: Spec) -> int:
@@ -155,8 +158,8 @@ class Job:
         self.model, self.algo, self.L = model, algo, L
         self.S, self.R, self.K = n_samples, n_replicas, K
         self.C = n_samples * n_replicas * K
-        self.N = L ** 3
-        self.NW = wheels_per_copy(L)
+        self.N = L ** (4 if model == GPOTTS4 else 3)
+        self.NW = wheels_per_copy(L, model)
         self.bytes = job_bytes(self.spec)
         if arena is None:
             arena = torch.empty(self.bytes, dtype=torch.uint8, device=f"cuda:{ctx.device}")
@@ -164,10 +167,10 @@ class Job:
         # +-1 couplings as int8; glassy-Potts permutation bytes as uint8 (same
         # width); Ising-like models: rows J_x, J_y, J_z, x, f
         self.ising_spins = model in (ISING, ISING_GEN)
-        J = np.ascontiguousarray(J, dtype=np.uint8 if model == GPOTTS else np.int8)
+        J = np.ascontiguousarray(J, dtype=np.uint8 if model in (GPOTTS, GPOTTS4) else np.int8)
         spins = np.ascontiguousarray(spins, dtype=np.int8 if self.ising_spins else np.uint8)
         wheels = np.ascontiguousarray(wheels, dtype=np.uint32)
-        rows = 5 if model == ISING_GEN else 3
+        rows = {ISING_GEN: 5, GPOTTS4: 4}.get(model, 3)
         assert J.size == self.S * rows * self.N and spins.size == self.C * self.N
         assert wheels.size == self.C * self.NW * 61
         pw = None if ptwheels is None else np.ascontiguousarray(ptwheels, dtype=np.uint32)

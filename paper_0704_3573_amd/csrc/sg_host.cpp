@@ -160,12 +160,18 @@ struct Layout {
 
 static uint64_t al(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
-static bool is_potts(int model) { return model == SG_POTTS || model == SG_GPOTTS; }
+static bool is_potts(int model) { return model == SG_POTTS || model == SG_GPOTTS || model == SG_GPOTTS4; }
+
+// geometry of a model: 4D wheels for the 4D glassy Potts model, else 3D
+static Geom geom_of(int model, int L) { return model == SG_GPOTTS4 ? sg::geom4(L) : sg::geom(L); }
+static uint64_t sites_of(int model, int L) {
+  const uint64_t N = (uint64_t)L * L * L;
+  return model == SG_GPOTTS4 ? N * L : N;
+}
 
 static int check_spec(const sg_job_spec *sp) {
   if (!sp) return fail(SG_E_INVALID, "spec is NULL");
-  if (sp->model != SG_ISING && sp->model != SG_POTTS && sp->model != SG_GPOTTS && sp->model != SG_ISING_GEN)
-    return fail(SG_E_INVALID, "bad model %d", sp->model);
+  if (sp->model < SG_ISING || sp->model > SG_GPOTTS4) return fail(SG_E_INVALID, "bad model %d", sp->model);
   if (sp->algo != SG_METROPOLIS && sp->algo != SG_HEATBATH) return fail(SG_E_INVALID, "bad algo %d", sp->algo);
   if (is_potts(sp->model) && sp->algo != SG_HEATBATH)
     return fail(SG_E_UNSUPPORTED, "the Potts models are built for heat bath only");
@@ -179,6 +185,8 @@ static int check_spec(const sg_job_spec *sp) {
   if (!sg::supported_L(sp->L)) return fail(SG_E_UNSUPPORTED, "L = %d is not built", sp->L);
   if (is_potts(sp->model) && !sg::potts_supported_L(sp->L))
     return fail(SG_E_UNSUPPORTED, "Potts L = %d is not built (L <= 48)", sp->L);
+  if (sp->model == SG_GPOTTS4 && !sg::potts4_supported_L(sp->L))
+    return fail(SG_E_UNSUPPORTED, "4D Potts L = %d is not built (2, 4, 8, 16)", sp->L);
   if (sp->n_samples < 1 || sp->n_replicas < 1 || sp->n_temps < 1)
     return fail(SG_E_INVALID, "S, R, K must be >= 1");
   if (sp->pt_every < 0) return fail(SG_E_INVALID, "pt_every must be >= 0");
@@ -188,9 +196,9 @@ static int check_spec(const sg_job_spec *sp) {
 }
 
 static Layout layout(const sg_job_spec *sp) {
-  const Geom g = sg::geom(sp->L);
+  const Geom g = geom_of(sp->model, sp->L);
   const uint64_t S = sp->n_samples, R = sp->n_replicas, K = sp->n_temps, C = S * R * K;
-  const uint64_t N = (uint64_t)sp->L * sp->L * sp->L;
+  const uint64_t N = sites_of(sp->model, sp->L);
   const uint64_t K1 = K > 1 ? K - 1 : 1;
   Layout l{};
   uint64_t o = 0;
@@ -199,6 +207,7 @@ static Layout layout(const sg_job_spec *sp) {
               (uint64_t)(sp->model == SG_ISING       ? sg::ising_js(sp->L)
                          : sp->model == SG_POTTS     ? sg::potts_js(sp->L)
                          : sp->model == SG_ISING_GEN ? sg::gen_js(sp->L)
+                         : sp->model == SG_GPOTTS4   ? sg::gpotts4_js(sp->L)
                                                      : sg::gpotts_js(sp->L));
   l.wheels_bytes = (uint64_t)g.M * C * g.NW * 4;
   l.spins = o; o = al(o + l.spins_bytes);
@@ -253,6 +262,11 @@ static size_t item_lds(const sg_job *j, int G) {
   // Ising-like: copies, per-copy threshold tables and two counters, scratch copy
   if (j->sp.model == SG_ISING_GEN)
     return (size_t)(G + 1) * j->g.CS * 4 + (size_t)G * (sg::GEN_TAB_STRIDE + 2) * 4;
+  if (j->sp.model == SG_GPOTTS4) {
+    const size_t dummy4 = j->g.NW % 64 ? (size_t)j->g.RHO * j->L * sg::potts4_us(j->L) : 0;
+    return (size_t)48 * 4 + (size_t)G * sg::potts4_lds_copy(j->L) + (size_t)G * sg::POTTS4_W_WORDS * 4 +
+           (size_t)G * 4 + dummy4;
+  }
   const size_t dummy = j->g.NW % 64 ? (size_t)j->g.RHO * j->L * j->L : 0;
   return (size_t)sg::POTTS_TAB_WORDS * 4 + (size_t)G * sg::potts_lds_copy(j->L) +
          (size_t)G * sg::POTTS_W_WORDS * 4 + (size_t)G * 4 + dummy;
@@ -501,6 +515,58 @@ static void pack_gpotts_J(const Geom &g, const uint8_t *P, const int num[256], u
         }
 }
 
+// 4D Potts spins: canonical i = x + L (y + L (z + L u)) -> bytes [y][u][x][z]
+static uint64_t potts4_idx(int L, int x, int y, int z, int u) {
+  return (((uint64_t)y * L + u) * L + x) * L + z;
+}
+
+static void pack_potts4_spins(int L, const uint8_t *s, uint8_t *out) {
+  for (int u = 0; u < L; u++)
+    for (int z = 0; z < L; z++)
+      for (int y = 0; y < L; y++)
+        for (int x = 0; x < L; x++)
+          out[potts4_idx(L, x, y, z, u)] = (uint8_t)(s[x + L * (y + L * (z + (uint64_t)L * u))] << 3);
+}
+
+static void unpack_potts4_spins(int L, const uint8_t *in, uint8_t *s) {
+  for (int u = 0; u < L; u++)
+    for (int z = 0; z < L; z++)
+      for (int y = 0; y < L; y++)
+        for (int x = 0; x < L; x++)
+          s[x + L * (y + L * (z + (uint64_t)L * u))] = (uint8_t)(in[potts4_idx(L, x, y, z, u)] >> 3);
+}
+
+// 4D glassy Potts couplings (P = [4][N] permutation bytes) -> two words per
+// site in wheel draw order (see sg_layout.h)
+static void pack_gpotts4_J(const Geom &g, const uint8_t *P, const int num[256], uint32_t *out) {
+  const int L = g.L;
+  const uint64_t N = (uint64_t)L * L * L * L;
+  auto idx = [&](int x, int y, int z, int u) {
+    return (uint64_t)((x + L) % L) +
+           L * ((uint64_t)((y + L) % L) + L * ((uint64_t)((z + L) % L) + (uint64_t)L * ((u + L) % L)));
+  };
+  for (int p = 0; p < 2; p++)
+    for (int blk = 0; blk < g.NBLK; blk++)
+      for (int kb = 0; kb < g.B; kb++)
+        for (int w = 0; w < g.NW; w++) {
+          const int gr = w / (L * L), u = (w / L) % L, z = w % L;
+          const int y = gr * g.RHO + blk * g.RPB + kb / g.H;
+          const int x = 2 * (kb % g.H) + ((p + y + z + u) & 1);
+          const uint64_t own = idx(x, y, z, u);
+          const uint64_t low[4] = {idx(x - 1, y, z, u), idx(x, y - 1, z, u), idx(x, y, z - 1, u),
+                                   idx(x, y, z, u - 1)};
+          uint32_t w0 = 0, w1 = 0;
+          for (int a = 0; a < 3; a++) {
+            w0 |= (uint32_t)num[P[a * N + own]] << (5 * (2 * a));
+            w0 |= (uint32_t)num[P[a * N + low[a]]] << (5 * (2 * a + 1));
+          }
+          w1 = (uint32_t)num[P[3 * N + own]] | (uint32_t)num[P[3 * N + low[3]]] << 5;
+          const size_t e = ((size_t)(p * g.NBLK + blk) * g.B + kb) * g.NW + w;
+          out[2 * e] = w0;
+          out[2 * e + 1] = w1;
+        }
+}
+
 // wheel words (oldest first) of a state that has drawn k0 numbers -> slots
 static void pack_wheels(const sg_job *j, const uint32_t *wh, uint64_t k0, uint32_t *out) {
   const uint64_t M = j->g.M, NW = j->g.NW, C = j->C, stride = C * NW;
@@ -574,6 +640,11 @@ const char *sg_last_error(void) { return g_err.c_str(); }
 
 int32_t sg_wheels_per_copy(int32_t L) { return sg::supported_L(L) ? sg::geom(L).NW : 0; }
 
+int32_t sg_model_wheels_per_copy(int32_t model, int32_t L) {
+  if (model == SG_GPOTTS4) return sg::potts4_supported_L(L) ? sg::geom4(L).NW : 0;
+  return sg_wheels_per_copy(L);
+}
+
 int sg_ctx_create(int device, sg_ctx **out) {
   GUARD_BEGIN
   if (!out) return fail(SG_E_INVALID, "out is NULL");
@@ -632,14 +703,15 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   if (((uintptr_t)d_arena & 255) != 0) return fail(SG_E_INVALID, "arena must be 256-byte aligned");
   if (lay.spins_bytes >= (1ull << 32) || lay.wheels_bytes >= (1ull << 32) || lay.J_bytes >= (1ull << 32))
     return fail(SG_E_UNSUPPORTED, "job too large for one device buffer (split it into several jobs)");
-  const uint64_t N = (uint64_t)spec->L * spec->L * spec->L;
+  const uint64_t N = sites_of(spec->model, spec->L);
   // validate host inputs
   const uint64_t S = spec->n_samples, R = spec->n_replicas, K = spec->n_temps, C = S * R * K;
   int perm_num[256];
   permutation_numbers(perm_num);
-  if (spec->model == SG_GPOTTS) {
+  if (spec->model == SG_GPOTTS || spec->model == SG_GPOTTS4) {
     const uint8_t *P = (const uint8_t *)J;
-    for (uint64_t i = 0; i < S * 3 * N; i++)
+    const uint64_t dims = spec->model == SG_GPOTTS4 ? 4 : 3;
+    for (uint64_t i = 0; i < S * dims * N; i++)
       if (perm_num[P[i]] < 0) return fail(SG_E_INVALID, "coupling byte %u is not a permutation", P[i]);
   } else if (spec->model == SG_ISING_GEN) {
     for (uint64_t s = 0; s < S; s++)
@@ -678,7 +750,7 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   sg_job *j = new sg_job;
   j->ctx = ctx;
   j->sp = *spec;
-  j->g = sg::geom(spec->L);
+  j->g = geom_of(spec->model, spec->L);
   j->L = spec->L;
   j->S = spec->n_samples;
   j->R = spec->n_replicas;
@@ -708,10 +780,17 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
     HIPCHK(hipMemcpy(j->at<void>(lay.J), jw.data(), lay.J_bytes, hipMemcpyHostToDevice));
   } else {
     std::vector<uint8_t> sp((size_t)C * N);
-    for (uint64_t c = 0; c < C; c++) pack_potts_spins(j->L, (const uint8_t *)spins + c * N, &sp[c * N]);
+    for (uint64_t c = 0; c < C; c++)
+      if (spec->model == SG_GPOTTS4)
+        pack_potts4_spins(j->L, (const uint8_t *)spins + c * N, &sp[c * N]);
+      else
+        pack_potts_spins(j->L, (const uint8_t *)spins + c * N, &sp[c * N]);
     std::vector<uint32_t> jp((size_t)lay.J_bytes / 4);
     if (spec->model == SG_POTTS) {
       for (uint64_t s = 0; s < S; s++) pack_potts_J(j->g, J + s * 3 * N, &jp[s * sg::potts_js(j->L)]);
+    } else if (spec->model == SG_GPOTTS4) {
+      for (uint64_t s = 0; s < S; s++)
+        pack_gpotts4_J(j->g, (const uint8_t *)J + s * 4 * N, perm_num, &jp[s * sg::gpotts4_js(j->L)]);
     } else {
       for (uint64_t s = 0; s < S; s++)
         pack_gpotts_J(j->g, (const uint8_t *)J + s * 3 * N, perm_num, &jp[s * sg::gpotts_js(j->L)]);
@@ -884,6 +963,8 @@ int sg_job_get_spins(sg_job *job, void *out, void *stream) {
   for (int c = 0; c < job->C; c++) {
     if (!is_potts(job->sp.model))
       unpack_ising_spins(job->g, (const uint32_t *)raw.data() + (size_t)c * job->g.CS, (int8_t *)out + (size_t)c * job->N);
+    else if (job->sp.model == SG_GPOTTS4)
+      unpack_potts4_spins(job->L, raw.data() + (size_t)c * job->N, (uint8_t *)out + (size_t)c * job->N);
     else
       unpack_potts_spins(job->L, raw.data() + (size_t)c * job->N, (uint8_t *)out + (size_t)c * job->N);
   }
@@ -975,7 +1056,7 @@ struct PtTable {
 };
 
 // fused launches of a period: one per (model, algorithm)
-static const int NMODEL = 4, NGROUP = 2 * NMODEL;
+static const int NMODEL = 5, NGROUP = 2 * NMODEL;
 
 struct sg_batch {
   sg_ctx *ctx;

@@ -1134,6 +1134,264 @@ __global__ __launch_bounds__(POTTS_MAX_TPB) void gpotts_sweep_kernel(const Work 
   potts_dispatch<true>(w, lds);
 }
 // ---------------------------------------------------------------------------
+// 4D glassy Potts model (Eq. 3 on the hypercubic lattice), heat bath.  The
+// 3D glassy kernel with eight neighbours: lanes serve the wheels of the
+// (z, u) planes, neighbours u +- 1 are one padded u plane (US bytes) away,
+// and each site's eight permutation numbers come in two coupling words (x,
+// y, z in the first, u in the second).  Byte a of the vote sum is
+// 4 h_a <= 32; the weight table holds W[0..8].
+// ---------------------------------------------------------------------------
+template <int L>
+struct Potts4K {
+  static constexpr Geom G4 = geom4(L);
+  static constexpr int M = G4.M, B = G4.B, V = G4.V, NBLK = G4.NBLK, H = G4.H, RPB = G4.RPB,
+                       RHO = G4.RHO, NW = G4.NW;
+  static constexpr int US = potts4_us(L), YS = L * US;  // LDS strides of u and y
+  uint8_t *sp;          // LDS bytes of the lane's copy (layout of sg_layout.h), 8 sigma
+  uint8_t *wp;          // where the lane stores its new spins: sp, or the dummy region
+  const uint32_t *tab;  // LDS vote words: pi (0..23), pi^-1 (24..47)
+  const uint8_t *Wb;    // LDS weight table of the lane's temperature
+  rsrc_t rJ;            // coupling words of the job
+  uint32_t voff;        // byte offset of the lane's coupling words
+  int z, dzp, dzm, dup, dum, g, inplane;  // inplane = u US + z
+  uint32_t nextpat[2 * B];  // coupling words of the next block
+
+  DEV void fetch(int p, int blk) {
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * B) * NW * 8u);
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      nextpat[2 * q] = bload(rJ, voff, s0 + (uint32_t)q * NW * 8u);
+      nextpat[2 * q + 1] = bload(rJ, voff + 4, s0 + (uint32_t)q * NW * 8u);
+    }
+  }
+
+  template <int VI>
+  DEV void block(uint32_t (&ring)[M], int p, int blk) {
+    uint32_t pat[2 * B];
+#pragma unroll
+    for (int q = 0; q < 2 * B; q++) pat[q] = nextpat[q];
+    if (blk + 1 < NBLK)
+      fetch(p, blk + 1);
+    else
+      fetch(p ^ 1, 0);
+    rows<VI>(ring, pat, p, g * RHO + blk * RPB, sp, wp, tab, Wb);
+  }
+
+  // Offsets of row y's site j = 0 (x = e) of the lane's (z, u) plane, of the
+  // x neighbour that wraps (x = L - 1 for e = 0, x = 0 for e = 1; it is also
+  // the non-wrapping x+ of j = H - 1, e = 0 and x- of j = 0, e = 1) and of
+  // the y neighbours; site j is 2 j L further.
+  DEV void row_offsets(int p, int y, int &own, int &bxw, int &byp, int &bym) const {
+    const int e = (p + y + g_parity) & 1;
+    const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+    own = y * YS + inplane + e * L;
+    bxw = e ? own - L : own + (L - 1) * L;
+    byp = own + (yp - y) * YS;
+    bym = own + (ym - y) * YS;
+  }
+  int g_parity;  // (z + u) & 1
+
+  // Same pipeline as the 3D kernels: neighbour bytes and vote words of site
+  // n + 2, fields and weight reads of site n + 1, draw and store of site n.
+  template <int VI>
+  DEV void rows(uint32_t (&ring)[M], const uint32_t (&pat)[2 * B], int p, int y0,
+                const uint8_t *__restrict__ rd, uint8_t *__restrict__ wr,
+                const uint32_t *__restrict__ tb, const uint8_t *__restrict__ wt) const {
+    int own[RPB], bxw[RPB], byp[RPB], bym[RPB];
+#pragma unroll
+    for (int rr = 0; rr < RPB; rr++) row_offsets(p, y0 + rr, own[rr], bxw[rr], byp[rr], bym[rr]);
+    uint32_t nb[B][8], rb[B][8], w[B][4];
+
+    auto request_site = [&](int kb) {
+      const int rr = kb / H, j = kb - rr * H, o = 2 * j * L;
+      const uint32_t w0 = pat[2 * kb], w1 = pat[2 * kb + 1];
+#pragma unroll
+      for (int d = 0; d < 6; d++) rb[kb][d] = tb[(d & 1) * 24 + ((w0 >> (5 * d)) & 31u)];
+      rb[kb][6] = tb[w1 & 31u];
+      rb[kb][7] = tb[24 + ((w1 >> 5) & 31u)];
+      const int s = own[rr] + o;
+      nb[kb][0] = rd[j == H - 1 ? bxw[rr] : s + L];
+      nb[kb][1] = rd[j == 0 ? bxw[rr] : s - L];
+      nb[kb][2] = rd[byp[rr] + o];
+      nb[kb][3] = rd[bym[rr] + o];
+      nb[kb][4] = rd[s + dzp];
+      nb[kb][5] = rd[s + dzm];
+      nb[kb][6] = rd[s + dup];
+      nb[kb][7] = rd[s + dum];
+    };
+    auto request_weights = [&](int kb) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int d = 0; d < 8; d++) c += 4u << ((rb[kb][d] >> nb[kb][d]) & 31u);
+      const uint32_t c0 = c & 0xFFu, c1 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c3 = c >> 24;
+      const uint8_t *wm = wt + max(max(c0, c3), max(c2, c1));
+      w[kb][0] = *(const uint32_t *)(wm - c0);
+      w[kb][1] = *(const uint32_t *)(wm - c1);
+      w[kb][2] = *(const uint32_t *)(wm - c2);
+      w[kb][3] = *(const uint32_t *)(wm - c3);
+    };
+    auto finish_site = [&](int kb) {
+      const int rr = kb / H, j = kb - rr * H;
+      const int k = VI * B + kb;  // ring slot (static)
+      ring[k % M] = ring[(k + M - 24) % M] + ring[(k + M - 55) % M];
+      const uint32_t r = ring[k % M] ^ ring[(k + M - 61) % M];
+      const uint32_t C1 = w[kb][0] + w[kb][1], C2 = C1 + w[kb][2];
+      const uint32_t t = __umulhi(r, C2 + w[kb][3]);
+      uint32_t v = t >= w[kb][0] ? 8u : 0u;
+      v = t >= C1 ? 16u : v;
+      v = t >= C2 ? 24u : v;
+      wr[own[rr] + 2 * j * L] = (uint8_t)v;
+    };
+
+    request_site(0);
+    if constexpr (B > 1) request_site(1);
+    __builtin_amdgcn_sched_barrier(0);
+    request_weights(0);
+#pragma unroll
+    for (int kb = 0; kb < B; kb++) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (kb + 2 < B) request_site(kb + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kb + 1 < B) request_weights(kb + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      finish_site(kb);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // sum over the lane's colour-0 sites of the number of its eight bonds whose
+  // term is 1 (every bond joins a colour-0 and a colour-1 site)
+  DEV int lane_bond_sum() const {
+    int hsum = 0;
+    for (int blk = 0; blk < NBLK; blk++) {
+      const int y0 = g * RHO + blk * RPB;
+      for (int kb = 0; kb < B; kb++) {
+        const int rr = kb / H, j = kb - rr * H, o = 2 * j * L;
+        int own, bxw, byp, bym;
+        row_offsets(0, y0 + rr, own, bxw, byp, bym);
+        const int s = own + o;
+        const int nbo[8] = {j == H - 1 ? bxw : s + L, j == 0 ? bxw : s - L, byp + o, bym + o,
+                            s + dzp, s + dzm, s + dup, s + dum};
+        const uint32_t el = voff + (uint32_t)((blk * B + kb) * NW) * 8u;
+        const uint32_t w0 = bload(rJ, el), w1 = bload(rJ, el + 4);
+        const uint32_t si = sp[s];
+        for (int d = 0; d < 8; d++) {
+          const uint32_t num = d < 6 ? (w0 >> (5 * d)) & 31u : (w1 >> (5 * (d - 6))) & 31u;
+          const uint32_t vote = tab[(d & 1) * 24 + num];
+          hsum += ((vote >> sp[nbo[d]]) & 31u) == si;
+        }
+      }
+    }
+    return hsum;
+  }
+};
+
+template <int L>
+DEV void potts4_run(const Work &w, uint32_t *lds) {
+  using K4 = Potts4K<L>;
+  constexpr int N4 = L * L * L * L;
+  constexpr int CW = potts4_lds_copy(L) / 4;  // LDS words per copy
+  constexpr int L2 = L * L, UW = potts4_us(L) / 4;  // HBM u-plane bytes, LDS u-plane words
+  const int t = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int lanes = w.ncopies * K4::NW;
+  const bool active = t < lanes;
+  uint32_t *tab = lds;                                   // [48] vote words
+  uint32_t *cp = lds + 48;                               // [ncopies][CW] spins
+  uint32_t *Wt = cp + w.ncopies * CW;                    // [ncopies][POTTS4_W_WORDS]
+  int *Hcnt = (int *)(Wt + w.ncopies * POTTS4_W_WORDS);  // [ncopies]
+  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);        // RHO L US bytes if NW % 64 != 0
+  const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
+  const uint32_t sbase = (uint32_t)w.copy0 * N4;
+  // vote words of the 24 permutations (lexicographic order): pi, then pi^-1
+  for (int i = t; i < 48; i += nthr) {
+    const int k = i % 24;
+    int avail[4] = {0, 1, 2, 3}, pi[4], inv[4];
+    const int digit[3] = {k / 6, (k / 2) % 3, k % 2};
+    int left = 4;
+    for (int v = 0; v < 4; v++) {
+      const int c = v < 3 ? digit[v] : 0;
+      pi[v] = avail[c];
+      for (int q = c; q + 1 < left; q++) avail[q] = avail[q + 1];
+      left--;
+    }
+    for (int v = 0; v < 4; v++) inv[pi[v]] = v;
+    uint32_t word = 0;
+    for (int v = 0; v < 4; v++) word |= (uint32_t)(8 * (i < 24 ? pi[v] : inv[v])) << (8 * v);
+    tab[i] = word;
+  }
+  // HBM word q of a copy ([y][u][x][z], u planes L^2 bytes apart) -> LDS
+  // (u planes potts4_us(L) bytes apart)
+  for (int i = t; i < w.ncopies * (N4 / 4); i += nthr) {
+    const int c = i / (N4 / 4), q = i - c * (N4 / 4);
+    const int yu = q / (L2 / 4), r = q - yu * (L2 / 4);
+    cp[c * CW + yu * UW + r] = bload(rsp, i * 4, sbase);
+  }
+  for (int i = t; i < w.ncopies * POTTS4_W_WORDS; i += nthr) {
+    const int c = w.copy0 + i / POTTS4_W_WORDS;
+    Wt[i] = w.thr[w.temp_of_slot[c] * THR_WORDS + i % POTTS4_W_WORDS];
+  }
+  for (int i = t; i < w.ncopies; i += nthr) Hcnt[i] = 0;
+
+  // lanes without a wheel run the blocks of wheel (z = t mod L, u = 0, row
+  // group 0) of the first copy and store into the dummy region
+  K4 k;
+  const int cl = active ? t / K4::NW : 0;
+  const int wl = active ? t - cl * K4::NW : t % L;
+  const int copy = w.copy0 + cl;
+  k.sp = (uint8_t *)(cp + cl * CW);
+  k.wp = active ? k.sp : dummy;
+  k.tab = tab;
+  k.Wb = (const uint8_t *)(Wt + cl * POTTS4_W_WORDS);
+  const int u = (wl / L) % L;
+  k.g = wl / L2;
+  k.z = wl % L;
+  k.g_parity = (k.z + u) & 1;
+  k.inplane = u * K4::US + k.z;
+  k.dzp = k.z + 1 == L ? 1 - L : 1;
+  k.dzm = k.z == 0 ? L - 1 : -1;
+  k.dup = u + 1 == L ? (1 - L) * K4::US : K4::US;
+  k.dum = u == 0 ? (L - 1) * K4::US : -K4::US;
+  k.rJ = make_rsrc(w.J, w.J_bytes);
+  k.voff = ((uint32_t)(copy / w.RK) * gpotts4_js(L) + 2 * wl) * 4u;
+
+  Drive d;
+  d.nsweeps = w.nsweeps_cap;
+  d.active = active;
+  d.rwh = make_rsrc(w.wheels, w.wheels_bytes);
+  d.wstride = (uint32_t)w.C * K4::NW * 4u;
+  d.widx = ((uint32_t)copy * K4::NW + wl) * 4u;
+  d.kmod = (int)__builtin_amdgcn_readfirstlane((uint32_t)((*w.done * (uint64_t)(K4::RHO * L)) % K4::M));
+  __syncthreads();
+  k.fetch(0, 0);
+  drive(k, d);
+
+  if (active) atomicAdd(&Hcnt[cl], k.lane_bond_sum());
+  __syncthreads();
+  if (w.nsweeps_cap > 0)
+    for (int i = t; i < w.ncopies * (N4 / 4); i += nthr) {
+      const int c = i / (N4 / 4), q = i - c * (N4 / 4);
+      const int yu = q / (L2 / 4), r = q - yu * (L2 / 4);
+      bstore(rsp, cp[c * CW + yu * UW + r], i * 4, sbase);
+    }
+  for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = -(int64_t)Hcnt[i];
+}
+
+__global__ __launch_bounds__(POTTS_MAX_TPB) void gpotts4_sweep_kernel(const Work *__restrict__ works,
+                                                                      int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  switch (w.L) {
+    case 2: potts4_run<2>(w, lds); break;
+    case 4: potts4_run<4>(w, lds); break;
+    case 8: potts4_run<8>(w, lds); break;
+    case 16: potts4_run<16>(w, lds); break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Overlap between replica 0 and replica 1 at every temperature.
 //   Ising: Q = N - 2 popcount(a xor b) over the packed words (pads are zero);
 //   Ising-like models: over occupied sites, Q = sum popcount(X) -
@@ -1390,7 +1648,9 @@ hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st) {
 hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, int tpb,
                         size_t lds, int nsweeps, hipStream_t st) {
   if (nworks <= 0) return hipSuccess;
-  if (model == 3 && algo == 0)
+  if (model == 4)
+    hipLaunchKernelGGL(gpotts4_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == 3 && algo == 0)
     hipLaunchKernelGGL(gen_sweep_kernel<0>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == 3)
     hipLaunchKernelGGL(gen_sweep_kernel<1>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
@@ -1410,6 +1670,9 @@ hipError_t set_max_lds(int bytes) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)gpotts_sweep_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)gpotts4_sweep_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)gen_sweep_kernel<0>,

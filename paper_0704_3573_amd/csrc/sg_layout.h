@@ -84,6 +84,49 @@ SG_HD constexpr int potts_js(int L) { return 2 * geom(L).NBLK * potts_bq(L) * ge
 // site itself, for d odd the bond stored at the neighbour.
 SG_HD constexpr int gpotts_js(int L) { return 2 * geom(L).NBLK * geom(L).B * geom(L).NW; }
 
+// 4D glassy Potts model (Eq. 3 on the hypercubic lattice of side L, site
+// i = x + L (y + L (z + L u))): one wheel per (z, u, group of rho rows),
+// index (g L + u) L + z, drawing for its rows in the 3D order (colour, row,
+// x).  Blocks hold at most 8 draws (each site needs two coupling words,
+// prefetched a block ahead).
+SG_HD constexpr Geom geom4(int L) {
+  Geom g{};
+  g.L = L;
+  g.RHO = L < 8 ? L : 8;
+  g.NG = L / g.RHO;
+  g.NW = L * L * g.NG;
+  g.H = L / 2;
+  int r = g.H >= 8 ? 1 : 8 / g.H;
+  g.RPB = r < g.RHO ? r : g.RHO;
+  g.B = g.RPB * g.H;
+  g.NBLK = g.RHO / g.RPB;
+  g.NWB = g.L / g.RPB;
+  g.WZ = g.NWB | 1;
+  g.CS = 0;
+  g.V = (62 + g.B - 1) / g.B;
+  g.V += g.V & 1;
+  g.M = g.V * g.B;
+  return g;
+}
+
+SG_HD constexpr bool potts4_supported_L(int L) { return L == 2 || L == 4 || L == 8 || L == 16; }
+
+// 4D copy: one byte per site holding 8 sigma, ordered [y][u][x][z] (z
+// fastest).  In HBM the u planes are L^2 bytes apart; in LDS each u plane
+// is padded to potts4_us(L) bytes, so that the lanes of a wave (consecutive
+// z, then u) reading sites of both x parities (L bytes apart) touch a window
+// of 2L bytes per u plane and the windows of the wave's u planes fall on
+// distinct LDS banks.
+SG_HD constexpr int potts4_us(int L) { return L * L + (L == 16 ? 32 : (L == 8 ? 16 : 0)); }
+SG_HD constexpr int potts4_lds_copy(int L) { return L * L * potts4_us(L); }
+// Couplings: per site two words in draw order, element
+// ((p NBLK + blk) B + k) NW + wheel (8 bytes): word 0 holds the permutation
+// numbers of directions x+, x-, y+, y-, z+, z- (bits 5d..5d+4, as in 3D),
+// word 1 those of u+ (bits 0..4) and u- (bits 5..9).
+SG_HD constexpr int gpotts4_js(int L) { return 4 * geom4(L).NBLK * geom4(L).B * geom4(L).NW; }
+// Weights W[0..8] are used (h_a in 0..8); 12 words per copy.
+constexpr int POTTS4_W_WORDS = 12;
+
 // Potts work items: at most 512 lanes per workgroup (the kernel keeps up to
 // 256 VGPRs per lane).  LDS = the 64-entry rotation-base table (6 words per
 // coupling pattern at an odd stride of 7 words, so that lanes reading

@@ -6,7 +6,8 @@ import oracle
 from paper_0704_3573_amd import inputs
 
 MODELS = {"ising": oracle.ISING, "potts": oracle.POTTS, "gpotts": oracle.GPOTTS,
-          "rfim": oracle.ISING_GEN, "daff": oracle.ISING_GEN, "isinggen": oracle.ISING_GEN}
+          "rfim": oracle.ISING_GEN, "daff": oracle.ISING_GEN, "isinggen": oracle.ISING_GEN,
+          "gpotts4": oracle.GPOTTS4}
 
 
 def instance(model, L, S=1, R=1, K=1, seed=1, sample0=0):

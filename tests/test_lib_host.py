@@ -28,6 +28,10 @@ def test_wheels_per_copy():
     for L, nw in ((2, 2), (4, 4), (8, 8), (16, 32), (24, 72), (32, 128), (48, 288), (64, 512)):
         assert B.wheels_per_copy(L) == nw
     assert B.wheels_per_copy(12) == 0 and B.wheels_per_copy(72) == 0
+    # 4D glassy Potts: one wheel per (z, u, row group)
+    for L, nw in ((2, 4), (4, 16), (8, 64), (16, 512)):
+        assert B.wheels_per_copy(L, B.GPOTTS4) == nw
+    assert B.wheels_per_copy(24, B.GPOTTS4) == 0
 
 
 def test_glassy_potts_job_bytes():
@@ -50,6 +54,13 @@ def test_ising_like_job_bytes():
     assert B.job_bytes(B.Spec(B.ISING_GEN, B.HEATBATH, 4, 8, 1, 2, 1, 10, 0.0)) > 0
 
 
+def test_4d_glassy_potts_job_bytes():
+    # L = 16 in 4D: 65536 bytes of spins per copy, two coupling words per
+    # site and sample, 512 wheels per copy
+    b = B.job_bytes(B.Spec(B.GPOTTS4, B.HEATBATH, 4, 16, 2, 2, 1, 0))
+    assert 4 * 16 ** 4 + 2 * 8 * 16 ** 4 + 4 * 512 * 64 * 4 < b < 3_000_000
+
+
 def test_job_bytes_and_validation():
     n = B.job_bytes(B.Spec(B.ISING, B.METROPOLIS, 4, 64, 1, 2, 1, 0))
     # two copies of 64^3 bit-packed spins, shared couplings, 512 wheels x 64 slots each
@@ -65,12 +76,15 @@ def test_job_bytes_and_validation():
         (B.Spec(B.GPOTTS, B.METROPOLIS, 4, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
         (B.Spec(B.GPOTTS, B.HEATBATH, 3, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
         (B.Spec(B.GPOTTS, B.HEATBATH, 4, 56, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
-        (B.Spec(4, B.HEATBATH, 4, 8, 1, 1, 1, 0), B.SG_E_INVALID),
         (B.Spec(B.ISING_GEN, B.METROPOLIS, 4, 8, 1, 1, 1, 0, -0.5), B.SG_E_INVALID),
         (B.Spec(B.ISING_GEN, B.HEATBATH, 4, 8, 1, 1, 1, 0, float("inf")), B.SG_E_INVALID),
         (B.Spec(B.ISING_GEN, B.HEATBATH, 4, 8, 1, 1, 1, 0, float("nan")), B.SG_E_INVALID),
         (B.Spec(B.ISING_GEN, B.METROPOLIS, 4, 8, 1, 2, 4, 10, 1.0), B.SG_E_UNSUPPORTED),
         (B.Spec(B.ISING_GEN, B.METROPOLIS, 4, 12, 1, 1, 1, 0, 1.0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.GPOTTS4, B.METROPOLIS, 4, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.GPOTTS4, B.HEATBATH, 4, 24, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(B.GPOTTS4, B.HEATBATH, 3, 8, 1, 1, 1, 0), B.SG_E_UNSUPPORTED),
+        (B.Spec(5, B.HEATBATH, 4, 8, 1, 1, 1, 0), B.SG_E_INVALID),
     ):
         with pytest.raises(B.SgError) as e:
             B.job_bytes(spec)
