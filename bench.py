@@ -155,14 +155,17 @@ def cpu_baseline(budget_s=15.0):
 
 
 def potts_c4(ctx, B, inputs, np, torch, stream, sweeps, model="potts"):
-    """q = 4 Potts heat bath, L = 16 and 32, 128 samples x 2 replicas:
-    updates/ns over periods of `sweeps` sweeps (one launch each), wall clock
-    and HIP-event kernel time.  model "potts": the +-J glass at T = 0.9;
+    """q = 4 Potts heat bath, 128 samples x 2 replicas: updates/ns over
+    periods of `sweeps` sweeps (one launch each), wall clock and HIP-event
+    kernel time.  model "potts": the +-J glass at T = 0.9, L = 16 and 32;
     "gpotts": the glassy (permutation) model of Eq. 3 at beta = 2.4, the
-    paper's 3D Potts temperature."""
+    paper's 3D Potts temperature, L = 16 and 32; "gpotts4": the glassy model
+    in 4D at beta = 1.405, the paper's 4D temperature, L = 16."""
     out = {}
-    mid, beta, seed = (B.POTTS, 1 / 0.9, 4000) if model == "potts" else (B.GPOTTS, 2.4, 4100)
-    for L in (16, 32):
+    mid, beta, seed, Ls = {"potts": (B.POTTS, 1 / 0.9, 4000, (16, 32)),
+                           "gpotts": (B.GPOTTS, 2.4, 4100, (16, 32)),
+                           "gpotts4": (B.GPOTTS4, 1.405, 4600, (16,))}[model]
+    for L in Ls:
         inst = inputs.make_instance(model, L, 128, 2, 1, seed=seed)
         job = B.Job(ctx, mid, B.HEATBATH, L, [beta], inst["J"], inst["spins"],
                     inst["wheels"], n_samples=128, n_replicas=2)
@@ -191,6 +194,14 @@ def potts_c4(ctx, B, inputs, np, torch, stream, sweeps, model="potts"):
     if model == "potts":
         out["workload"] = (f"q=4 +-J Potts glass, 128 samples x 2 replicas, heat bath T=0.9, "
                            f"period = {sweeps} sweeps (one launch)")
+    elif model == "gpotts4":
+        out["workload"] = (f"q=4 glassy Potts model (Eq. 3) on the 4D hypercubic lattice, L=16, "
+                           f"128 samples x 2 replicas, heat bath beta=1.405, period = {sweeps} "
+                           f"sweeps (one launch)")
+        # the paper's 4D glassy Potts rates (L = 16): 64 ps/spin (LX200),
+        # 125 ps/spin (LX160), 150 ns/spin (PC)
+        out["paper_updates_per_ns"] = {"Virtex4-LX200": 15.625, "Virtex4-LX160": 8.0,
+                                       "PC": round(1 / 150, 5)}
     else:
         out["workload"] = (f"q=4 glassy Potts model (random permutation couplings, Eq. 3), "
                            f"128 samples x 2 replicas, heat bath beta=2.4, period = {sweeps} "
@@ -365,6 +376,8 @@ def main():
         log(f"[bench] Potts only: {potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps)}")
         log("[bench] glassy Potts only: "
             f"{potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps, 'gpotts')}")
+        log("[bench] 4D glassy Potts only: "
+            f"{potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps, 'gpotts4')}")
         return
 
     # ------------------------------------------------ batched (headline) --
@@ -443,6 +456,8 @@ def main():
         if args.potts_sweeps > 0 else None
     glassy = potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps, "gpotts") \
         if args.potts_sweeps > 0 else None
+    glassy4d = potts_c4(ctx, B, inputs, np, torch, stream, args.potts_sweeps, "gpotts4") \
+        if args.potts_sweeps > 0 else None
 
     isinglike = ising_like(ctx, B, inputs, np, torch, stream, args.gen_sweeps) \
         if args.gen_sweeps > 0 else None
@@ -504,6 +519,7 @@ def main():
         "speedup_batched_over_plain": round(value / plain_value, 2),
         "potts_c4": potts,
         "glassy_potts": glassy,
+        "glassy_potts_4d": glassy4d,
         "ising_like": isinglike,
         "equilibration": eq,
         "serving": serving_stats,
