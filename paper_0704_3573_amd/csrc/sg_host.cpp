@@ -310,6 +310,30 @@ static void make_items(const sg_job *j, int G, std::vector<Work> &out) {
   }
 }
 
+// Work items of one launch are dealt to the 8 XCDs round-robin by workgroup
+// index, and each XCD has its own L2.  Items reading the same sample's
+// couplings (consecutive in the list) are put on one XCD so that its L2
+// serves the second reader: within each run of equal-size items (the list
+// stays sorted by size), the run is cut into 8 contiguous parts and part x
+// fills the run's positions p with p mod 8 = x.  Results do not depend on
+// the order of the items.
+static uint64_t work_size(const Work &w) { return (uint64_t)w.ncopies * w.L * w.L * w.L; }
+
+static void xcd_order(std::vector<Work> &v) {
+  const size_t NX = 8;
+  size_t i = 0;
+  while (i < v.size()) {
+    size_t j = i;
+    while (j < v.size() && work_size(v[j]) == work_size(v[i])) j++;
+    const std::vector<Work> run(v.begin() + i, v.begin() + j);
+    size_t r = 0;
+    for (size_t x = 0; x < NX; x++)
+      for (size_t p = i; p < j; p++)
+        if (p % NX == x) v[p] = run[r++];
+    i = j;
+  }
+}
+
 static const int PT_FUSED_KMAX = 64;
 
 static void make_pt_works(const sg_job *j, std::vector<PtWork> &out) {
@@ -831,6 +855,7 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
     return fail(SG_E_UNSUPPORTED, "one copy of L = %d needs more LDS than the device offers", spec->L);
   }
   make_items(j, G, j->works);
+  xcd_order(j->works);
   j->tpb = ((G * j->g.NW + 63) / 64) * 64;
   j->lds = item_lds(j, G);
   HIPCHK(hipMemcpy(j->at<void>(lay.works), j->works.data(), j->works.size() * sizeof(Work), hipMemcpyHostToDevice));
@@ -1138,8 +1163,10 @@ static int plan(sg_batch *b) {
   for (auto &a : b->items)
     for (auto &v : a)
       std::stable_sort(v.begin(), v.end(), [](const Work &x, const Work &y) {
-        return (uint64_t)x.ncopies * x.L * x.L * x.L > (uint64_t)y.ncopies * y.L * y.L * y.L;
+        return work_size(x) > work_size(y);
       });
+  for (auto &a : b->items)
+    for (auto &v : a) xcd_order(v);
   for (auto &a : b->items)
     for (auto &v : a) total += v.size();
   if (total > b->d_items_cap) {
