@@ -268,6 +268,49 @@ DEV void hb_s4(uint64_t m2, uint64_t m1, uint64_t m0, uint32_t &b2, uint32_t &b1
                : "vcc");
 }
 
+// (a & m) | c with the mask in a scalar register (one instruction).
+DEV uint32_t and_or(uint32_t a, uint32_t m, uint32_t c) {
+  uint32_t r;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(m), "v"(c));
+  return r;
+}
+
+// base + byte n of x (one instruction; n is a compile-time constant).
+DEV uint32_t add_byte(int n, uint32_t base, uint32_t x) {
+  uint32_t r;
+  switch (n) {
+    case 0:
+      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+          : "=v"(r) : "v"(base), "v"(x));
+      break;
+    case 1:
+      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+          : "=v"(r) : "v"(base), "v"(x));
+      break;
+    case 2:
+      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+          : "=v"(r) : "v"(base), "v"(x));
+      break;
+    default:
+      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+          : "=v"(r) : "v"(base), "v"(x));
+      break;
+  }
+  return r;
+}
+
+// LDS words addressed by 32-bit byte offsets.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+DEV uint32_t lds_offset(const uint32_t *p) { return (uint32_t)(uintptr_t)(lds_u32 *)p; }
+
+// Single compare-result insert: acc = 2 acc + c (first: acc = c).
+DEV void ins1(bool first, uint64_t m, uint32_t &acc) {
+  if (first)
+    asm volatile("v_addc_co_u32 %[a], vcc, 0, 0, %[m]" : [a] "=&v"(acc) : [m] "s"(m) : "vcc");
+  else
+    asm volatile("v_addc_co_u32 %[a], vcc, %[a], %[a], %[m]" : [a] "+v"(acc) : [m] "s"(m) : "vcc");
+}
+
 // One block: B draws of the lane's wheel at ring phase VI, one per site.
 // The block's LDS and coupling loads are issued first; the B ALU-only draw
 // steps then cover their latency before the bit-sliced logic consumes them.
@@ -473,6 +516,100 @@ struct IsingK {
   }
 };
 
+// Metropolis with a per-copy threshold table (the LUT of the paper's update
+// cell).  The number n of unsatisfied bonds of every site of the block is
+// counted bit-sliced before the draws; each draw is compared with T[n mod 4]
+// read from the copy's 4-word LDS table at byte offset 4 (n mod 4) (the two
+// low count planes transposed into bytes, one byte-select add per site), and
+// the flips that are certain in advance (n >= 3, dE <= 0; or n >= m when the
+// thresholds from m on equal 2^32, beta ~ 0) are one bit-sliced compare per
+// block.  Per draw: add, xor, compare, insert and the address add.  The
+// block's couplings are loaded one block ahead.
+template <int L>
+struct IsingMetK {
+  using G = GC<L>;
+  static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK;
+  IsingLane ln;
+  const uint32_t *tab;  // LDS table of the lane's copy: T[0], T[1], T[2], 0
+  uint32_t mlo, mhi;    // limit m in 0..3 of the certain flips, bits as lane masks
+  uint32_t nextJ[6];    // coupling words of the next block
+
+  DEV void fetch(int p, int blk) { ising_couplings<L>(ln, p, blk, nextJ); }
+
+  template <int VI>
+  DEV void block(uint32_t (&ring)[M], int p, int blk) {
+    uint32_t Jw[6];
+#pragma unroll
+    for (int d = 0; d < 6; d++) Jw[d] = nextJ[d];
+    if (blk + 1 < NBLK)
+      fetch(p, blk + 1);
+    else
+      fetch(p ^ 1, 0);
+    uint32_t S, N[6];
+    uint32_t *own;
+    ising_neighbours<L>(ln, p, blk, S, N, own);
+    uint32_t n0, n1, n2;
+    {
+      uint32_t u[6];
+#pragma unroll
+      for (int d = 0; d < 6; d++) u[d] = S ^ N[d] ^ Jw[d];
+      count6(u, n0, n1, n2);
+    }
+    // n >= m  <=>  n2 or (n1, n0) >= (mhi, mlo)
+    const uint32_t below = bfi(n1 ^ mhi, mhi, ~n0 & mlo);
+    const uint32_t cert = n2 | ~below;
+    // byte j of word w = 4 (n mod 4) of the site at bit w + 8 j
+    uint32_t Kw[8];
+#pragma unroll
+    for (int w = 0; w < 8; w++) {
+      const uint32_t a = 2 >= w ? n0 << (2 - w) : n0 >> (w - 2);
+      const uint32_t b = 3 >= w ? n1 << (3 - w) : n1 >> (w - 3);
+      Kw[w] = and_or(a, 0x04040404u, b & 0x08080808u);
+    }
+    const uint32_t tbase = lds_offset(tab);
+    uint32_t T[B];
+    // threshold of draw i (site at bit B - 1 - i), read PF draws ahead
+    auto load = [&](int i) {
+      const int q = B - 1 - i;
+      T[i] = *(const lds_u32 *)(uintptr_t)add_byte(q >> 3, tbase, Kw[q & 7]);
+    };
+    constexpr int PF = B < 8 ? B : 8;
+#pragma unroll
+    for (int i = 0; i < PF; i++) load(i);
+    __builtin_amdgcn_sched_barrier(0);
+
+    static_assert(B >= 2, "the draw pipeline needs two draws per block");
+    uint32_t acc = 0, r;
+    uint64_t m[B];
+    auto s1 = [&](int i) {
+      const int k = VI * B + i;  // static after unrolling
+      met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
+             T[i], r, m[i]);
+    };
+    s1(0);
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+      if (i + PF < B) load(i + PF);
+      if (i + 1 < B)
+        s1(i + 1);
+      else
+        asm volatile("s_nop 1");
+      ins1(i == 0, m[i], acc);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    *own = S ^ ((cert | acc) & G::MB);
+  }
+};
+
+template <int L, int ALGO>
+struct IsingKernelOf {
+  using type = IsingK<L, ALGO>;
+};
+template <int L>
+struct IsingKernelOf<L, 0> {
+  using type = IsingMetK<L>;
+};
+
 template <int L, int ALGO>
 DEV void ising_run(const Work &w, uint32_t *lds) {
   using G = GC<L>;
@@ -482,16 +619,23 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   const bool active = t < lanes;
   int *Ucnt = (int *)(lds + w.ncopies * G::CS);
   uint32_t *scratch_copy = lds + w.ncopies * G::CS + w.ncopies;  // CS words
+  uint32_t *tabs = scratch_copy + G::CS;  // Metropolis: [ncopies][ISING_TAB_STRIDE]
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
 
-  // stage the copies in LDS
+  // stage the copies (and the Metropolis threshold tables) in LDS
   const uint32_t sbase = (uint32_t)w.copy0 * G::CS * 4u;
   for (int i = t; i < w.ncopies * G::CS; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
   for (int i = t; i < w.ncopies; i += nthr) Ucnt[i] = 0;
+  if constexpr (ALGO == 0)
+    for (int i = t; i < w.ncopies * 4; i += nthr) {
+      const int c = i >> 2, e = i & 3;
+      tabs[c * ISING_TAB_STRIDE + e] =
+          e < 3 ? w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + e] : 0u;
+    }
 
   // lanes without a wheel serve wheel (z = t mod L, row group 0) of the
   // scratch copy, so all their accesses stay inside it
-  IsingK<L, ALGO> k;
+  typename IsingKernelOf<L, ALGO>::type k;
   IsingLane &ln = k.ln;
   const int cl = active ? t / G::NW : 0;
   const int wl = active ? t - cl * G::NW : t % L;
@@ -512,7 +656,16 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
     for (int q = 0; q < 7; q++) ln.T[q] = tr[q];
     ln.A = tr[15];
   }
-  k.any_always = __any(active && ln.A != 0);
+  if constexpr (ALGO == 0) {
+    // certain flips from n = m on: m = 3 (dE <= 0), or the first n whose
+    // threshold is 2^32 (thresholds grow with n)
+    const int m = ln.A ? min(3, __ffs(ln.A) - 1) : 3;
+    k.mlo = (m & 1) ? ~0u : 0u;
+    k.mhi = (m & 2) ? ~0u : 0u;
+    k.tab = tabs + cl * ISING_TAB_STRIDE;
+  } else {
+    k.any_always = __any(active && ln.A != 0);
+  }
 
   Drive d;
   d.nsweeps = w.nsweeps_cap;
@@ -522,6 +675,7 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   d.widx = ((uint32_t)copy * G::NW + wl) * 4u;
   d.kmod = (int)__builtin_amdgcn_readfirstlane((uint32_t)((*w.done * (uint64_t)(G::RHO * L)) % G::M));
   __syncthreads();
+  if constexpr (ALGO == 0) k.fetch(0, 0);
   drive(k, d);
 
   // energy of every copy, then write back the spins
@@ -585,49 +739,6 @@ DEV void gen_classify(uint32_t S, const uint32_t N[6], const uint32_t Jw[GEN_WOR
   fadd(e2, g1, e1 & g0, P[2], c2);
   P[3] = g2 | c2;
   P[4] = MET ? (S ^ Jw[13]) : Jw[13];
-}
-
-// (a & m) | c with the mask in a scalar register (one instruction).
-DEV uint32_t and_or(uint32_t a, uint32_t m, uint32_t c) {
-  uint32_t r;
-  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(m), "v"(c));
-  return r;
-}
-
-// base + byte n of x (one instruction; n is a compile-time constant).
-DEV uint32_t add_byte(int n, uint32_t base, uint32_t x) {
-  uint32_t r;
-  switch (n) {
-    case 0:
-      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
-          : "=v"(r) : "v"(base), "v"(x));
-      break;
-    case 1:
-      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
-          : "=v"(r) : "v"(base), "v"(x));
-      break;
-    case 2:
-      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
-          : "=v"(r) : "v"(base), "v"(x));
-      break;
-    default:
-      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
-          : "=v"(r) : "v"(base), "v"(x));
-      break;
-  }
-  return r;
-}
-
-// LDS words addressed by 32-bit byte offsets.
-typedef __attribute__((address_space(3))) const uint32_t lds_u32;
-DEV uint32_t lds_offset(const uint32_t *p) { return (uint32_t)(uintptr_t)(lds_u32 *)p; }
-
-// Single compare-result insert: acc = 2 acc + c (first: acc = c).
-DEV void ins1(bool first, uint64_t m, uint32_t &acc) {
-  if (first)
-    asm volatile("v_addc_co_u32 %[a], vcc, 0, 0, %[m]" : [a] "=&v"(acc) : [m] "s"(m) : "vcc");
-  else
-    asm volatile("v_addc_co_u32 %[a], vcc, %[a], %[a], %[m]" : [a] "+v"(acc) : [m] "s"(m) : "vcc");
 }
 
 template <int L, int ALGO>
