@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -773,7 +774,9 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
     }
   }
 
-  sg_job *j = new sg_job;
+  // owned here until the job is complete: every early return frees it
+  std::unique_ptr<sg_job> owner(new sg_job);
+  sg_job *j = owner.get();
   j->ctx = ctx;
   j->sp = *spec;
   j->g = geom_of(spec->model, spec->L);
@@ -844,18 +847,13 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
     HIPCHK(hipMemcpy(j->at<void>(lay.E), z.data(), z.size(), hipMemcpyHostToDevice));
   }
   rc = upload_tables(j, st);
-  if (rc) {
-    delete j;
-    return rc;
-  }
+  if (rc) return rc;
   // own launch plan
   int tpb = 512;
   if (j->g.NW > tpb) tpb = j->g.NW;
   int G = copies_per_item(j, tpb);
-  if (G < 1 || item_lds(j, 1) > (size_t)ctx->max_lds) {
-    delete j;
+  if (G < 1 || item_lds(j, 1) > (size_t)ctx->max_lds)
     return fail(SG_E_UNSUPPORTED, "one copy of L = %d needs more LDS than the device offers", spec->L);
-  }
   make_items(j, G, j->works);
   xcd_order(j->works);
   j->tpb = ((G * j->g.NW + 63) / 64) * 64;
@@ -867,7 +865,7 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
     HIPCHK(hipMemcpy(j->at<void>(lay.ptworks), pw.data(), pw.size() * sizeof(PtWork), hipMemcpyHostToDevice));
   }
   HIPCHK(hipDeviceSynchronize());
-  *out = j;
+  *out = owner.release();
   return SG_OK;
   GUARD_END
 }
@@ -1314,6 +1312,18 @@ static int prepare_pt(sg_batch *b, const std::vector<int> &pt_jobs) {
   return SG_OK;
 }
 
+// capture stream, side streams and events of a new batch
+static int batch_streams(sg_batch *b) {
+  HIPCHK(hipSetDevice(b->ctx->device));
+  HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  for (int i = 0; i < NGROUP - 1; i++) {
+    HIPCHK(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming));
+  }
+  HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  return SG_OK;
+}
+
 extern "C" {
 
 int sg_batch_create(sg_ctx *ctx, sg_batch **out) {
@@ -1321,13 +1331,11 @@ int sg_batch_create(sg_ctx *ctx, sg_batch **out) {
   if (!ctx || !out) return fail(SG_E_INVALID, "NULL argument");
   sg_batch *b = new sg_batch;
   b->ctx = ctx;
-  HIPCHK(hipSetDevice(ctx->device));
-  HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-  for (int i = 0; i < NGROUP - 1; i++) {
-    HIPCHK(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming));
+  const int rc = batch_streams(b);
+  if (rc) {
+    sg_batch_destroy(b);  // releases whatever was created
+    return rc;
   }
-  HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
   *out = b;
   return SG_OK;
   GUARD_END
