@@ -75,7 +75,8 @@ def measured_traffic():
         return None
 
 
-def build_c3(ctx, B, inputs):
+def build_c3(ctx, B, inputs, algo=None):
+    algo = B.METROPOLIS if algo is None else algo
     jobs = []
     sample0 = 0
     betas = 1.0 / inputs.linear_temperatures(C3_K, 0.7, 1.6)
@@ -83,7 +84,7 @@ def build_c3(ctx, B, inputs):
         t = time.perf_counter()
         inst = inputs.make_instance("ising", L, C3_SAMPLES_PER_L, C3_R, C3_K, seed=3000,
                                     sample0=sample0)
-        jobs.append(B.Job(ctx, B.ISING, B.METROPOLIS, L, betas, inst["J"], inst["spins"],
+        jobs.append(B.Job(ctx, B.ISING, algo, L, betas, inst["J"], inst["spins"],
                           inst["wheels"], inst["ptwheels"], n_samples=C3_SAMPLES_PER_L,
                           n_replicas=C3_R, pt_every=C3_PT))
         del inst
@@ -152,6 +153,38 @@ def cpu_baseline(budget_s=15.0):
             "sample": f"one sample per L in {list(C3_LS)} with its {C3_R * C3_K} copies "
                       f"(2 replicas x 32 temperatures), {periods} parallel-tempering period(s) "
                       f"of {C3_PT} sweeps each, {updates:.3g} updates in {elapsed:.1f}s"}
+
+
+def heat_bath_c3(ctx, B, inputs, np, torch, stream, steps, block):
+    """The batched parallel-tempering workload with heat-bath dynamics (Eq. 4)
+    instead of Metropolis: same samples, temperatures and PT period, the
+    fused launch at the Metropolis run's block size; wall clock per step and
+    HIP-event time of the sweep launch."""
+    jobs = build_c3(ctx, B, inputs, B.HEATBATH)
+    batch = B.Batch(ctx, jobs, block=block)
+    for _ in range(3):
+        batch.run(C3_PT, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.run(C3_PT, stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    batch.set_timing(True)
+    batch.run(C3_PT, stream)
+    batch.sweep_ms()
+    kms = []
+    for _ in range(10):
+        batch.run(C3_PT, stream)
+        kms.append(batch.sweep_ms())
+    sites = sum(j.C * j.N for j in jobs)
+    out = {"value": round(C3_PT * sites / (ms * 1e6), 3), "unit": "spin updates/ns",
+           "ms_per_step": round(ms, 4), "kernel_ms_per_launch": round(float(np.mean(kms)), 4),
+           "block_threads": block,
+           "workload": "the batched workload (256 EA samples at L=16,24,32,48 x 2 replicas x 32 "
+                       "temperatures, PT every 10 sweeps) with heat-bath dynamics"}
+    log(f"[bench] heat bath: {out}")
+    return out
 
 
 def potts_c4(ctx, B, inputs, np, torch, stream, sweeps, model="potts"):
@@ -333,6 +366,8 @@ def main():
                     help="time only the Ising-like workload (profiling runs)")
     ap.add_argument("--eq-meas", type=int, default=256,
                     help="measurements of the equilibration-analysis run (0 = skip)")
+    ap.add_argument("--no-heat-bath", dest="heat_bath", action="store_false",
+                    help="skip the heat-bath run of the batched workload")
     ap.add_argument("--no-tune", action="store_true", help="skip the block-size autotuner")
     ap.add_argument("--block", type=int, default=0,
                     help="force the fused launch's threads per workgroup (skips the tuner)")
@@ -431,6 +466,9 @@ def main():
         log(f"[bench] batched only: {value:.1f} updates/ns")
         return
 
+    hb = heat_bath_c3(ctx, B, inputs, np, torch, stream, max(10, args.steps // 4), tpb) \
+        if args.heat_bath else None
+
     # --------------------------------------------------------- plain form --
     L2 = 64
     inst = inputs.make_instance("ising", L2, 1, 2, 1, seed=2)
@@ -517,6 +555,7 @@ def main():
             "ms_per_step": round(plain_ms, 3),
         },
         "speedup_batched_over_plain": round(value / plain_value, 2),
+        "heat_bath": hb,
         "potts_c4": potts,
         "glassy_potts": glassy,
         "glassy_potts_4d": glassy4d,

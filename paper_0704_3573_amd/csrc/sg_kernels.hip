@@ -12,11 +12,14 @@
 //    compiled for one of V = M / B ring phases, so every register index is
 //    static (the paper's "wheel in logic, not memory", sec. 3.3);
 //  * the B sites served by those draws are one 32-bit word of the bit-packed
-//    lattice; each draw is compared with the site's thresholds and the compare
-//    result (a 64-lane mask) is shifted into per-lane accumulator words with
-//    add-with-carry, so the per-site work is draw + compare + insert;
-//  * the six-neighbour unsatisfied-bond count is computed bit-sliced on whole
-//    words (32 sites per operation) from LDS-resident neighbour words;
+//    lattice; the six-neighbour bond count is computed bit-sliced on whole
+//    words (32 sites per operation) from LDS-resident neighbour words, and
+//    each site's threshold is read from the copy's small LDS table indexed by
+//    its count (the LUT of the paper's update cell);
+//  * each draw is compared with its site's threshold and the compare result
+//    (a 64-lane mask) is shifted into a per-lane accumulator word with
+//    add-with-carry, so the per-site work is draw + address + compare +
+//    insert;
 //  * the copies' spins stay in LDS for the whole launch; a workgroup barrier
 //    separates the two colours (sec. 3.1: same-colour sites never interact).
 #include <hip/hip_runtime.h>
@@ -88,13 +91,6 @@ DEV void count6(const uint32_t u[6], uint32_t &n0, uint32_t &n1, uint32_t &n2) {
   fadd(c1, c2, c3, n1, n2);
 }
 
-// a > b for bit-sliced 3-bit numbers.
-DEV uint32_t gt3(uint32_t a2, uint32_t a1, uint32_t a0, uint32_t b2, uint32_t b1, uint32_t b0) {
-  uint32_t lo = a0 & ~b0;
-  uint32_t mid = (a1 & ~b1) | (~(a1 ^ b1) & lo);
-  return (a2 & ~b2) | (~(a2 ^ b2) & mid);
-}
-
 // Per-lane context of the Ising sweep.
 struct IsingLane {
   uint32_t *sp;        // LDS base of the lane's copy (lanes without a wheel: a
@@ -102,8 +98,7 @@ struct IsingLane {
   rsrc_t rJ;           // couplings of the job
   uint32_t joff;       // byte offset of (sample, z) in the couplings
   int z, zp, zm, g;
-  uint32_t T[7];       // thresholds (Metropolis: 3, heat bath: 7)
-  uint32_t A;          // "always" bits
+  uint32_t A;          // bits of the thresholds equal to 2^32 ("always")
 };
 
 // The six other-colour neighbour words of block (p, wb) and its own word.
@@ -170,102 +165,25 @@ DEV void ising_couplings(const IsingLane &ln, int p, int blk, uint32_t Jw[6]) {
 }
 
 // Per-draw ALU steps in inline assembly.  Each draw computes
-// I(k) = I(k-24) + I(k-55) and r = I(k) xor I(k-61) (Eq. 5), compares r with
-// the site's thresholds (64-lane masks in SGPR pairs) and shifts the compare
-// results into per-lane accumulator words by add-with-carry (acc = 2 acc + c).
+// I(k) = I(k-24) + I(k-55) and r = I(k) xor I(k-61) (Eq. 5) and compares r
+// with the site's threshold (a 64-lane mask in an SGPR pair); a second stage
+// shifts the compare result into a per-lane accumulator word by
+// add-with-carry (acc = 2 acc + c).
 //
 // On gfx94x / gfx950 a VALU instruction that reads an SGPR written by another
-// VALU instruction (here: a compare mask used as select mask or carry-in) must
-// issue at least two instructions after it.  The draws of a block are
-// therefore issued as a software pipeline: each draw is split into stages and
-// the stages of neighbouring draws are interleaved (volatile asm statements
-// keep their order), so every mask is read at least two instructions after it
-// was written without any wait instructions.
-//
-// Metropolis (7 VALU operations per site): c1 = [r < T1], c0 = [r < (c1 ? T0 :
-// T2)], accumulators b1, b0.
-//   stage 1: add, xor, compare c1;  stage 2: select, compare c0;
-//   stage 3: insert c1, insert c0.
-// Order: stage 1 of draw 0, then for i = 0 .. B: stage 1 of draw i + 1,
-// stage 2 of draw i, stage 3 of draw i - 1 (gaps: c1 -> select >= 3
-// instructions, c0 -> insert >= 3, for B >= 2).
-DEV void met_s1(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T1,
-                uint32_t &r, uint64_t &m1) {
+// VALU instruction (here: a compare mask used as carry-in) must issue at
+// least two instructions after it.  The draws of a block are therefore
+// issued as a software pipeline (volatile asm statements keep their order):
+// stage 1 of draw 0, then for each draw i: stage 1 of draw i + 1, insert of
+// draw i, so every mask is read at least two instructions after it was
+// written; the block's last insert follows an explicit wait.
+DEV void met_s1(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T,
+                uint32_t &r, uint64_t &m) {
   asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
                "v_xor_b32 %[r], %[n], %[c]\n\t"
-               "v_cmp_lt_u32 %[m1], %[r], %[T1]"
-               : [n] "=&v"(inew), [r] "=&v"(r), [m1] "=&s"(m1)
-               : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T1] "v"(T1));
-}
-
-DEV void met_s2(uint32_t r, uint64_t m1, uint32_t T0, uint32_t T2, uint64_t &m0) {
-  uint32_t ts;
-  asm volatile("v_cndmask_b32 %[ts], %[T2], %[T0], %[m1]\n\t"
-               "v_cmp_lt_u32 %[m0], %[r], %[ts]"
-               : [ts] "=&v"(ts), [m0] "=&s"(m0)
-               : [r] "v"(r), [m1] "s"(m1), [T0] "v"(T0), [T2] "v"(T2));
-}
-
-// first draw of a block: the accumulators start from the carry; the carry-out
-// of the inserts is not used (written to VCC)
-DEV void met_s3(bool first, uint64_t m1, uint64_t m0, uint32_t &b1, uint32_t &b0) {
-  if (first)
-    asm volatile("v_addc_co_u32 %[b1], vcc, 0, 0, %[m1]\n\t"
-                 "v_addc_co_u32 %[b0], vcc, 0, 0, %[m0]"
-                 : [b1] "=&v"(b1), [b0] "=&v"(b0)
-                 : [m1] "s"(m1), [m0] "s"(m0)
-                 : "vcc");
-  else
-    asm volatile("v_addc_co_u32 %[b1], vcc, %[b1], %[b1], %[m1]\n\t"
-                 "v_addc_co_u32 %[b0], vcc, %[b0], %[b0], %[m0]"
-                 : [b1] "+v"(b1), [b0] "+v"(b0)
-                 : [m1] "s"(m1), [m0] "s"(m0)
-                 : "vcc");
-}
-
-// Heat bath (11 VALU operations per site): b = #{k : r < T[k]} over seven
-// nested thresholds, three bits by binary search into b2, b1, b0.
-//   stage 1: add, xor, compare c2 = [r < T3];
-//   stage 2: three selects by c2, compare c1 = [r < (c2 ? T1 : T5)];
-//   stage 3: select by c1, compare c0;  stage 4: insert c2, c1, c0.
-// Order: stage 1 of draw 0, then for i = 0 .. B + 1: stage 1 of draw i + 1,
-// stage 2 of draw i, stage 3 of draw i - 1, stage 4 of draw i - 2.
-DEV void hb_s1(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T3,
-               uint32_t &r, uint64_t &m2) {
-  asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
-               "v_xor_b32 %[r], %[n], %[c]\n\t"
-               "v_cmp_lt_u32 %[m2], %[r], %[T3]"
-               : [n] "=&v"(inew), [r] "=&v"(r), [m2] "=&s"(m2)
-               : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T3] "v"(T3));
-}
-
-DEV void hb_s2(uint32_t r, uint64_t m2, const uint32_t T[7], uint32_t &x, uint32_t &y,
-               uint64_t &m1) {
-  uint32_t ta;
-  asm volatile("v_cndmask_b32 %[ta], %[T5], %[T1], %[m2]\n\t"
-               "v_cndmask_b32 %[x], %[T6], %[T2], %[m2]\n\t"
-               "v_cndmask_b32 %[y], %[T4], %[T0], %[m2]\n\t"
-               "v_cmp_lt_u32 %[m1], %[r], %[ta]"
-               : [ta] "=&v"(ta), [x] "=&v"(x), [y] "=&v"(y), [m1] "=&s"(m1)
-               : [r] "v"(r), [m2] "s"(m2), [T0] "v"(T[0]), [T1] "v"(T[1]), [T2] "v"(T[2]),
-                 [T4] "v"(T[4]), [T5] "v"(T[5]), [T6] "v"(T[6]));
-}
-
-DEV void hb_s3(uint32_t r, uint64_t m1, uint32_t x, uint32_t y, uint64_t &m0) {
-  uint32_t tb;
-  asm volatile("v_cndmask_b32 %[tb], %[x], %[y], %[m1]\n\t"
-               "v_cmp_lt_u32 %[m0], %[r], %[tb]"
-               : [tb] "=&v"(tb), [m0] "=&s"(m0)
-               : [r] "v"(r), [m1] "s"(m1), [x] "v"(x), [y] "v"(y));
-}
-
-DEV void hb_s4(uint64_t m2, uint64_t m1, uint64_t m0, uint32_t &b2, uint32_t &b1, uint32_t &b0) {
-  asm volatile("v_addc_co_u32 %[b2], vcc, %[b2], %[b2], %[m2]\n\t"
-               "v_addc_co_u32 %[b1], vcc, %[b1], %[b1], %[m1]\n\t"
-               "v_addc_co_u32 %[b0], vcc, %[b0], %[b0], %[m0]"
-               : [b2] "+v"(b2), [b1] "+v"(b1), [b0] "+v"(b0)
-               : [m2] "s"(m2), [m1] "s"(m1), [m0] "s"(m0)
-               : "vcc");
+               "v_cmp_lt_u32 %[m], %[r], %[T]"
+               : [n] "=&v"(inew), [r] "=&v"(r), [m] "=&s"(m)
+               : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T] "v"(T));
 }
 
 // (a & m) | c with the mask in a scalar register (one instruction).
@@ -309,89 +227,6 @@ DEV void ins1(bool first, uint64_t m, uint32_t &acc) {
     asm volatile("v_addc_co_u32 %[a], vcc, 0, 0, %[m]" : [a] "=&v"(acc) : [m] "s"(m) : "vcc");
   else
     asm volatile("v_addc_co_u32 %[a], vcc, %[a], %[a], %[m]" : [a] "+v"(acc) : [m] "s"(m) : "vcc");
-}
-
-// One block: B draws of the lane's wheel at ring phase VI, one per site.
-// The block's LDS and coupling loads are issued first; the B ALU-only draw
-// steps then cover their latency before the bit-sliced logic consumes them.
-template <int L, int ALGO, int VI>
-DEV void ising_block(uint32_t (&ring)[GC<L>::M], const IsingLane &ln, int p, int blk,
-                     bool any_always) {
-  using G = GC<L>;
-  constexpr int M = G::M, B = G::B;
-  uint32_t S, N[6], Jw[6];
-  uint32_t *own;
-  ising_couplings<L>(ln, p, blk, Jw);
-  ising_neighbours<L>(ln, p, blk, S, N, own);
-  __builtin_amdgcn_sched_barrier(0);
-
-  static_assert(B >= 2, "the draw pipeline needs two draws per block");
-  uint32_t b0 = 0, b1 = 0, b2 = 0;
-  uint32_t r[B];
-  uint64_t m2[B], m1[B], m0[B];
-  if constexpr (ALGO == 0) {
-    auto s1 = [&](int i) {
-      const int k = VI * B + i;  // static after unrolling
-      met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
-             ln.T[1], r[i], m1[i]);
-    };
-    s1(0);
-#pragma unroll
-    for (int i = 0; i <= B; i++) {
-      if (i + 1 < B) s1(i + 1);
-      if (i < B) met_s2(r[i], m1[i], ln.T[0], ln.T[2], m0[i]);
-      if (i >= 1) met_s3(i == 1, m1[i - 1], m0[i - 1], b1, b0);
-    }
-  } else {
-    uint32_t x[B], y[B];
-    auto s1 = [&](int i) {
-      const int k = VI * B + i;  // static after unrolling
-      hb_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
-            ln.T[3], r[i], m2[i]);
-    };
-    s1(0);
-#pragma unroll
-    for (int i = 0; i <= B + 1; i++) {
-      if (i + 1 < B) s1(i + 1);
-      if (i < B) hb_s2(r[i], m2[i], ln.T, x[i], y[i], m1[i]);
-      if (i >= 1 && i <= B) hb_s3(r[i - 1], m1[i - 1], x[i - 1], y[i - 1], m0[i - 1]);
-      if (i >= 2) hb_s4(m2[i - 2], m1[i - 2], m0[i - 2], b2, b1, b0);
-    }
-  }
-  __builtin_amdgcn_sched_barrier(0);
-
-  // bit-sliced neighbour count
-  uint32_t n0, n1, n2;
-  {
-    uint32_t u[6];
-#pragma unroll
-    for (int d = 0; d < 6; d++) u[d] = ALGO == 0 ? (S ^ N[d] ^ Jw[d]) : (N[d] ^ Jw[d]);
-    count6(u, n0, n1, n2);
-  }
-  if constexpr (ALGO == 0) {
-    // Metropolis: n unsatisfied bonds; flip iff n >= 3 or r < T[n], i.e. n + b >= 3.
-    uint32_t acc = n2 | (n1 & (n0 | b0 | b1)) | (b1 & (n0 | b0));
-    if (__builtin_expect(any_always, 0)) {
-      // a threshold equal to 2^32 (beta ~ 0): kept out of line (the empty asm
-      // stops the compiler from turning this rare path into selects)
-      asm volatile("" ::: "memory");
-      const uint32_t A0 = (ln.A & 1) ? ~0u : 0u, A1 = (ln.A & 2) ? ~0u : 0u,
-                     A2 = (ln.A & 4) ? ~0u : 0u;
-      acc |= A0 | (A1 & (n0 | n1 | n2)) | (A2 & (n1 | n2));
-    }
-    *own = S ^ (acc & G::MB);
-  } else {
-    // Heat bath: m = #{d : J_d s_d = -1}, k = 6 - m; s = +1 iff r < T[k], i.e. b > m.
-    uint32_t plus = gt3(b2, b1, b0, n2, n1, n0);
-    if (__builtin_expect(any_always, 0)) {
-      // T[k] = 2^32 for every k >= kmin: force +1 where m <= 6 - kmin
-      asm volatile("" ::: "memory");
-      const int a = ln.A ? 6 - (__ffs(ln.A) - 1) : -1;
-      const uint32_t a2 = (a & 4) ? ~0u : 0u, a1 = (a & 2) ? ~0u : 0u, a0 = (a & 1) ? ~0u : 0u;
-      if (a >= 0) plus |= ~gt3(n2, n1, n0, a2, a1, a0);
-    }
-    *own = ~plus & G::MB;
-  }
 }
 
 // Number of unsatisfied bonds touching the lane's colour-0 sites (every bond
@@ -504,18 +339,6 @@ DEV void drive(K &k, Drive &d) {
   }
 }
 
-template <int L, int ALGO>
-struct IsingK {
-  using G = GC<L>;
-  static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK;
-  IsingLane ln;
-  bool any_always;
-  template <int VI>
-  DEV void block(uint32_t (&ring)[M], int p, int blk) {
-    ising_block<L, ALGO, VI>(ring, ln, p, blk, any_always);
-  }
-};
-
 // Metropolis with a per-copy threshold table (the LUT of the paper's update
 // cell).  The number n of unsatisfied bonds of every site of the block is
 // counted bit-sliced before the draws; each draw is compared with T[n mod 4]
@@ -601,9 +424,91 @@ struct IsingMetK {
   }
 };
 
+// Heat bath with the same table: with m = #{j : J_ij s_j = -1} counted
+// bit-sliced (k = 6 - m bonds favour s_i = +1), the new spin is +1 iff
+// r < T_HB[6 - m], read from the copy's 8-word LDS table at byte offset 4 m
+// (three count planes transposed into bytes); the sites whose threshold is
+// 2^32 (s = +1 certain, large local field at large beta) are m < m_lim.
+template <int L>
+struct IsingHbK {
+  using G = GC<L>;
+  static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK;
+  IsingLane ln;
+  const uint32_t *tab;      // LDS table of the lane's copy: T_HB[6 - m], m = 0..6, then 0
+  uint32_t ml0, ml1, ml2;   // limit m_lim in 0..7 of the certain +1 sites, as lane masks
+  uint32_t nextJ[6];        // coupling words of the next block
+
+  DEV void fetch(int p, int blk) { ising_couplings<L>(ln, p, blk, nextJ); }
+
+  template <int VI>
+  DEV void block(uint32_t (&ring)[M], int p, int blk) {
+    uint32_t Jw[6];
+#pragma unroll
+    for (int d = 0; d < 6; d++) Jw[d] = nextJ[d];
+    if (blk + 1 < NBLK)
+      fetch(p, blk + 1);
+    else
+      fetch(p ^ 1, 0);
+    uint32_t S, N[6];
+    uint32_t *own;
+    ising_neighbours<L>(ln, p, blk, S, N, own);
+    uint32_t n0, n1, n2;
+    {
+      uint32_t u[6];
+#pragma unroll
+      for (int d = 0; d < 6; d++) u[d] = N[d] ^ Jw[d];  // 1: J s_j = -1
+      count6(u, n0, n1, n2);
+    }
+    // m < m_lim, bit-sliced over three bits
+    uint32_t below = ~n0 & ml0;
+    below = bfi(n1 ^ ml1, ml1, below);
+    below = bfi(n2 ^ ml2, ml2, below);
+    // byte j of word w = 4 m of the site at bit w + 8 j
+    uint32_t Kw[8];
+#pragma unroll
+    for (int w = 0; w < 8; w++) {
+      const uint32_t a = 2 >= w ? n0 << (2 - w) : n0 >> (w - 2);
+      const uint32_t b = 3 >= w ? n1 << (3 - w) : n1 >> (w - 3);
+      const uint32_t c = 4 >= w ? n2 << (4 - w) : n2 >> (w - 4);
+      Kw[w] = and_or(a, 0x04040404u, and_or(b, 0x08080808u, c & 0x10101010u));
+    }
+    const uint32_t tbase = lds_offset(tab);
+    uint32_t T[B];
+    auto load = [&](int i) {
+      const int q = B - 1 - i;
+      T[i] = *(const lds_u32 *)(uintptr_t)add_byte(q >> 3, tbase, Kw[q & 7]);
+    };
+    constexpr int PF = B < 8 ? B : 8;
+#pragma unroll
+    for (int i = 0; i < PF; i++) load(i);
+    __builtin_amdgcn_sched_barrier(0);
+
+    static_assert(B >= 2, "the draw pipeline needs two draws per block");
+    uint32_t acc = 0, r;
+    uint64_t m[B];
+    auto s1 = [&](int i) {
+      const int k = VI * B + i;  // static after unrolling
+      met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
+             T[i], r, m[i]);
+    };
+    s1(0);
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+      if (i + PF < B) load(i + PF);
+      if (i + 1 < B)
+        s1(i + 1);
+      else
+        asm volatile("s_nop 1");
+      ins1(i == 0, m[i], acc);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    *own = ~(below | acc) & G::MB;  // bit 1 <-> spin -1
+  }
+};
+
 template <int L, int ALGO>
 struct IsingKernelOf {
-  using type = IsingK<L, ALGO>;
+  using type = IsingHbK<L>;
 };
 template <int L>
 struct IsingKernelOf<L, 0> {
@@ -619,10 +524,10 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   const bool active = t < lanes;
   int *Ucnt = (int *)(lds + w.ncopies * G::CS);
   uint32_t *scratch_copy = lds + w.ncopies * G::CS + w.ncopies;  // CS words
-  uint32_t *tabs = scratch_copy + G::CS;  // Metropolis: [ncopies][ISING_TAB_STRIDE]
+  uint32_t *tabs = scratch_copy + G::CS;  // [ncopies][ISING_TAB_STRIDE] thresholds
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
 
-  // stage the copies (and the Metropolis threshold tables) in LDS
+  // stage the copies and their threshold tables in LDS
   const uint32_t sbase = (uint32_t)w.copy0 * G::CS * 4u;
   for (int i = t; i < w.ncopies * G::CS; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
   for (int i = t; i < w.ncopies; i += nthr) Ucnt[i] = 0;
@@ -631,6 +536,12 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
       const int c = i >> 2, e = i & 3;
       tabs[c * ISING_TAB_STRIDE + e] =
           e < 3 ? w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + e] : 0u;
+    }
+  else  // heat bath: entry m holds T_HB[6 - m]
+    for (int i = t; i < w.ncopies * 8; i += nthr) {
+      const int c = i >> 3, e = i & 7;
+      tabs[c * ISING_TAB_STRIDE + e] =
+          e < 7 ? w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + 6 - e] : 0u;
     }
 
   // lanes without a wheel serve wheel (z = t mod L, row group 0) of the
@@ -647,25 +558,22 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   ln.zm = ln.z == 0 ? L - 1 : ln.z - 1;
   ln.rJ = make_rsrc(w.J, w.J_bytes);
   ln.joff = ((uint32_t)(copy / w.RK) * ising_js(L) + ln.z) * 4u;
-  ln.A = 0;
-#pragma unroll
-  for (int q = 0; q < 7; q++) ln.T[q] = 0;
-  if (active) {
-    const uint32_t *tr = w.thr + w.temp_of_slot[copy] * THR_WORDS;
-#pragma unroll
-    for (int q = 0; q < 7; q++) ln.T[q] = tr[q];
-    ln.A = tr[15];
-  }
+  ln.A = active ? w.thr[w.temp_of_slot[copy] * THR_WORDS + 15] : 0u;
   if constexpr (ALGO == 0) {
     // certain flips from n = m on: m = 3 (dE <= 0), or the first n whose
     // threshold is 2^32 (thresholds grow with n)
     const int m = ln.A ? min(3, __ffs(ln.A) - 1) : 3;
     k.mlo = (m & 1) ? ~0u : 0u;
     k.mhi = (m & 2) ? ~0u : 0u;
-    k.tab = tabs + cl * ISING_TAB_STRIDE;
   } else {
-    k.any_always = __any(active && ln.A != 0);
+    // certain +1 for k >= k0 (first k whose threshold is 2^32; thresholds
+    // grow with k), i.e. m = 6 - k < m_lim = 7 - k0
+    const int mlim = ln.A ? 7 - (__ffs(ln.A) - 1) : 0;
+    k.ml0 = (mlim & 1) ? ~0u : 0u;
+    k.ml1 = (mlim & 2) ? ~0u : 0u;
+    k.ml2 = (mlim & 4) ? ~0u : 0u;
   }
+  k.tab = tabs + cl * ISING_TAB_STRIDE;
 
   Drive d;
   d.nsweeps = w.nsweeps_cap;
@@ -675,7 +583,7 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   d.widx = ((uint32_t)copy * G::NW + wl) * 4u;
   d.kmod = (int)__builtin_amdgcn_readfirstlane((uint32_t)((*w.done * (uint64_t)(G::RHO * L)) % G::M));
   __syncthreads();
-  if constexpr (ALGO == 0) k.fetch(0, 0);
+  k.fetch(0, 0);
   drive(k, d);
 
   // energy of every copy, then write back the spins

@@ -159,9 +159,9 @@ SG_HD constexpr int gen_js(int L) { return gen_block_js(L) + geom(L).CS; }
 // LDS threshold table of a copy: 32 words at an odd stride (bank spread).
 constexpr int GEN_TAB_STRIDE = 33;
 
-// Ising Metropolis: LDS threshold table of a copy (T[0..2], 0) at an odd
-// stride of 5 words.
-constexpr int ISING_TAB_STRIDE = 5;
+// Ising: LDS threshold table of a copy at an odd stride of 9 words
+// (Metropolis: T[0..2], 0; heat bath: T_HB[6 - m] for m = 0..6, 0).
+constexpr int ISING_TAB_STRIDE = 9;
 
 // Per-temperature threshold row: 32 words.  Ising Metropolis uses [0..2],
 // heat bath [0..6], Potts [0..12]; a threshold equal to 2^32 is stored as
