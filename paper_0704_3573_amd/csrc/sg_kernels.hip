@@ -193,6 +193,19 @@ DEV uint32_t and_or(uint32_t a, uint32_t m, uint32_t c) {
   return r;
 }
 
+// x shifted right by s (left by -s); s is a compile-time constant.
+DEV uint32_t shr(uint32_t x, int s) { return s >= 0 ? x >> s : x << -s; }
+
+// Bit planes a, b interleaved by bit pairs: word 0 holds a[2i] at bit 2i and
+// b[2i] at bit 2i + 1, word 1 holds a[2i + 1] at bit 2i and b[2i + 1] at
+// bit 2i + 1.  Bit w + 8 j of a and b then sit at bits 8 j + 2 (w / 2) and
+// 8 j + 2 (w / 2) + 1 of word w & 1: one shift and one mask move the pair of
+// every site of a byte column into place (byte transposes below).
+DEV void pair_planes(uint32_t a, uint32_t b, uint32_t &z0, uint32_t &z1) {
+  z0 = bfi(0x55555555u, a, b << 1);
+  z1 = bfi(0x55555555u, a >> 1, b);
+}
+
 // base + byte n of x (one instruction; n is a compile-time constant).
 DEV uint32_t add_byte(int n, uint32_t base, uint32_t x) {
   uint32_t r;
@@ -382,13 +395,10 @@ struct IsingMetK {
     const uint32_t below = bfi(n1 ^ mhi, mhi, ~n0 & mlo);
     const uint32_t cert = n2 | ~below;
     // byte j of word w = 4 (n mod 4) of the site at bit w + 8 j
-    uint32_t Kw[8];
+    uint32_t Kw[8], z[2];
+    pair_planes(n0, n1, z[0], z[1]);
 #pragma unroll
-    for (int w = 0; w < 8; w++) {
-      const uint32_t a = 2 >= w ? n0 << (2 - w) : n0 >> (w - 2);
-      const uint32_t b = 3 >= w ? n1 << (3 - w) : n1 >> (w - 3);
-      Kw[w] = and_or(a, 0x04040404u, b & 0x08080808u);
-    }
+    for (int w = 0; w < 8; w++) Kw[w] = shr(z[w & 1], 2 * (w >> 1) - 2) & 0x0C0C0C0Cu;
     const uint32_t tbase = lds_offset(tab);
     uint32_t T[B];
     // threshold of draw i (site at bit B - 1 - i), read PF draws ahead
@@ -464,14 +474,11 @@ struct IsingHbK {
     below = bfi(n1 ^ ml1, ml1, below);
     below = bfi(n2 ^ ml2, ml2, below);
     // byte j of word w = 4 m of the site at bit w + 8 j
-    uint32_t Kw[8];
+    uint32_t Kw[8], z[2];
+    pair_planes(n0, n1, z[0], z[1]);
 #pragma unroll
-    for (int w = 0; w < 8; w++) {
-      const uint32_t a = 2 >= w ? n0 << (2 - w) : n0 >> (w - 2);
-      const uint32_t b = 3 >= w ? n1 << (3 - w) : n1 >> (w - 3);
-      const uint32_t c = 4 >= w ? n2 << (4 - w) : n2 >> (w - 4);
-      Kw[w] = and_or(a, 0x04040404u, and_or(b, 0x08080808u, c & 0x10101010u));
-    }
+    for (int w = 0; w < 8; w++)
+      Kw[w] = and_or(shr(z[w & 1], 2 * (w >> 1) - 2), 0x0C0C0C0Cu, shr(n2, w - 4) & 0x10101010u);
     const uint32_t tbase = lds_offset(tab);
     uint32_t T[B];
     auto load = [&](int i) {
@@ -687,16 +694,14 @@ struct GenK {
     // threshold of every site: the five class planes are transposed into
     // bytes, byte j of word w holding 4 (k + 16 phi) of the site at bit
     // q = w + 8 j, so each site's table address is one byte-select add
-    uint32_t Kw[8];
+    uint32_t Kw[8], z01[2], z23[2];
+    pair_planes(P[0], P[1], z01[0], z01[1]);
+    pair_planes(P[2], P[3], z23[0], z23[1]);
 #pragma unroll
     for (int w = 0; w < 8; w++) {
-      Kw[w] = 0;
-#pragma unroll
-      for (int b = 0; b < 5; b++) {
-        const int sh = b + 2 - w;
-        const uint32_t v = sh >= 0 ? P[b] << sh : P[b] >> -sh;
-        Kw[w] = and_or(v, 0x01010101u << (b + 2), Kw[w]);
-      }
+      const int t2 = 2 * (w >> 1);
+      Kw[w] = and_or(shr(z01[w & 1], t2 - 2), 0x0C0C0C0Cu,
+                     and_or(shr(z23[w & 1], t2 - 4), 0x30303030u, shr(P[4], w - 6) & 0x40404040u));
     }
     const uint32_t tbase = lds_offset(tab);
     uint32_t T[B];
