@@ -164,7 +164,10 @@ static uint64_t al(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 static bool is_potts(int model) { return model == SG_POTTS || model == SG_GPOTTS || model == SG_GPOTTS4; }
 
 // geometry of a model: 4D wheels for the 4D glassy Potts model, else 3D
-static Geom geom_of(int model, int L) { return model == SG_GPOTTS4 ? sg::geom4(L) : sg::geom(L); }
+static Geom geom_of(int model, int L) {
+  if (model == SG_GPOTTS4) return sg::geom4(L);
+  return model == SG_ISING || model == SG_ISING_GEN ? sg::igeom(L) : sg::geom(L);
+}
 static uint64_t sites_of(int model, int L) {
   const uint64_t N = (uint64_t)L * L * L;
   return model == SG_GPOTTS4 ? N * L : N;
@@ -357,6 +360,18 @@ static void make_pt_works(const sg_job *j, std::vector<PtWork> &out) {
 }
 
 // --------------------------------------------------------------- packing --
+// Site of bit t (draw order, 0 = most significant bit) of block word wb of
+// colour p in plane z of an Ising copy: string position s = wb B + t, row
+// y = s / (L/2), x = 2 (s mod L/2) + e.
+struct BitSite {
+  int x, y;
+};
+static BitSite bit_site(const Geom &g, int p, int z, int wb, int t) {
+  const int s = wb * g.B + t;
+  const int y = s / g.H;
+  return {2 * (s % g.H) + ((p + y + z) & 1), y};
+}
+
 static void pack_ising_spins(const Geom &g, const int8_t *s, uint32_t *out) {
   const int L = g.L;
   std::memset(out, 0, sizeof(uint32_t) * g.CS);
@@ -364,14 +379,9 @@ static void pack_ising_spins(const Geom &g, const int8_t *s, uint32_t *out) {
     for (int z = 0; z < L; z++)
       for (int wb = 0; wb < g.NWB; wb++) {
         uint32_t word = 0;
-        for (int r = 0; r < g.RPB; r++) {
-          const int y = wb * g.RPB + r;
-          const int e = (p + y + z) & 1;
-          for (int j = 0; j < g.H; j++) {
-            const int x = 2 * j + e;
-            const int bit = g.B - 1 - (r * g.H + j);
-            if (s[x + L * (y + L * z)] < 0) word |= 1u << bit;
-          }
+        for (int t = 0; t < g.B; t++) {
+          const BitSite b = bit_site(g, p, z, wb, t);
+          if (s[b.x + L * (b.y + L * z)] < 0) word |= 1u << (g.B - 1 - t);
         }
         out[(p * L + z) * g.WZ + wb] = word;
       }
@@ -383,14 +393,9 @@ static void unpack_ising_spins(const Geom &g, const uint32_t *in, int8_t *s) {
     for (int z = 0; z < L; z++)
       for (int wb = 0; wb < g.NWB; wb++) {
         const uint32_t word = in[(p * L + z) * g.WZ + wb];
-        for (int r = 0; r < g.RPB; r++) {
-          const int y = wb * g.RPB + r;
-          const int e = (p + y + z) & 1;
-          for (int j = 0; j < g.H; j++) {
-            const int x = 2 * j + e;
-            const int bit = g.B - 1 - (r * g.H + j);
-            s[x + L * (y + L * z)] = ((word >> bit) & 1u) ? -1 : 1;
-          }
+        for (int t = 0; t < g.B; t++) {
+          const BitSite b = bit_site(g, p, z, wb, t);
+          s[b.x + L * (b.y + L * z)] = ((word >> (g.B - 1 - t)) & 1u) ? -1 : 1;
         }
       }
 }
@@ -416,21 +421,16 @@ static void pack_ising_J(const Geom &g, const int8_t *J, uint32_t *out) {
       for (int d = 0; d < 6; d++)
         for (int z = 0; z < L; z++) {
           uint32_t word = 0;
-          for (int r = 0; r < g.RPB; r++) {
-            const int y = wb * g.RPB + r;
-            const int e = (p + y + z) & 1;
-            for (int j = 0; j < g.H; j++) {
-              const int x = 2 * j + e;
-              const int bit = g.B - 1 - (r * g.H + j);
-              if (bond(J, L, x, y, z, d) < 0) word |= 1u << bit;
-            }
+          for (int t = 0; t < g.B; t++) {
+            const BitSite b = bit_site(g, p, z, wb, t);
+            if (bond(J, L, b.x, b.y, z, d) < 0) word |= 1u << (g.B - 1 - t);
           }
           out[((p * g.NWB + wb) * 6 + d) * L + z] = word;
         }
 }
 
 // Ising-like models: D = [5][N] rows J_x, J_y, J_z, x, f -> the 14 words of
-// every (colour, block-row, plane) and the occupancy words in the spin-copy
+// every (colour, block word, plane) and the occupancy words in the spin-copy
 // layout (see sg_layout.h)
 static void pack_gen_J(const Geom &g, const int8_t *D, uint32_t *out) {
   const int L = g.L;
@@ -444,19 +444,16 @@ static void pack_gen_J(const Geom &g, const int8_t *D, uint32_t *out) {
     for (int wb = 0; wb < g.NWB; wb++)
       for (int z = 0; z < L; z++) {
         uint32_t w[sg::GEN_WORDS] = {};
-        for (int r = 0; r < g.RPB; r++) {
-          const int y = wb * g.RPB + r;
-          const int e = (p + y + z) & 1;
-          for (int j = 0; j < g.H; j++) {
-            const int x = 2 * j + e;
-            const uint32_t bit = 1u << (g.B - 1 - (r * g.H + j));
-            for (int d = 0; d < 6; d++) {
-              if (bond(D, L, x, y, z, d) < 0) w[d] |= bit;
-              if (X[idx(x + dx[d], y + dy[d], z + dz[d])]) w[6 + d] |= bit;
-            }
-            if (X[idx(x, y, z)]) w[12] |= bit;
-            if (F[idx(x, y, z)] < 0) w[13] |= bit;
+        for (int t = 0; t < g.B; t++) {
+          const BitSite b = bit_site(g, p, z, wb, t);
+          const int x = b.x, y = b.y;
+          const uint32_t bit = 1u << (g.B - 1 - t);
+          for (int d = 0; d < 6; d++) {
+            if (bond(D, L, x, y, z, d) < 0) w[d] |= bit;
+            if (X[idx(x + dx[d], y + dy[d], z + dz[d])]) w[6 + d] |= bit;
           }
+          if (X[idx(x, y, z)]) w[12] |= bit;
+          if (F[idx(x, y, z)] < 0) w[13] |= bit;
         }
         for (int d = 0; d < sg::GEN_WORDS; d++)
           out[((p * g.NWB + wb) * sg::GEN_WORDS + d) * L + z] = w[d];

@@ -72,7 +72,89 @@ struct GC {
   static constexpr uint32_t LOWB = lowb(), TOPB = topb(), EVENSEG = segs(0), ODDSEG = segs(1);
 };
 
+// Compile-time geometry of the bit-packed Ising copies (plane strings cut
+// into B-bit block words, see sg_layout.h) and, per block word of a row
+// group, the bits of the sites that end a row (in-row index L/2 - 1), start
+// a row (index 0) and lie in an odd row (a row group starts at an even row,
+// so these depend on the block's index within its group only).
+template <int L>
+struct IC {
+  static constexpr Geom g = igeom(L);
+  static constexpr int RHO = g.RHO, NG = g.NG, NW = g.NW, H = g.H, B = g.B, NBLK = g.NBLK,
+                       NWB = g.NWB, WZ = g.WZ, CS = g.CS, M = g.M, V = g.V;
+  static constexpr uint32_t MB = B == 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
+  struct Masks {
+    uint32_t ends[8], starts[8], odd[8];
+  };
+  static constexpr Masks masks() {
+    Masks m{};
+    for (int b = 0; b < NBLK; b++)
+      for (int t = 0; t < B; t++) {
+        const int s = b * B + t;
+        const uint32_t bit = 1u << (B - 1 - t);
+        if (s % H == H - 1) m.ends[b] |= bit;
+        if (s % H == 0) m.starts[b] |= bit;
+        if ((s / H) & 1) m.odd[b] |= bit;
+      }
+    return m;
+  }
+  static constexpr Masks MK = masks();
+  static constexpr uint32_t mask(int kind, int b) {
+    return b >= NBLK ? 0u : kind == 0 ? MK.ends[b] : kind == 1 ? MK.starts[b] : MK.odd[b];
+  }
+  static_assert(NBLK <= 8, "row groups hold at most 8 block words");
+};
+
 DEV uint32_t bfi(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
+
+// A compile-time mask in an SGPR, written next to its use (gfx9 VOP3
+// instructions take no 32-bit literal; left to itself the compiler hoists
+// every distinct mask of an unrolled loop into its own SGPR).
+template <uint32_t V>
+DEV uint32_t smask() {
+  if constexpr (V == 0u || V == 0xFFFFFFFFu) {
+    return V;
+  } else {
+    uint32_t r;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(r) : "i"(V));
+    return r;
+  }
+}
+
+// Row-end (kind 0), row-start (1) or odd-row (2) mask of block blk of an
+// Ising row group; blk is a constant after unrolling, so the switch folds.
+template <int L, int KIND>
+DEV uint32_t imask(int blk) {
+  using G = IC<L>;
+  switch (blk) {
+    case 0: return smask<G::mask(KIND, 0)>();
+    case 1: return smask<G::mask(KIND, 1)>();
+    case 2: return smask<G::mask(KIND, 2)>();
+    case 3: return smask<G::mask(KIND, 3)>();
+    case 4: return smask<G::mask(KIND, 4)>();
+    case 5: return smask<G::mask(KIND, 5)>();
+    case 6: return smask<G::mask(KIND, 6)>();
+    default: return smask<G::mask(KIND, 7)>();
+  }
+}
+
+// Shifts of a plane string cut into B-bit words (first position at bit
+// B - 1), seen from word c with its successor n and predecessor q: bit of
+// position s of the result holds position s + k (str_next) or s - k
+// (str_prev), 0 <= k <= B.  Bits above B of the result are don't-care; the
+// inputs have them zero.
+template <int B>
+DEV uint32_t str_next(uint32_t c, uint32_t n, int k) {
+  if (k == 0) return c;
+  if (k == B) return n;
+  return (c << k) | (n >> (B - k));
+}
+template <int B>
+DEV uint32_t str_prev(uint32_t c, uint32_t q, int k) {
+  if (k == 0) return c;
+  if (k == B) return q;
+  return (c >> k) | (q << (B - k));
+}
 
 // Full adder on bit-sliced words: sum and majority carry.
 DEV void fadd(uint32_t a, uint32_t b, uint32_t c, uint32_t &s, uint32_t &cy) {
@@ -98,63 +180,55 @@ struct IsingLane {
   rsrc_t rJ;           // couplings of the job
   uint32_t joff;       // byte offset of (sample, z) in the couplings
   int z, zp, zm, g;
+  uint32_t zodd;       // all ones when z is odd
   uint32_t A;          // bits of the thresholds equal to 2^32 ("always")
 };
 
-// The six other-colour neighbour words of block (p, wb) and its own word.
+// The six other-colour neighbour words of block blk of the lane's row group
+// in colour p, and its own word.  With the other colour's plane string Q,
+// the y neighbours of position s are Q[s + L/2] and Q[s - L/2]; in a row of
+// parity e = (p + y + z) & 1, site j (x = 2j + e) has x+1 at index j + e and
+// x-1 at index j + e - 1, periodic within the row: Q[s + 1] or, at a row's
+// last site, Q[s + 1 - L/2]; Q[s - 1] or, at its first site, Q[s - 1 + L/2].
 template <int L>
 DEV void ising_neighbours(const IsingLane &ln, int p, int blk, uint32_t &S, uint32_t N[6],
                           uint32_t *&own) {
-  using G = GC<L>;
+  using G = IC<L>;
+  if constexpr (G::NBLK == 1) blk = 0;
   const int q = p ^ 1;
   const int wb = ln.g * G::NBLK + blk;
-  const int y0 = ln.g * G::RHO + blk * G::RPB;
   own = ln.sp + (p * L + ln.z) * G::WZ + wb;
   S = *own;
   const uint32_t *oc = ln.sp + (q * L + ln.z) * G::WZ;
   const uint32_t Wc = oc[wb];
   N[4] = ln.sp[(q * L + ln.zp) * G::WZ + wb];  // z+
   N[5] = ln.sp[(q * L + ln.zm) * G::WZ + wb];  // z-
-  if constexpr (G::NWB == 1) {
-    // one block covers the whole plane: y neighbours are rows of the same word
-    if constexpr (G::RPB == 1) {
-      N[2] = Wc;
-      N[3] = Wc;
-    } else {
-      N[2] = (Wc << G::H) | (Wc >> (G::B - G::H));
-      N[3] = (Wc >> G::H) | (Wc << (G::B - G::H));
-    }
-  } else {
-    const uint32_t Wn = oc[wb + 1 == G::NWB ? 0 : wb + 1];
-    const uint32_t Wp = oc[wb == 0 ? G::NWB - 1 : wb - 1];
-    if constexpr (G::RPB == 1) {
-      N[2] = Wn;
-      N[3] = Wp;
-    } else {
-      N[2] = (Wc << G::H) | (Wn >> (G::B - G::H));  // row r needs row r + 1
-      N[3] = (Wc >> G::H) | (Wp << (G::B - G::H));  // row r needs row r - 1
-    }
+  uint32_t Wn = Wc, Wp = Wc;
+  if constexpr (G::NWB > 1) {
+    Wn = oc[wb + 1 == G::NWB ? 0 : wb + 1];
+    Wp = oc[wb == 0 ? G::NWB - 1 : wb - 1];
   }
-  // x neighbours: in a row of parity e = (p + y + z) & 1, site j (x = 2j + e)
-  // has x+1 at other-colour index j + e and x-1 at index j + e - 1 (periodic
-  // within the row).
-  uint32_t rl, rr;
-  if constexpr (G::RPB == 1) {
-    // one row per word: plain rotations of B bits (bits above B are don't-care)
-    rl = (Wc << 1) | (Wc >> (G::B - 1));  // index j+1 into j
-    rr = (Wc >> 1) | (Wc << (G::B - 1));  // index j-1 into j
+  constexpr int B = G::B, H = G::H;
+  N[2] = str_next<B>(Wc, Wn, H);  // y+
+  N[3] = str_prev<B>(Wc, Wp, H);  // y-
+  uint32_t rl, rr;                // other-colour index j + 1, j - 1
+  if constexpr (H == B) {
+    // one row per word: rotations
+    rl = (Wc << 1) | (Wc >> (B - 1));
+    rr = (Wc >> 1) | (Wc << (B - 1));
   } else {
-    rl = bfi(G::LOWB, Wc >> (G::H - 1), Wc << 1);
-    rr = bfi(G::TOPB, Wc << (G::H - 1), Wc >> 1);
+    rl = bfi(imask<L, 0>(blk), str_prev<B>(Wc, Wp, H - 1), str_next<B>(Wc, Wn, 1));
+    rr = bfi(imask<L, 1>(blk), str_next<B>(Wc, Wn, H - 1), str_prev<B>(Wc, Wp, 1));
   }
-  const uint32_t em = ((p + y0 + ln.z) & 1) ? G::EVENSEG : G::ODDSEG;
+  // sites of rows with e = 1: odd rows when p + z is even, even rows otherwise
+  const uint32_t em = imask<L, 2>(blk) ^ (p ? ~ln.zodd : ln.zodd);
   N[0] = bfi(em, rl, Wc);
   N[1] = bfi(em, Wc, rr);
 }
 
 template <int L>
 DEV void ising_couplings(const IsingLane &ln, int p, int blk, uint32_t Jw[6]) {
-  using G = GC<L>;
+  using G = IC<L>;
   // per-lane part (sample, row group, plane) in the VGPR offset, the
   // wave-uniform part (colour, block, direction) in the SGPR offset
   const uint32_t voff = ln.joff + (uint32_t)(ln.g * G::NBLK * 6 * L) * 4u;
@@ -246,8 +320,9 @@ DEV void ins1(bool first, uint64_t m, uint32_t &acc) {
 // has exactly one colour-0 end, so the per-copy sum is U and E = 2U - 3N).
 template <int L>
 DEV int ising_lane_unsat(const IsingLane &ln) {
-  using G = GC<L>;
+  using G = IC<L>;
   int U = 0;
+#pragma unroll
   for (int blk = 0; blk < G::NBLK; blk++) {
     uint32_t S, N[6], Jw[6], u[6];
     uint32_t *own;
@@ -326,6 +401,16 @@ DEV void drive_half(K &k, uint32_t (&ring)[K::M], int p) {
   if constexpr (BLK + 1 < K::NBLK) drive_half<K, BLK + 1>(k, ring, p);
 }
 
+// When V divides 2 NBLK but not NBLK every sweep starts at ring phase 0:
+// the 2 NBLK blocks of a sweep are unrolled (colour, block index and phase
+// compile-time constants).
+template <class K, int I>
+DEV void drive_sweep(K &k, uint32_t (&ring)[K::M]) {
+  k.template block<I % K::V>(ring, I / K::NBLK, I % K::NBLK);
+  if constexpr (I % K::NBLK == K::NBLK - 1) __syncthreads();
+  if constexpr (I + 1 < 2 * K::NBLK) drive_sweep<K, I + 1>(k, ring);
+}
+
 template <class K>
 DEV void drive(K &k, Drive &d) {
   if (d.nsweeps <= 0) return;
@@ -342,6 +427,9 @@ DEV void drive(K &k, Drive &d) {
         drive_half<K, 0>(k, ring, p);
         __syncthreads();
       }
+    if (d.active) ring_store<K::M, K::M - 1>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+  } else if constexpr ((2 * K::NBLK) % K::V == 0) {
+    for (int s = 0; s < d.nsweeps; s++) drive_sweep<K, 0>(k, ring);
     if (d.active) ring_store<K::M, K::M - 1>(ring, d.rwh, d.widx, d.wstride, d.kmod);
   } else {
     d.p = 0;
@@ -363,7 +451,7 @@ DEV void drive(K &k, Drive &d) {
 // block's couplings are loaded one block ahead.
 template <int L>
 struct IsingMetK {
-  using G = GC<L>;
+  using G = IC<L>;
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK;
   IsingLane ln;
   const uint32_t *tab;  // LDS table of the lane's copy: T[0], T[1], T[2], 0
@@ -441,7 +529,7 @@ struct IsingMetK {
 // 2^32 (s = +1 certain, large local field at large beta) are m < m_lim.
 template <int L>
 struct IsingHbK {
-  using G = GC<L>;
+  using G = IC<L>;
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK;
   IsingLane ln;
   const uint32_t *tab;      // LDS table of the lane's copy: T_HB[6 - m], m = 0..6, then 0
@@ -524,7 +612,7 @@ struct IsingKernelOf<L, 0> {
 
 template <int L, int ALGO>
 DEV void ising_run(const Work &w, uint32_t *lds) {
-  using G = GC<L>;
+  using G = IC<L>;
   const int t = threadIdx.x;
   const int nthr = blockDim.x;
   const int lanes = w.ncopies * G::NW;
@@ -563,6 +651,7 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   ln.z = wl - ln.g * L;
   ln.zp = ln.z + 1 == L ? 0 : ln.z + 1;
   ln.zm = ln.z == 0 ? L - 1 : ln.z - 1;
+  ln.zodd = (ln.z & 1) ? ~0u : 0u;
   ln.rJ = make_rsrc(w.J, w.J_bytes);
   ln.joff = ((uint32_t)(copy / w.RK) * ising_js(L) + ln.z) * 4u;
   ln.A = active ? w.thr[w.temp_of_slot[copy] * THR_WORDS + 15] : 0u;
@@ -658,7 +747,7 @@ DEV void gen_classify(uint32_t S, const uint32_t N[6], const uint32_t Jw[GEN_WOR
 
 template <int L, int ALGO>
 struct GenK {
-  using G = GC<L>;
+  using G = IC<L>;
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK, NWB = G::NWB;
   IsingLane ln;                // spins, couplings and position of the lane
   const uint32_t *tab;         // LDS threshold table of the lane's copy
@@ -765,7 +854,7 @@ struct GenK {
 
 template <int L, int ALGO>
 DEV void gen_run(const Work &w, uint32_t *lds) {
-  using G = GC<L>;
+  using G = IC<L>;
   const int t = threadIdx.x;
   const int nthr = blockDim.x;
   const int lanes = w.ncopies * G::NW;
@@ -796,6 +885,7 @@ DEV void gen_run(const Work &w, uint32_t *lds) {
   ln.z = wl - ln.g * L;
   ln.zp = ln.z + 1 == L ? 0 : ln.z + 1;
   ln.zm = ln.z == 0 ? L - 1 : ln.z - 1;
+  ln.zodd = (ln.z & 1) ? ~0u : 0u;
   ln.rJ = make_rsrc(w.J, w.J_bytes);
   ln.joff = ((uint32_t)(copy / w.RK) * gen_js(L) + ln.z) * 4u;
   k.tab = tabs + cl * GEN_TAB_STRIDE;

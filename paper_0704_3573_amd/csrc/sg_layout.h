@@ -2,14 +2,18 @@
 // the host-side packing code and the gfx950 kernels.  (Internal header; the
 // public boundary is include/sg.h.)
 //
-// Ising copy (bit-packed, 1 bit per spin, bit 1 <-> spin -1):
-//   The rho = min(8, L) rows of one z-plane served by one Parisi-Rapuano wheel
-//   are cut into NBLK blocks of RPB rows.  A block holds B = RPB * L/2 sites of
-//   one colour, exactly the B consecutive draws of the wheel, and is stored in
-//   one 32-bit word, most significant bit first: the k-th site of the block in
-//   draw order (row r, then x = 2j + e) sits at bit B - 1 - k.  Words are
-//   indexed [colour p][plane z][block-row wb] with the wb stride padded to an
-//   odd count WZ (LDS bank spread).  Unused high bits are zero.
+// Ising copy (bit-packed, 1 bit per spin, bit 1 <-> spin -1; igeom):
+//   The sites of one colour of a z-plane, taken row by row (y ascending) and
+//   within a row in increasing x, form a string of L * L/2 bits: site
+//   (x = 2j + e, y) is string position s = y L/2 + j.  The string is cut
+//   into 32-bit block words (B = min(32, L^2/2) sites each), most significant
+//   bit first: position s sits in word wb = s / B at bit B - 1 - s mod B.
+//   The rho = min(8, L) rows served by one Parisi-Rapuano wheel are the
+//   NBLK = rho L / (2 B) consecutive words of its row group, so a block word
+//   holds exactly B consecutive draws of the wheel; rows may straddle two
+//   words (L = 24, 40, 48, 56).  Words are indexed [colour p][plane z]
+//   [block word wb] with the wb stride padded to an odd count WZ (LDS bank
+//   spread).  Unused high bits (B < 32) are zero.
 // Ising couplings: six words per (colour, wb, z), one per bond direction
 //   (x+, x-, y+, y-, z+, z-), same bit order, bit 1 <-> J = -1, laid out
 //   [p][wb][d][z] so that the lanes of a wave (consecutive z) read one
@@ -62,6 +66,28 @@ SG_HD constexpr Geom geom(int L) {
   return g;
 }
 
+// Geometry of the bit-packed Ising copies (EA glass and the Ising-like
+// models): one block word of B = min(32, L^2/2) draws, NBLK = L/8 words per
+// row group for L >= 8 (one word per plane below).  RPB is not used.
+SG_HD constexpr Geom igeom(int L) {
+  Geom g{};
+  g.L = L;
+  g.RHO = L < 8 ? L : 8;
+  g.NG = L / g.RHO;
+  g.NW = L * g.NG;
+  g.H = L / 2;
+  g.RPB = 0;
+  g.B = g.RHO * g.H < 32 ? g.RHO * g.H : 32;
+  g.NBLK = g.RHO * g.H / g.B;
+  g.NWB = g.NG * g.NBLK;
+  g.WZ = g.NWB | 1;
+  g.CS = 2 * g.L * g.WZ;
+  g.V = (62 + g.B - 1) / g.B;
+  g.V += g.V & 1;
+  g.M = g.V * g.B;
+  return g;
+}
+
 SG_HD constexpr bool supported_L(int L) {
   return L == 2 || L == 4 || L == 8 || L == 16 || L == 24 || L == 32 || L == 40 || L == 48 ||
          L == 56 || L == 64;
@@ -70,7 +96,7 @@ SG_HD constexpr bool supported_L(int L) {
 SG_HD constexpr bool potts_supported_L(int L) { return supported_L(L) && L <= 48; }
 
 // Words of Ising couplings per sample.
-SG_HD constexpr int ising_js(int L) { return 2 * geom(L).NWB * 6 * L; }
+SG_HD constexpr int ising_js(int L) { return 2 * igeom(L).NWB * 6 * L; }
 
 // Potts pattern words per block and per sample.
 SG_HD constexpr int potts_bq(int L) { return (geom(L).B + 3) / 4; }
@@ -145,7 +171,7 @@ constexpr int POTTS_W_WORDS = 8;
 SG_HD constexpr int potts_lds_copy(int L) { return (L * L * L + 2 * geom(L).NG * L + 3) / 4 * 4; }
 
 // Ising-like models of Eq. (2) of the paper (dilution x_i, field h_i =
-// |h| f_i): spins as for the EA glass.  Per (colour p, block-row wb, plane z)
+// |h| f_i): spins as for the EA glass.  Per (colour p, block word wb, plane z)
 // 14 words in the site order of the spin words, laid out [p][wb][d][z]:
 //   d = 0..5   bit 1 <-> J = -1 on the bond in direction x+, x-, y+, y-, z+, z-
 //   d = 6..11  bit 1 <-> the neighbour in that direction is occupied
@@ -154,8 +180,8 @@ SG_HD constexpr int potts_lds_copy(int L) { return (L * L * L + 2 * geom(L).NG *
 // followed, per sample, by the occupancy bits of every site in the spin-copy
 // layout (CS words, pads zero) for the overlap.
 constexpr int GEN_WORDS = 14;
-SG_HD constexpr int gen_block_js(int L) { return 2 * geom(L).NWB * GEN_WORDS * L; }
-SG_HD constexpr int gen_js(int L) { return gen_block_js(L) + geom(L).CS; }
+SG_HD constexpr int gen_block_js(int L) { return 2 * igeom(L).NWB * GEN_WORDS * L; }
+SG_HD constexpr int gen_js(int L) { return gen_block_js(L) + igeom(L).CS; }
 // LDS threshold table of a copy: 32 words at an odd stride (bank spread).
 constexpr int GEN_TAB_STRIDE = 33;
 
