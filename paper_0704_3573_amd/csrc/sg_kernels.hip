@@ -173,10 +173,19 @@ DEV void count6(const uint32_t u[6], uint32_t &n0, uint32_t &n1, uint32_t &n2) {
   fadd(c1, c2, c3, n1, n2);
 }
 
+// Word pointer into LDS: 32-bit address arithmetic (a generic pointer into a
+// shared array costs 64-bit multiply-adds per access).
+typedef __attribute__((address_space(3))) uint32_t lds_w32;
+DEV lds_w32 *to_lds(uint32_t *p) { return (lds_w32 *)p; }
+
 // Per-lane context of the Ising sweep.
 struct IsingLane {
-  uint32_t *sp;        // LDS base of the lane's copy (lanes without a wheel: a
+  lds_w32 *sp;         // LDS base of the lane's copy (lanes without a wheel: a
                        // scratch copy they may read and overwrite)
+  lds_w32 *zb, *zpb, *zmb;  // first block word of the lane's row group in
+                            // planes z, z + 1, z - 1 (colour 0)
+  int nwrap, pwrap;    // word offsets from the group's last (first) block to
+                       // the plane's next (previous) one, across the wrap
   rsrc_t rJ;           // couplings of the job
   uint32_t joff;       // byte offset of (sample, z) in the couplings
   int z, zp, zm, g;
@@ -192,21 +201,21 @@ struct IsingLane {
 // last site, Q[s + 1 - L/2]; Q[s - 1] or, at its first site, Q[s - 1 + L/2].
 template <int L>
 DEV void ising_neighbours(const IsingLane &ln, int p, int blk, uint32_t &S, uint32_t N[6],
-                          uint32_t *&own) {
+                          lds_w32 *&own) {
   using G = IC<L>;
   if constexpr (G::NBLK == 1) blk = 0;
   const int q = p ^ 1;
-  const int wb = ln.g * G::NBLK + blk;
-  own = ln.sp + (p * L + ln.z) * G::WZ + wb;
+  constexpr int PL = L * G::WZ;  // words per colour
+  own = ln.zb + p * PL + blk;
   S = *own;
-  const uint32_t *oc = ln.sp + (q * L + ln.z) * G::WZ;
-  const uint32_t Wc = oc[wb];
-  N[4] = ln.sp[(q * L + ln.zp) * G::WZ + wb];  // z+
-  N[5] = ln.sp[(q * L + ln.zm) * G::WZ + wb];  // z-
+  const lds_w32 *oc = ln.zb + q * PL;
+  const uint32_t Wc = oc[blk];
+  N[4] = ln.zpb[q * PL + blk];  // z+
+  N[5] = ln.zmb[q * PL + blk];  // z-
   uint32_t Wn = Wc, Wp = Wc;
   if constexpr (G::NWB > 1) {
-    Wn = oc[wb + 1 == G::NWB ? 0 : wb + 1];
-    Wp = oc[wb == 0 ? G::NWB - 1 : wb - 1];
+    Wn = blk + 1 < G::NBLK ? oc[blk + 1] : oc[blk + 1 + ln.nwrap];
+    Wp = blk > 0 ? oc[blk - 1] : oc[blk - 1 + ln.pwrap];
   }
   constexpr int B = G::B, H = G::H;
   N[2] = str_next<B>(Wc, Wn, H);  // y+
@@ -325,7 +334,7 @@ DEV int ising_lane_unsat(const IsingLane &ln) {
 #pragma unroll
   for (int blk = 0; blk < G::NBLK; blk++) {
     uint32_t S, N[6], Jw[6], u[6];
-    uint32_t *own;
+    lds_w32 *own;
     ising_neighbours<L>(ln, 0, blk, S, N, own);
     ising_couplings<L>(ln, 0, blk, Jw);
 #pragma unroll
@@ -470,7 +479,7 @@ struct IsingMetK {
     else
       fetch(p ^ 1, 0);
     uint32_t S, N[6];
-    uint32_t *own;
+    lds_w32 *own;
     ising_neighbours<L>(ln, p, blk, S, N, own);
     uint32_t n0, n1, n2;
     {
@@ -548,7 +557,7 @@ struct IsingHbK {
     else
       fetch(p ^ 1, 0);
     uint32_t S, N[6];
-    uint32_t *own;
+    lds_w32 *own;
     ising_neighbours<L>(ln, p, blk, S, N, own);
     uint32_t n0, n1, n2;
     {
@@ -646,12 +655,17 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   const int cl = active ? t / G::NW : 0;
   const int wl = active ? t - cl * G::NW : t % L;
   const int copy = w.copy0 + cl;
-  ln.sp = active ? lds + cl * G::CS : scratch_copy;
+  ln.sp = to_lds(active ? lds + cl * G::CS : scratch_copy);
   ln.g = wl / L;
   ln.z = wl - ln.g * L;
   ln.zp = ln.z + 1 == L ? 0 : ln.z + 1;
   ln.zm = ln.z == 0 ? L - 1 : ln.z - 1;
   ln.zodd = (ln.z & 1) ? ~0u : 0u;
+  ln.zb = ln.sp + ln.z * G::WZ + ln.g * G::NBLK;
+  ln.zpb = ln.sp + ln.zp * G::WZ + ln.g * G::NBLK;
+  ln.zmb = ln.sp + ln.zm * G::WZ + ln.g * G::NBLK;
+  ln.nwrap = ln.g == G::NG - 1 ? -G::NWB : 0;
+  ln.pwrap = ln.g == 0 ? G::NWB : 0;
   ln.rJ = make_rsrc(w.J, w.J_bytes);
   ln.joff = ((uint32_t)(copy / w.RK) * ising_js(L) + ln.z) * 4u;
   ln.A = active ? w.thr[w.temp_of_slot[copy] * THR_WORDS + 15] : 0u;
@@ -773,7 +787,7 @@ struct GenK {
     else
       fetch(p ^ 1, 0);
     uint32_t S, N[6];
-    uint32_t *own;
+    lds_w32 *own;
     ising_neighbours<L>(ln, p, blk, S, N, own);
     uint32_t P[5];
     gen_classify<ALGO == 0>(S, N, Jw, P);
@@ -838,7 +852,7 @@ struct GenK {
     for (int p = 0; p < 2; p++)
       for (int blk = 0; blk < NBLK; blk++) {
         uint32_t Jw[GEN_WORDS], S, N[6], P[5];
-        uint32_t *own;
+        lds_w32 *own;
         load(p, blk, Jw);
         ising_neighbours<L>(ln, p, blk, S, N, own);
         const uint32_t X = Jw[12];
@@ -880,12 +894,17 @@ DEV void gen_run(const Work &w, uint32_t *lds) {
   const int cl = active ? t / G::NW : 0;
   const int wl = active ? t - cl * G::NW : t % L;
   const int copy = w.copy0 + cl;
-  ln.sp = active ? lds + cl * G::CS : scratch_copy;
+  ln.sp = to_lds(active ? lds + cl * G::CS : scratch_copy);
   ln.g = wl / L;
   ln.z = wl - ln.g * L;
   ln.zp = ln.z + 1 == L ? 0 : ln.z + 1;
   ln.zm = ln.z == 0 ? L - 1 : ln.z - 1;
   ln.zodd = (ln.z & 1) ? ~0u : 0u;
+  ln.zb = ln.sp + ln.z * G::WZ + ln.g * G::NBLK;
+  ln.zpb = ln.sp + ln.zp * G::WZ + ln.g * G::NBLK;
+  ln.zmb = ln.sp + ln.zm * G::WZ + ln.g * G::NBLK;
+  ln.nwrap = ln.g == G::NG - 1 ? -G::NWB : 0;
+  ln.pwrap = ln.g == 0 ? G::NWB : 0;
   ln.rJ = make_rsrc(w.J, w.J_bytes);
   ln.joff = ((uint32_t)(copy / w.RK) * gen_js(L) + ln.z) * 4u;
   k.tab = tabs + cl * GEN_TAB_STRIDE;
