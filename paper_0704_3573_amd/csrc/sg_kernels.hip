@@ -45,6 +45,27 @@ DEV void bstore(rsrc_t r, uint32_t v, uint32_t voff, uint32_t soff = 0) {
   __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, 0);
 }
 
+// Staging of n words from HBM into LDS by the whole workgroup with U loads
+// in flight per thread (one wait per U words rather than one HBM round trip
+// per word): load(i) reads word i (i < n), put(i, v) stores it.
+template <int U, class Load, class Put>
+DEV void stage_words(int n, Load load, Put put) {
+  const int t = threadIdx.x, nthr = blockDim.x;
+  for (int i0 = t; i0 < n; i0 += U * nthr) {
+    uint32_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int i = i0 + u * nthr;
+      v[u] = i < n ? load(i) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int i = i0 + u * nthr;
+      if (i < n) put(i, v[u]);
+    }
+  }
+}
+
 template <int L>
 struct GC {
   static constexpr Geom g = geom(L);
@@ -260,12 +281,16 @@ DEV void ising_couplings(const IsingLane &ln, int p, int blk, uint32_t Jw[6]) {
 // stage 1 of draw 0, then for each draw i: stage 1 of draw i + 1, insert of
 // draw i, so every mask is read at least two instructions after it was
 // written; the block's last insert follows an explicit wait.
+// r is a read-write operand so that one register holds it through the whole
+// draw loop: left dead after the compare, its register would be handed to
+// the next table address add, and an SDWA write to a register written by the
+// previous instructions costs a wait state.
 DEV void met_s1(uint32_t &inew, uint32_t a24, uint32_t a55, uint32_t a61, uint32_t T,
                 uint32_t &r, uint64_t &m) {
   asm volatile("v_add_u32 %[n], %[a], %[b]\n\t"
                "v_xor_b32 %[r], %[n], %[c]\n\t"
                "v_cmp_lt_u32 %[m], %[r], %[T]"
-               : [n] "=&v"(inew), [r] "=&v"(r), [m] "=&s"(m)
+               : [n] "=&v"(inew), [r] "+&v"(r), [m] "=&s"(m)
                : [a] "v"(a24), [b] "v"(a55), [c] "v"(a61), [T] "v"(T));
 }
 
@@ -294,19 +319,19 @@ DEV uint32_t add_byte(int n, uint32_t base, uint32_t x) {
   uint32_t r;
   switch (n) {
     case 0:
-      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+      asm volatile("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
           : "=v"(r) : "v"(base), "v"(x));
       break;
     case 1:
-      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+      asm volatile("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
           : "=v"(r) : "v"(base), "v"(x));
       break;
     case 2:
-      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+      asm volatile("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
           : "=v"(r) : "v"(base), "v"(x));
       break;
     default:
-      asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+      asm volatile("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
           : "=v"(r) : "v"(base), "v"(x));
       break;
   }
@@ -317,12 +342,18 @@ DEV uint32_t add_byte(int n, uint32_t base, uint32_t x) {
 typedef __attribute__((address_space(3))) const uint32_t lds_u32;
 DEV uint32_t lds_offset(const uint32_t *p) { return (uint32_t)(uintptr_t)(lds_u32 *)p; }
 
-// Single compare-result insert: acc = 2 acc + c (first: acc = c).
+// Single compare-result insert: acc = 2 acc + c (first: acc = c).  The
+// carry-out goes to an unused SGPR pair, not VCC: the compiler pads a VCC
+// write followed by an SDWA instruction (the table address adds) with a wait
+// state.
 DEV void ins1(bool first, uint64_t m, uint32_t &acc) {
+  uint64_t co;
   if (first)
-    asm volatile("v_addc_co_u32 %[a], vcc, 0, 0, %[m]" : [a] "=&v"(acc) : [m] "s"(m) : "vcc");
+    asm volatile("v_addc_co_u32 %[a], %[co], 0, 0, %[m]" : [a] "=&v"(acc), [co] "=s"(co) : [m] "s"(m));
   else
-    asm volatile("v_addc_co_u32 %[a], vcc, %[a], %[a], %[m]" : [a] "+v"(acc) : [m] "s"(m) : "vcc");
+    asm volatile("v_addc_co_u32 %[a], %[co], %[a], %[a], %[m]"
+                 : [a] "+v"(acc), [co] "=s"(co)
+                 : [m] "s"(m));
 }
 
 // Number of unsatisfied bonds touching the lane's colour-0 sites (every bond
@@ -430,6 +461,9 @@ DEV void drive(K &k, Drive &d) {
   }
   uint32_t ring[K::M];
   if (d.active) ring_load<K::M>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+  // wait for the ring once here: with loads still in flight on entry, the
+  // sweep loop would carry a vector-memory wait in front of every draw
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   if constexpr (K::NBLK % K::V == 0) {
     for (int s = 0; s < d.nsweeps; s++)
       for (int p = 0; p < 2; p++) {
@@ -509,8 +543,11 @@ struct IsingMetK {
     __builtin_amdgcn_sched_barrier(0);
 
     static_assert(B >= 2, "the draw pipeline needs two draws per block");
-    uint32_t acc = 0, r;
+    uint32_t acc = 0, r = 0;
     uint64_t m[B];
+    // per step: add, xor and compare of draw i + 1; the address add and
+    // read of draw i + PF; the insert of draw i (an insert directly before an
+    // SDWA address add would cost a wait state)
     auto s1 = [&](int i) {
       const int k = VI * B + i;  // static after unrolling
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
@@ -519,11 +556,11 @@ struct IsingMetK {
     s1(0);
 #pragma unroll
     for (int i = 0; i < B; i++) {
-      if (i + PF < B) load(i + PF);
       if (i + 1 < B)
         s1(i + 1);
       else
         asm volatile("s_nop 1");
+      if (i + PF < B) load(i + PF);
       ins1(i == 0, m[i], acc);
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -588,8 +625,11 @@ struct IsingHbK {
     __builtin_amdgcn_sched_barrier(0);
 
     static_assert(B >= 2, "the draw pipeline needs two draws per block");
-    uint32_t acc = 0, r;
+    uint32_t acc = 0, r = 0;
     uint64_t m[B];
+    // per step: add, xor and compare of draw i + 1; the address add and
+    // read of draw i + PF; the insert of draw i (an insert directly before an
+    // SDWA address add would cost a wait state)
     auto s1 = [&](int i) {
       const int k = VI * B + i;  // static after unrolling
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
@@ -598,11 +638,11 @@ struct IsingHbK {
     s1(0);
 #pragma unroll
     for (int i = 0; i < B; i++) {
-      if (i + PF < B) load(i + PF);
       if (i + 1 < B)
         s1(i + 1);
       else
         asm volatile("s_nop 1");
+      if (i + PF < B) load(i + PF);
       ins1(i == 0, m[i], acc);
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -631,9 +671,8 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   uint32_t *tabs = scratch_copy + G::CS;  // [ncopies][ISING_TAB_STRIDE] thresholds
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
 
-  // stage the copies and their threshold tables in LDS
+  // stage the threshold tables and the copies in LDS
   const uint32_t sbase = (uint32_t)w.copy0 * G::CS * 4u;
-  for (int i = t; i < w.ncopies * G::CS; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
   for (int i = t; i < w.ncopies; i += nthr) Ucnt[i] = 0;
   if constexpr (ALGO == 0)
     for (int i = t; i < w.ncopies * 4; i += nthr) {
@@ -647,6 +686,9 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
       tabs[c * ISING_TAB_STRIDE + e] =
           e < 7 ? w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + 6 - e] : 0u;
     }
+  stage_words<8>(
+      w.ncopies * G::CS, [&](int i) { return bload(rsp, i * 4, sbase); },
+      [&](int i, uint32_t v) { lds[i] = v; });
 
   // lanes without a wheel serve wheel (z = t mod L, row group 0) of the
   // scratch copy, so all their accesses stay inside it
@@ -819,7 +861,7 @@ struct GenK {
     // the result into acc; each compare mask is read three or more
     // instructions after it was written (the last one after a wait)
     static_assert(B >= 2, "the draw pipeline needs two draws per block");
-    uint32_t acc = 0, r;
+    uint32_t acc = 0, r = 0;
     uint64_t m[B];
     auto s1 = [&](int i) {
       const int k = VI * B + i;  // static after unrolling
@@ -880,12 +922,14 @@ DEV void gen_run(const Work &w, uint32_t *lds) {
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
 
   const uint32_t sbase = (uint32_t)w.copy0 * G::CS * 4u;
-  for (int i = t; i < w.ncopies * G::CS; i += nthr) lds[i] = bload(rsp, i * 4, sbase);
   for (int i = t; i < w.ncopies * 32; i += nthr) {
     const int c = i >> 5, e = i & 31;
     tabs[c * GEN_TAB_STRIDE + e] = w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + e];
   }
   for (int i = t; i < 2 * w.ncopies; i += nthr) Ecnt[i] = 0;
+  stage_words<8>(
+      w.ncopies * G::CS, [&](int i) { return bload(rsp, i * 4, sbase); },
+      [&](int i, uint32_t v) { lds[i] = v; });
 
   // lanes without a wheel serve wheel (z = t mod L, row group 0) of the
   // scratch copy with the first copy's table
@@ -1185,15 +1229,17 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
       tab[i] = d < 6 && ((pat >> d) & 1) ? 0x04040400u : 4u;
     }
   }
-  // word u of a copy in HBM (rows at y L^2) -> LDS word u + (row group) L / 2
-  for (int i = t; i < w.ncopies * (N3 / 4); i += nthr) {
-    const int c = i / (N3 / 4), u = i - c * (N3 / 4);
-    cp[c * CW + u + (u / GW) * L / 2] = bload(rsp, i * 4, sbase);
-  }
   for (int i = t; i < w.ncopies * POTTS_W_WORDS; i += nthr) {
     const int c = w.copy0 + i / POTTS_W_WORDS;
     Wt[i] = w.thr[w.temp_of_slot[c] * THR_WORDS + i % POTTS_W_WORDS];
   }
+  // word u of a copy in HBM (rows at y L^2) -> LDS word u + (row group) L / 2
+  stage_words<8>(
+      w.ncopies * (N3 / 4), [&](int i) { return bload(rsp, i * 4, sbase); },
+      [&](int i, uint32_t v) {
+        const int c = i / (N3 / 4), u = i - c * (N3 / 4);
+        cp[c * CW + u + (u / GW) * L / 2] = v;
+      });
   for (int i = t; i < w.ncopies; i += nthr) Hcnt[i] = 0;
 
   // lanes without a wheel run the blocks of wheel (z = t mod L, row group 0)
@@ -1455,15 +1501,17 @@ DEV void potts4_run(const Work &w, uint32_t *lds) {
   }
   // HBM word q of a copy ([y][u][x][z], u planes L^2 bytes apart) -> LDS
   // (u planes potts4_us(L) bytes apart)
-  for (int i = t; i < w.ncopies * (N4 / 4); i += nthr) {
-    const int c = i / (N4 / 4), q = i - c * (N4 / 4);
-    const int yu = q / (L2 / 4), r = q - yu * (L2 / 4);
-    cp[c * CW + yu * UW + r] = bload(rsp, i * 4, sbase);
-  }
   for (int i = t; i < w.ncopies * POTTS4_W_WORDS; i += nthr) {
     const int c = w.copy0 + i / POTTS4_W_WORDS;
     Wt[i] = w.thr[w.temp_of_slot[c] * THR_WORDS + i % POTTS4_W_WORDS];
   }
+  stage_words<8>(
+      w.ncopies * (N4 / 4), [&](int i) { return bload(rsp, i * 4, sbase); },
+      [&](int i, uint32_t v) {
+        const int c = i / (N4 / 4), q = i - c * (N4 / 4);
+        const int yu = q / (L2 / 4), r = q - yu * (L2 / 4);
+        cp[c * CW + yu * UW + r] = v;
+      });
   for (int i = t; i < w.ncopies; i += nthr) Hcnt[i] = 0;
 
   // lanes without a wheel run the blocks of wheel (z = t mod L, u = 0, row
