@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include "sg_layout.h"
+#include <type_traits>
 
 #define DEV __device__ __forceinline__
 
@@ -260,12 +261,13 @@ template <int L>
 DEV void ising_couplings(const IsingLane &ln, int p, int blk, uint32_t Jw[6]) {
   using G = IC<L>;
   // per-lane part (sample, row group, plane) in the VGPR offset, the
-  // wave-uniform part (colour, block, direction) in the SGPR offset
+  // wave-uniform part (colour, block) in the SGPR offset, the direction in
+  // the instruction's immediate offset
   const uint32_t voff = ln.joff + (uint32_t)(ln.g * G::NBLK * 6 * L) * 4u;
   const uint32_t soff =
       __builtin_amdgcn_readfirstlane((uint32_t)((p * G::NWB + blk) * 6 * L) * 4u);
 #pragma unroll
-  for (int d = 0; d < 6; d++) Jw[d] = bload(ln.rJ, voff, soff + d * L * 4);
+  for (int d = 0; d < 6; d++) Jw[d] = bload(ln.rJ, voff + d * L * 4, soff);
 }
 
 // Per-draw ALU steps in inline assembly.  Each draw computes
@@ -342,17 +344,42 @@ DEV uint32_t add_byte(int n, uint32_t base, uint32_t x) {
 typedef __attribute__((address_space(3))) const uint32_t lds_u32;
 DEV uint32_t lds_offset(const uint32_t *p) { return (uint32_t)(uintptr_t)(lds_u32 *)p; }
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [A, B).
+template <int A, int B, class F>
+DEV void static_for(F &&f) {
+  if constexpr (A < B) {
+    f(std::integral_constant<int, A>{});
+    static_for<A + 1, B>(f);
+  }
+}
+
+// Wait until at most N vector-memory operations are outstanding (lgkmcnt
+// and expcnt left at their maxima).
+template <int N>
+DEV void vm_wait() {
+  static_assert(N >= 0 && N <= 63, "vmcnt is a 6-bit field");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// Wait until at most N LDS/scalar-memory operations are outstanding (gfx9
+// s_waitcnt encoding: vmcnt and expcnt left at their maxima).
+template <int N>
+DEV void lgkm_wait() {
+  static_assert(N >= 0 && N <= 15, "lgkmcnt is a 4-bit field");
+  __builtin_amdgcn_s_waitcnt(0xC07F | (N << 8));
+}
+
 // Single compare-result insert: acc = 2 acc + c (first: acc = c).  The
-// carry-out goes to an unused SGPR pair, not VCC: the compiler pads a VCC
-// write followed by an SDWA instruction (the table address adds) with a wait
-// state.
-DEV void ins1(bool first, uint64_t m, uint32_t &acc) {
-  uint64_t co;
+// carry-out goes to an SGPR pair co that the draw loop holds for it alone
+// (not VCC, and never a compare mask's register): the compiler pads a wait
+// state after an SGPR write when the next statement is inline assembly
+// that writes or reads the same register, or an SDWA instruction.
+DEV void ins1(bool first, uint64_t m, uint32_t &acc, uint64_t &co) {
   if (first)
-    asm volatile("v_addc_co_u32 %[a], %[co], 0, 0, %[m]" : [a] "=&v"(acc), [co] "=s"(co) : [m] "s"(m));
+    asm volatile("v_addc_co_u32 %[a], %[co], 0, 0, %[m]" : [a] "=&v"(acc), [co] "+&s"(co) : [m] "s"(m));
   else
     asm volatile("v_addc_co_u32 %[a], %[co], %[a], %[a], %[m]"
-                 : [a] "+v"(acc), [co] "=s"(co)
+                 : [a] "+v"(acc), [co] "+&s"(co)
                  : [m] "s"(m));
 }
 
@@ -517,6 +544,7 @@ struct IsingMetK {
     ising_neighbours<L>(ln, p, blk, S, N, own);
     uint32_t n0, n1, n2;
     {
+      vm_wait<6>();  // this block's couplings; the next block's stay in flight
       uint32_t u[6];
 #pragma unroll
       for (int d = 0; d < 6; d++) u[d] = S ^ N[d] ^ Jw[d];
@@ -544,6 +572,7 @@ struct IsingMetK {
 
     static_assert(B >= 2, "the draw pipeline needs two draws per block");
     uint32_t acc = 0, r = 0;
+    uint64_t co = 0;
     uint64_t m[B];
     // per step: add, xor and compare of draw i + 1; the address add and
     // read of draw i + PF; the insert of draw i (an insert directly before an
@@ -553,16 +582,29 @@ struct IsingMetK {
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
              T[i], r, m[i]);
     };
+    // one LDS wait per two draws: before draw j (j odd) the reads of draws
+    // 0 .. min(j + PF - 2, B - 1) have been issued; those after j + 1 may
+    // stay in flight
+    auto pair_wait = [&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      if constexpr (j % 2 == 1) {
+        constexpr int last = j + PF - 2 < B - 1 ? j + PF - 2 : B - 1;
+        constexpr int after = last - (j + 1 < B ? j + 1 : j);
+        lgkm_wait<(after > 0 ? after : 0)>();
+      }
+    };
     s1(0);
-#pragma unroll
-    for (int i = 0; i < B; i++) {
-      if (i + 1 < B)
+    static_for<0, B>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      if constexpr (i + 1 < B) {
+        pair_wait(std::integral_constant<int, i + 1>{});
         s1(i + 1);
-      else
+      } else {
         asm volatile("s_nop 1");
-      if (i + PF < B) load(i + PF);
-      ins1(i == 0, m[i], acc);
-    }
+      }
+      if constexpr (i + PF < B) load(i + PF);
+      ins1(i == 0, m[i], acc, co);
+    });
     __builtin_amdgcn_sched_barrier(0);
     *own = S ^ ((cert | acc) & G::MB);
   }
@@ -598,6 +640,7 @@ struct IsingHbK {
     ising_neighbours<L>(ln, p, blk, S, N, own);
     uint32_t n0, n1, n2;
     {
+      vm_wait<6>();  // this block's couplings; the next block's stay in flight
       uint32_t u[6];
 #pragma unroll
       for (int d = 0; d < 6; d++) u[d] = N[d] ^ Jw[d];  // 1: J s_j = -1
@@ -626,6 +669,7 @@ struct IsingHbK {
 
     static_assert(B >= 2, "the draw pipeline needs two draws per block");
     uint32_t acc = 0, r = 0;
+    uint64_t co = 0;
     uint64_t m[B];
     // per step: add, xor and compare of draw i + 1; the address add and
     // read of draw i + PF; the insert of draw i (an insert directly before an
@@ -635,16 +679,29 @@ struct IsingHbK {
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
              T[i], r, m[i]);
     };
+    // one LDS wait per two draws: before draw j (j odd) the reads of draws
+    // 0 .. min(j + PF - 2, B - 1) have been issued; those after j + 1 may
+    // stay in flight
+    auto pair_wait = [&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      if constexpr (j % 2 == 1) {
+        constexpr int last = j + PF - 2 < B - 1 ? j + PF - 2 : B - 1;
+        constexpr int after = last - (j + 1 < B ? j + 1 : j);
+        lgkm_wait<(after > 0 ? after : 0)>();
+      }
+    };
     s1(0);
-#pragma unroll
-    for (int i = 0; i < B; i++) {
-      if (i + 1 < B)
+    static_for<0, B>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      if constexpr (i + 1 < B) {
+        pair_wait(std::integral_constant<int, i + 1>{});
         s1(i + 1);
-      else
+      } else {
         asm volatile("s_nop 1");
-      if (i + PF < B) load(i + PF);
-      ins1(i == 0, m[i], acc);
-    }
+      }
+      if constexpr (i + PF < B) load(i + PF);
+      ins1(i == 0, m[i], acc, co);
+    });
     __builtin_amdgcn_sched_barrier(0);
     *own = ~(below | acc) & G::MB;  // bit 1 <-> spin -1
   }
@@ -862,6 +919,7 @@ struct GenK {
     // instructions after it was written (the last one after a wait)
     static_assert(B >= 2, "the draw pipeline needs two draws per block");
     uint32_t acc = 0, r = 0;
+    uint64_t co = 0;
     uint64_t m[B];
     auto s1 = [&](int i) {
       const int k = VI * B + i;  // static after unrolling
@@ -875,7 +933,7 @@ struct GenK {
         s1(i + 1);
       else
         asm volatile("s_nop 1");
-      ins1(i == 0, m[i], acc);
+      ins1(i == 0, m[i], acc, co);
     }
     __builtin_amdgcn_sched_barrier(0);
 
