@@ -553,11 +553,18 @@ struct IsingMetK {
     // n >= m  <=>  n2 or (n1, n0) >= (mhi, mlo)
     const uint32_t below = bfi(n1 ^ mhi, mhi, ~n0 & mlo);
     const uint32_t cert = n2 | ~below;
-    // byte j of word w = 4 (n mod 4) of the site at bit w + 8 j
+    // byte j of word w (= 2 t + e) is the byte offset into the table of
+    // the site at bit w + 8 j: after the bit-pair interleave its count pair
+    // (n mod 4) sits at bits 2t, 2t + 1 of byte j of z[e]; masked in place
+    // it is the offset of entry v at word v (t = 1), 4 v (t = 2) or 16 v
+    // (t = 3); pairs at t = 0 are moved up by two bits first
     uint32_t Kw[8], z[2];
     pair_planes(n0, n1, z[0], z[1]);
 #pragma unroll
-    for (int w = 0; w < 8; w++) Kw[w] = shr(z[w & 1], 2 * (w >> 1) - 2) & 0x0C0C0C0Cu;
+    for (int w = 0; w < 8; w++) {
+      const int t = w >> 1;
+      Kw[w] = t == 0 ? (z[w & 1] << 2) & 0x0C0C0C0Cu : z[w & 1] & (0x03030303u << (2 * t));
+    }
     const uint32_t tbase = lds_offset(tab);
     uint32_t T[B];
     // threshold of draw i (site at bit B - 1 - i), read PF draws ahead
@@ -731,11 +738,11 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   // stage the threshold tables and the copies in LDS
   const uint32_t sbase = (uint32_t)w.copy0 * G::CS * 4u;
   for (int i = t; i < w.ncopies; i += nthr) Ucnt[i] = 0;
-  if constexpr (ALGO == 0)
-    for (int i = t; i < w.ncopies * 4; i += nthr) {
-      const int c = i >> 2, e = i & 3;
-      tabs[c * ISING_TAB_STRIDE + e] =
-          e < 3 ? w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + e] : 0u;
+  if constexpr (ALGO == 0)  // T[v] at words v, 4 v, 16 v (word 0 written thrice, same value)
+    for (int i = t; i < w.ncopies * 12; i += nthr) {
+      const int c = i / 12, k = (i % 12) >> 2, v = i & 3;
+      tabs[c * ISING_TAB_STRIDE + (v << (2 * k))] =
+          v < 3 ? w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + v] : 0u;
     }
   else  // heat bath: entry m holds T_HB[6 - m]
     for (int i = t; i < w.ncopies * 8; i += nthr) {

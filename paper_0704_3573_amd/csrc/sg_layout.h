@@ -185,9 +185,12 @@ SG_HD constexpr int gen_js(int L) { return gen_block_js(L) + igeom(L).CS; }
 // LDS threshold table of a copy: 32 words at an odd stride (bank spread).
 constexpr int GEN_TAB_STRIDE = 33;
 
-// Ising: LDS threshold table of a copy at an odd stride of 9 words
-// (Metropolis: T[0..2], 0; heat bath: T_HB[6 - m] for m = 0..6, 0).
-constexpr int ISING_TAB_STRIDE = 9;
+// Ising: LDS threshold table of a copy at an odd stride of 49 words.
+// Metropolis: T[v] (v = n mod 4 of the unsatisfied-bond count n, T[3] = 0)
+// at words v, 4 v and 16 v (the count pair read at byte offsets 4 v, 16 v
+// or 64 v, by its position in the byte); heat bath: T_HB[6 - m] at words
+// m = 0..6, then 0.
+constexpr int ISING_TAB_STRIDE = 49;
 
 // Per-temperature threshold row: 32 words.  Ising Metropolis uses [0..2],
 // heat bath [0..6], Potts [0..12]; a threshold equal to 2^32 is stored as
