@@ -879,7 +879,7 @@ struct GenK {
     const uint32_t s0 =
         __builtin_amdgcn_readfirstlane((uint32_t)((p * NWB + blk) * GEN_WORDS * L) * 4u);
 #pragma unroll
-    for (int d = 0; d < GEN_WORDS; d++) Jw[d] = bload(ln.rJ, voff, s0 + d * L * 4);
+    for (int d = 0; d < GEN_WORDS; d++) Jw[d] = bload(ln.rJ, voff + d * L * 4, s0);
   }
   DEV void fetch(int p, int blk) { load(p, blk, nextJ); }
 
@@ -896,6 +896,7 @@ struct GenK {
     lds_w32 *own;
     ising_neighbours<L>(ln, p, blk, S, N, own);
     uint32_t P[5];
+    vm_wait<GEN_WORDS>();  // this block's words; the next block's stay in flight
     gen_classify<ALGO == 0>(S, N, Jw, P);
     const uint32_t lo = lt4(P, m0), hi = lt4(P, m1);
     const uint32_t cert = ALGO == 0 ? bfi(P[4], hi, lo) : ~bfi(P[4], hi, lo);
@@ -914,16 +915,20 @@ struct GenK {
     }
     const uint32_t tbase = lds_offset(tab);
     uint32_t T[B];
-#pragma unroll
-    for (int i = 0; i < B; i++) {
-      const int q = B - 1 - i;  // bit of the i-th draw's site
+    // threshold of draw i (site at bit B - 1 - i), read PF draws ahead
+    auto load = [&](int i) {
+      const int q = B - 1 - i;
       T[i] = *(const lds_u32 *)(uintptr_t)add_byte(q >> 3, tbase, Kw[q & 7]);
-    }
+    };
+    constexpr int PF = B < 8 ? B : 8;
+#pragma unroll
+    for (int i = 0; i < PF; i++) load(i);
     __builtin_amdgcn_sched_barrier(0);
 
     // draws: r = I(k) xor I(k-61), compare with the site's threshold, shift
-    // the result into acc; each compare mask is read three or more
-    // instructions after it was written (the last one after a wait)
+    // the result into acc; per step the compare of draw i + 1, the table
+    // read of draw i + PF and the insert of draw i, with one LDS wait per
+    // two draws (as in the EA kernel)
     static_assert(B >= 2, "the draw pipeline needs two draws per block");
     uint32_t acc = 0, r = 0;
     uint64_t co = 0;
@@ -933,15 +938,26 @@ struct GenK {
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
              T[i], r, m[i]);
     };
+    auto pair_wait = [&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      if constexpr (j % 2 == 1) {
+        constexpr int last = j + PF - 2 < B - 1 ? j + PF - 2 : B - 1;
+        constexpr int after = last - (j + 1 < B ? j + 1 : j);
+        lgkm_wait<(after > 0 ? after : 0)>();
+      }
+    };
     s1(0);
-#pragma unroll
-    for (int i = 0; i < B; i++) {
-      if (i + 1 < B)
+    static_for<0, B>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      if constexpr (i + 1 < B) {
+        pair_wait(std::integral_constant<int, i + 1>{});
         s1(i + 1);
-      else
+      } else {
         asm volatile("s_nop 1");
+      }
+      if constexpr (i + PF < B) load(i + PF);
       ins1(i == 0, m[i], acc, co);
-    }
+    });
     __builtin_amdgcn_sched_barrier(0);
 
     const uint32_t X = Jw[12];
