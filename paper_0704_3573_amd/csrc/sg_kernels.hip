@@ -1775,15 +1775,37 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
   int32_t *so = (int32_t *)(lds + 64 * 62 + 64 * kmax) + t * kmax;  // slot by temperature
   uint64_t *Fl = (uint64_t *)(lds + 64 * 62 + 128 * kmax);       // [K-1][24]
   for (int i = t; i < (K - 1) * 24; i += 64) Fl[i] = w.F[i];
+  // the workgroup's chains are consecutive: stage their wheels (64 words per
+  // chain in memory, 62 used), energies and permutations cooperatively,
+  // coalesced and with several loads in flight per thread
+  const int nch = w.nchains;
+  const uint32_t *gw0 = w.ptw + (size_t)w.chain0 * 64;
+  stage_words<8>(
+      nch * 64, [&](int i) { return gw0[i]; },
+      [&](int i, uint32_t v) {
+        if ((i & 63) < 62) lds[(i >> 6) * 62 + (i & 63)] = v;
+      });
+  // |E| <= 3 L^3 fits 32 bits: the low word of each int64 energy
+  const uint32_t *E0 = (const uint32_t *)(w.E + (size_t)w.chain0 * K);
+  const uint32_t *S0 = (const uint32_t *)(w.slot_of_temp + (size_t)w.chain0 * K);
+  int32_t *EsAll = (int32_t *)(lds + 64 * 62);
+  int32_t *soAll = (int32_t *)(lds + 64 * 62 + 64 * kmax);
+  stage_words<8>(
+      nch * K, [&](int i) { return E0[2 * i]; },
+      [&](int i, uint32_t v) {
+        const int c = i / K;
+        EsAll[c * kmax + (i - c * K)] = (int32_t)v;
+      });
+  stage_words<8>(
+      nch * K, [&](int i) { return S0[i]; },
+      [&](int i, uint32_t v) {
+        const int c = i / K;
+        soAll[c * kmax + (i - c * K)] = (int32_t)v;
+      });
   __syncthreads();
-  if (t >= w.nchains) return;
+  if (t >= nch) return;
   const int ch = w.chain0 + t;
-  const uint32_t *gw = w.ptw + (size_t)ch * 64;
-  for (int j = 0; j < 62; j++) ring[j] = gw[j];
-  for (int k = 0; k < K; k++) {
-    Es[k] = (int32_t)w.E[(size_t)ch * K + k];  // |E| <= 3 L^3 fits 32 bits
-    so[k] = w.slot_of_temp[(size_t)ch * K + k];
-  }
+  uint64_t accepted = 0;  // bit i: the swap of temperatures i, i + 1 was accepted
   for (int i = 0; i + 1 < K; i++) {
     const int a = so[i], b = so[i + 1];
     const int32_t D = Es[b] - Es[a];
@@ -1809,9 +1831,15 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
     if (accept) {
       so[i] = b;
       so[i + 1] = a;
-      if (w.accepts) w.accepts[(size_t)ch * (K - 1) + i]++;
+      accepted |= 1ull << i;
     }
   }
+  // each counter belongs to this thread alone; atomics whose result is not
+  // used leave the thread without a dependent load per accepted swap
+  if (w.accepts)
+    for (uint64_t m = accepted; m; m &= m - 1)
+      atomicAdd((unsigned long long *)&w.accepts[(size_t)ch * (K - 1) + __ffsll((unsigned long long)m) - 1],
+                1ull);
   uint32_t *gwo = w.ptw + (size_t)ch * 64;
   for (int j = 0; j < 62; j++) gwo[j] = ring[j];
   for (int k = 0; k < K; k++) {
