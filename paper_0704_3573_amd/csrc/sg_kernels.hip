@@ -369,6 +369,23 @@ DEV void lgkm_wait() {
   __builtin_amdgcn_s_waitcnt(0xC07F | (N << 8));
 }
 
+// Table reads run PF draws ahead of their compares.  Before the compare of
+// draw J, every G draws (J = 1, G + 1, 2 G + 1, ...), one LDS wait covers the
+// reads of draws J .. J + G - 1; the reads issued after them (up to draw
+// J + PF - 2) stay in flight.  The compiler still adds a wait of its own
+// wherever one of these is not enough, so the counts only save issue slots.
+// Measured: the EA kernels are fastest with G = 2 (with G = 4 the compares
+// wait on reads issued only five draws earlier), the Ising-like kernel,
+// with more VALU work per block, with G = 4.
+template <int G, int PF, int B, int J>
+DEV void group_wait() {
+  if constexpr ((J - 1) % G == 0) {
+    constexpr int last = J + PF - 2 < B - 1 ? J + PF - 2 : B - 1;
+    constexpr int need = J + G - 1 < B - 1 ? J + G - 1 : B - 1;
+    lgkm_wait<(last - need > 0 ? last - need : 0)>();
+  }
+}
+
 // Single compare-result insert: acc = 2 acc + c (first: acc = c).  The
 // carry-out goes to an SGPR pair co that the draw loop holds for it alone
 // (not VCC, and never a compare mask's register): the compiler pads a wait
@@ -589,22 +606,12 @@ struct IsingMetK {
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
              T[i], r, m[i]);
     };
-    // one LDS wait per two draws: before draw j (j odd) the reads of draws
-    // 0 .. min(j + PF - 2, B - 1) have been issued; those after j + 1 may
-    // stay in flight
-    auto pair_wait = [&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      if constexpr (j % 2 == 1) {
-        constexpr int last = j + PF - 2 < B - 1 ? j + PF - 2 : B - 1;
-        constexpr int after = last - (j + 1 < B ? j + 1 : j);
-        lgkm_wait<(after > 0 ? after : 0)>();
-      }
-    };
+    // one LDS wait per two draws (group_wait)
     s1(0);
     static_for<0, B>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       if constexpr (i + 1 < B) {
-        pair_wait(std::integral_constant<int, i + 1>{});
+        group_wait<2, PF, B, i + 1>();
         s1(i + 1);
       } else {
         asm volatile("s_nop 1");
@@ -686,22 +693,12 @@ struct IsingHbK {
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
              T[i], r, m[i]);
     };
-    // one LDS wait per two draws: before draw j (j odd) the reads of draws
-    // 0 .. min(j + PF - 2, B - 1) have been issued; those after j + 1 may
-    // stay in flight
-    auto pair_wait = [&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      if constexpr (j % 2 == 1) {
-        constexpr int last = j + PF - 2 < B - 1 ? j + PF - 2 : B - 1;
-        constexpr int after = last - (j + 1 < B ? j + 1 : j);
-        lgkm_wait<(after > 0 ? after : 0)>();
-      }
-    };
+    // one LDS wait per two draws (group_wait)
     s1(0);
     static_for<0, B>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       if constexpr (i + 1 < B) {
-        pair_wait(std::integral_constant<int, i + 1>{});
+        group_wait<2, PF, B, i + 1>();
         s1(i + 1);
       } else {
         asm volatile("s_nop 1");
@@ -928,7 +925,7 @@ struct GenK {
     // draws: r = I(k) xor I(k-61), compare with the site's threshold, shift
     // the result into acc; per step the compare of draw i + 1, the table
     // read of draw i + PF and the insert of draw i, with one LDS wait per
-    // two draws (as in the EA kernel)
+    // four draws (group_wait)
     static_assert(B >= 2, "the draw pipeline needs two draws per block");
     uint32_t acc = 0, r = 0;
     uint64_t co = 0;
@@ -938,19 +935,11 @@ struct GenK {
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
              T[i], r, m[i]);
     };
-    auto pair_wait = [&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      if constexpr (j % 2 == 1) {
-        constexpr int last = j + PF - 2 < B - 1 ? j + PF - 2 : B - 1;
-        constexpr int after = last - (j + 1 < B ? j + 1 : j);
-        lgkm_wait<(after > 0 ? after : 0)>();
-      }
-    };
     s1(0);
     static_for<0, B>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       if constexpr (i + 1 < B) {
-        pair_wait(std::integral_constant<int, i + 1>{});
+        group_wait<4, PF, B, i + 1>();
         s1(i + 1);
       } else {
         asm volatile("s_nop 1");
