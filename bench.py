@@ -51,6 +51,10 @@ def c3_alg_bytes_per_update():
     return 0.25 + 0.375 / (C3_R * C3_K)
 
 
+# threads per workgroup of the rocprofv3 runs behind profiles/ising_sweep_c3_*
+PROFILED_BLOCK = 512
+
+
 def kernel_source_hash():
     with open(os.path.join(ROOT, "paper_0704_3573_amd", "csrc", "sg_kernels.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -424,6 +428,11 @@ def main():
     elif not args.no_tune:
         from paper_0704_3573_amd import autotune
         tpb, tune_times = autotune.tune(batch, C3_PT, periods=2, stream=stream, use_cache=False)
+        # keep the block the committed counter summary was taken on unless
+        # another one is clearly faster (within 1 % they tie in timing noise)
+        if tpb != PROFILED_BLOCK and tune_times.get(PROFILED_BLOCK, float("inf")) <= 1.01 * tune_times[tpb]:
+            tpb = PROFILED_BLOCK
+            batch.set_block(tpb)
         log(f"[bench] autotuned block: {tpb} threads "
             f"({', '.join(f'{k}:{v:.3f}ms' for k, v in sorted(tune_times.items()))})")
     tpb = batch.block()
