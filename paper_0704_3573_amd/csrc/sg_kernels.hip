@@ -67,31 +67,12 @@ DEV void stage_words(int n, Load load, Put put) {
   }
 }
 
+// Compile-time geometry of the Potts kernels (row-aligned blocks of draws).
 template <int L>
 struct GC {
   static constexpr Geom g = geom(L);
   static constexpr int RHO = g.RHO, NG = g.NG, NW = g.NW, H = g.H, RPB = g.RPB, B = g.B,
                        NBLK = g.NBLK, NWB = g.NWB, WZ = g.WZ, CS = g.CS, M = g.M, V = g.V;
-  static constexpr uint32_t MB = B == 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
-  static constexpr uint32_t seg_bits(int r) {
-    return (H == 32 ? 0xFFFFFFFFu : ((1u << H) - 1u)) << (B - (r + 1) * H);
-  }
-  static constexpr uint32_t lowb() {
-    uint32_t m = 0;
-    for (int r = 0; r < RPB; r++) m |= 1u << (B - (r + 1) * H);
-    return m;
-  }
-  static constexpr uint32_t topb() {
-    uint32_t m = 0;
-    for (int r = 0; r < RPB; r++) m |= 1u << (B - 1 - r * H);
-    return m;
-  }
-  static constexpr uint32_t segs(int parity) {
-    uint32_t m = 0;
-    for (int r = parity; r < RPB; r += 2) m |= seg_bits(r);
-    return m;
-  }
-  static constexpr uint32_t LOWB = lowb(), TOPB = topb(), EVENSEG = segs(0), ODDSEG = segs(1);
 };
 
 // Compile-time geometry of the bit-packed Ising copies (plane strings cut
@@ -530,8 +511,9 @@ DEV void drive(K &k, Drive &d) {
 // Metropolis with a per-copy threshold table (the LUT of the paper's update
 // cell).  The number n of unsatisfied bonds of every site of the block is
 // counted bit-sliced before the draws; each draw is compared with T[n mod 4]
-// read from the copy's 4-word LDS table at byte offset 4 (n mod 4) (the two
-// low count planes transposed into bytes, one byte-select add per site), and
+// read from the copy's LDS table (entry v at words v, 4 v and 16 v, addressed
+// by the two low count planes interleaved into bytes, one byte-select add
+// per site), and
 // the flips that are certain in advance (n >= 3, dE <= 0; or n >= m when the
 // thresholds from m on equal 2^32, beta ~ 0) are one bit-sliced compare per
 // block.  Per draw: add, xor, compare, insert and the address add.  The
@@ -541,7 +523,7 @@ struct IsingMetK {
   using G = IC<L>;
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK;
   IsingLane ln;
-  const uint32_t *tab;  // LDS table of the lane's copy: T[0], T[1], T[2], 0
+  const uint32_t *tab;  // LDS table of the lane's copy: T[v] at words v, 4 v, 16 v (T[3] = 0)
   uint32_t mlo, mhi;    // limit m in 0..3 of the certain flips, bits as lane masks
   uint32_t nextJ[6];    // coupling words of the next block
 
