@@ -1181,9 +1181,11 @@ struct PottsK {
       const uint32_t r = ring[k % M] ^ ring[(k + M - 61) % M];
       const uint32_t C1 = w[kb][0] + w[kb][1], C2 = C1 + w[kb][2];
       const uint32_t t = __umulhi(r, C2 + w[kb][3]);
-      uint32_t v = t >= w[kb][0] ? 8u : 0u;
-      v = t >= C1 ? 16u : v;
-      v = t >= C2 ? 24u : v;
+      // state = #{cumulative weights <= t}: weights are at most 2^28, so t
+      // and the sums stay below 2^31 and [C <= t] is bit 31 of C + ~t (no
+      // compare masks, whose reads by a select would cost wait states)
+      const uint32_t nt = ~t;
+      const uint32_t v = (((w[kb][0] + nt) >> 31) + ((C1 + nt) >> 31) + ((C2 + nt) >> 31)) << 3;
       wr[base[rr] + 2 * j * L] = (uint8_t)v;
     };
 
@@ -1468,6 +1470,8 @@ struct Potts4K {
       const uint32_t r = ring[k % M] ^ ring[(k + M - 61) % M];
       const uint32_t C1 = w[kb][0] + w[kb][1], C2 = C1 + w[kb][2];
       const uint32_t t = __umulhi(r, C2 + w[kb][3]);
+      // compare-and-select form: the 3D kernel's mask-free count measured
+      // slightly slower here
       uint32_t v = t >= w[kb][0] ? 8u : 0u;
       v = t >= C1 ? 16u : v;
       v = t >= C2 ? 24u : v;
