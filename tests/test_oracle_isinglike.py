@@ -16,6 +16,14 @@ antiferromagnet in a field, and the general mix).
 * L = 2 exact enumeration: the one-sweep transition matrix built from the
   oracle's own site update leaves exp(-beta (E_b - |h| M)) invariant, with
   dilution and a non-integer field.
+* Dilution, pinned against the Hamiltonian of Eq. (2) summed directly in
+  numpy (not through the oracle): E_b and M on diluted instances, the change
+  of both under every single-site move, the per-site move probabilities
+  against min(1, e^{-beta dH}) and the conditional Boltzmann law, and the
+  invisibility of empty sites (changing their stored spins changes nothing
+  else).  An oracle built with empty sites still coupling through their
+  frozen spins (x dropped from the local field and from E_b, a
+  self-consistent misreading) fails each of these.
 """
 import itertools
 
@@ -177,3 +185,156 @@ def test_l2_sweep_leaves_boltzmann_invariant(kind, algo):
     assert np.allclose(P.sum(1), 1.0)
     assert np.max(np.abs(pi @ P - pi)) < 1e-8
     assert np.max(np.abs(P - np.eye(len(states)))) > 0.05
+
+
+# ---------------------------------------------------------------------------
+# Dilution of Eq. (2), pinned independently of the oracle: the energy is
+# summed here in numpy straight from the Hamiltonian, every site change is
+# checked against it, and empty sites are shown to be invisible to the rest
+# of the lattice.  A reading in which empty sites keep coupling through their
+# frozen spins (x dropped from the local field and from E_b alike) is
+# self-consistent and passes the pins above; it fails these.
+# ---------------------------------------------------------------------------
+
+def brute_terms(L, s, D):
+    """(E_b, M) of Eq. (2) by direct summation: E_b = -sum over the 3N bonds
+    <i, i + e_d> of J x_i x_j s_i s_j, M = sum_i x_i f_i s_i."""
+    shape = (L, L, L)  # [z][y][x] for i = x + L (y + L z)
+    s = np.asarray(s, np.int64).reshape(shape)
+    x = np.asarray(D[3], np.int64).reshape(shape)
+    f = np.asarray(D[4], np.int64).reshape(shape)
+    E = 0
+    for d, axis in ((0, 2), (1, 1), (2, 0)):
+        J = np.asarray(D[d], np.int64).reshape(shape)
+        E -= int((J * x * np.roll(x, -1, axis) * s * np.roll(s, -1, axis)).sum())
+    return E, int((x * f * s).sum())
+
+
+def diluted_instance(L, seed, occupancy=0.6):
+    """Couplings, dilution and field signs all random (the general model)."""
+    rng = np.random.default_rng(seed)
+    N = L ** 3
+    D = np.empty((5, N), np.int8)
+    D[:3] = rng.choice(np.array([-1, 1], np.int8), size=(3, N))
+    D[3] = (rng.random(N) < occupancy).astype(np.int8)
+    D[4] = rng.choice(np.array([-1, 1], np.int8), size=N)
+    s = rng.choice(np.array([-1, 1], np.int8), size=N)
+    return D, s
+
+
+@pytest.mark.parametrize("L", [2, 4, 8])
+def test_terms_equal_the_hamiltonian_summed_directly(L):
+    for seed in range(4):
+        D, s = diluted_instance(L, 100 + seed)
+        assert oracle.isinggen_terms(L, s, D) == brute_terms(L, s, D)
+    for kind in KINDS:
+        inst = inputs.make_instance(kind, L, 1, 1, 1, seed=77)
+        assert oracle.isinggen_terms(L, inst["spins"][0], inst["J"][0]) == \
+            brute_terms(L, inst["spins"][0], inst["J"][0])
+
+
+@pytest.mark.parametrize("L", [2, 4])
+def test_every_site_move_changes_the_hamiltonian_as_summed_directly(L):
+    """Metropolis at small beta with r = 0 moves every occupied site; the
+    returned changes of E_b and M must be the differences of the directly
+    summed terms, and empty sites must not move."""
+    D, s = diluted_instance(L, 5)
+    for i in range(L ** 3):
+        u = s.copy()
+        dE, dM = oracle.isinggen_update_site(L, oracle.METROPOLIS, u, D, 0.8, 0.01, i, 0)
+        if D[3, i] == 0:
+            assert np.array_equal(u, s) and (dE, dM) == (0, 0)
+            continue
+        assert u[i] == -s[i] and np.array_equal(np.delete(u, i), np.delete(s, i))
+        e0, m0 = brute_terms(L, s, D)
+        e1, m1 = brute_terms(L, u, D)
+        assert (dE, dM) == (e1 - e0, m1 - m0), i
+        s = u
+
+
+@pytest.mark.parametrize("algo", [oracle.METROPOLIS, oracle.HEATBATH])
+def test_site_probabilities_follow_the_directly_summed_hamiltonian(algo):
+    """Share of r in [0, 2^32) that moves an occupied site (Metropolis: flips
+    it; heat bath: sets it to +1) against min(1, exp(-beta dH)) and the
+    conditional Boltzmann law, with H = E_b - |h| M summed directly."""
+    L, beta, field = 4, 0.45, 0.65
+    D, s = diluted_instance(L, 9)
+    for i in range(0, L ** 3, 3):
+        if D[3, i] == 0:
+            continue
+        lo, hi = 0, TWO32
+        while lo < hi:
+            mid = (lo + hi) // 2
+            u = s.copy()
+            oracle.isinggen_update_site(L, algo, u, D, field, beta, i, mid)
+            hit = (u[i] != s[i]) if algo == oracle.METROPOLIS else (u[i] == 1)
+            lo, hi = (mid + 1, hi) if hit else (lo, mid)
+        up, dn = s.copy(), s.copy()
+        up[i], dn[i] = 1, -1
+        Hu = (lambda e, m: e - field * m)(*brute_terms(L, up, D))
+        Hd = (lambda e, m: e - field * m)(*brute_terms(L, dn, D))
+        if algo == oracle.METROPOLIS:
+            dH = (Hd - Hu) if s[i] == 1 else (Hu - Hd)
+            want = min(1.0, np.exp(-beta * dH))
+        else:
+            want = 1.0 / (1.0 + np.exp(-beta * (Hd - Hu)))
+        assert abs(lo / TWO32 - want) <= 2.0 ** -31, (i, lo / TWO32, want)
+
+
+@pytest.mark.parametrize("algo", [oracle.METROPOLIS, oracle.HEATBATH])
+@pytest.mark.parametrize("kind", ["daff", "isinggen"])
+def test_empty_sites_are_invisible_to_the_occupied_sites(kind, algo):
+    """Changing the stored spin of every empty site changes nothing else: the
+    occupied sites follow the same trajectory and E_b, M are unchanged."""
+    L = 8
+    inst = inputs.make_instance(kind, L, 1, 1, 1, seed=80)
+    D = inst["J"][0]
+    empty = D[3] == 0
+    assert empty.any()
+    other = inst["spins"].copy()
+    other[0, empty] = -other[0, empty]
+    kw = dict(n_sweeps=9, field=0.8)
+    a = oracle.run(oracle.ISING_GEN, algo, L, [0.7], inst["J"], inst["spins"], inst["wheels"], **kw)
+    b = oracle.run(oracle.ISING_GEN, algo, L, [0.7], inst["J"], other, inst["wheels"], **kw)
+    assert np.array_equal(a["spins"][0, ~empty], b["spins"][0, ~empty])
+    assert np.array_equal(b["spins"][0, empty], other[0, empty])
+    assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["M"], b["M"])
+    assert np.array_equal(a["wheels"], b["wheels"])
+
+
+# The mutant: empty sites couple through their frozen spins (x dropped from
+# the local field and from the bond energy).  It is built from the oracle's
+# own source by two textual substitutions, so it changes exactly that.
+MUTANT_EDITS = (
+    ("b += D[bond[d]] * x[nb[d]] * s[nb[d]];", "b += D[bond[d]] * s[nb[d]];"),
+    ("E -= (int64_t)D[bond[d]] * x[i] * x[nb[d]] * s[i] * s[nb[d]];",
+     "E -= (int64_t)D[bond[d]] * s[i] * s[nb[d]];"),
+)
+
+
+def test_the_pins_reject_empty_sites_that_still_couple(tmp_path, monkeypatch):
+    import subprocess
+    src = open(oracle.SRC).read()
+    for old, new in MUTANT_EDITS:
+        assert src.count(old) == 1, old
+        src = src.replace(old, new)
+    path = tmp_path / "sg_oracle_mutant.c"
+    path.write_text(src)
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                           f"-I{oracle.HERE}", "-o", str(so), str(path), "-lm"])
+    monkeypatch.setattr(oracle, "_lib", None)
+    monkeypatch.setattr(oracle, "LIB", str(so))
+    # the mutant is self-consistent: tracked terms equal its own recomputation
+    inst = inputs.make_instance("daff", 8, 1, 1, 1, seed=60)
+    out = oracle.run(oracle.ISING_GEN, oracle.METROPOLIS, 8, [0.7], inst["J"], inst["spins"],
+                     inst["wheels"], n_sweeps=5, field=0.9, check_energy=True)
+    assert (out["E"][0], out["M"][0]) == oracle.isinggen_terms(8, out["spins"][0], inst["J"][0])
+    # ... and each of the dilution pins fails on it
+    checks = [lambda: test_terms_equal_the_hamiltonian_summed_directly(4),
+              lambda: test_every_site_move_changes_the_hamiltonian_as_summed_directly(4),
+              lambda: test_site_probabilities_follow_the_directly_summed_hamiltonian(oracle.HEATBATH),
+              lambda: test_empty_sites_are_invisible_to_the_occupied_sites("daff", oracle.METROPOLIS)]
+    for check in checks:
+        with pytest.raises(AssertionError):
+            check()
