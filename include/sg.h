@@ -93,18 +93,25 @@ typedef struct sg_job_spec {
   int32_t n_temps;    /* K >= 1                                                 */
   int32_t pt_every;   /* sweeps between parallel-tempering steps, 0 = none      */
   double field;       /* SG_ISING_GEN: |h| >= 0, finite; ignored otherwise       */
+  uint64_t seed;      /* instance seed: inputs passed as NULL to sg_job_create
+                         are generated from it (sg_generate)                    */
+  uint64_t sample0;   /* global number of the job's first sample (a campaign
+                         split over several jobs keeps every sample's inputs)   */
 } sg_job_spec;
 
 /* Message of the last error on this thread ("" if none). */
 const char *sg_last_error(void);
 
-/* Number of sweep wheels per copy for side L (0 if L is not supported). */
+/* Number of sweep wheels per copy for side L (0 if L is not supported): one
+ * wheel per plane z and group of min(8, L) rows (a reading of sec. 3.3,
+ * which lets one wheel feed many update cells without fixing the mapping). */
 int32_t sg_wheels_per_copy(int32_t L);
 /* The same for a model: SG_GPOTTS4 has one wheel per (z, u, row group),
  * L^3 / min(8, L); every other model as sg_wheels_per_copy(L). */
 int32_t sg_model_wheels_per_copy(int32_t model, int32_t L);
 
-/* Bind a context to HIP device `device`. */
+/* Bind a context to HIP device `device` (the kernels are built for gfx950;
+ * SG_E_UNSUPPORTED on any other device). */
 int sg_ctx_create(int device, sg_ctx **out);
 int sg_ctx_destroy(sg_ctx *ctx);
 
@@ -112,8 +119,42 @@ int sg_ctx_destroy(sg_ctx *ctx);
 int sg_job_bytes(const sg_job_spec *spec, uint64_t *bytes);
 
 /*
+ * Host only (no device needed): the seeded instance of a specification, in
+ * the canonical formats above.  Sec. 2.1 draws the couplings at random
+ * (+-1 with p = 1/2; iid permutations for Eq. 3; for SG_ISING_GEN the
+ * general mix of Eq. 2: J, x and f iid) and sec. 3.3 loads the wheels with
+ * externally generated random values; here every array is a SplitMix64
+ * counter stream keyed by (spec->seed, array, global sample/copy/chain
+ * number from spec->sample0, wheel).  Any output pointer may be NULL (not
+ * generated).  Sizes: J [S][3][N] (SG_ISING_GEN [S][5][N], SG_GPOTTS4
+ * [S][4][N]), spins [C][N], wheels [C][NW][61], ptwheels [S*R][61].
+ */
+int sg_generate(const sg_job_spec *spec, int8_t *J, void *spins, uint32_t *wheels,
+                uint32_t *ptwheels);
+
+/*
+ * Host only: the integer threshold row the library uploads for one
+ * temperature (32 words).  Metropolis (sec. 2.2): words n = 0..2 hold
+ * floor(2^32 exp(-beta (12 - 4n))) for n unsatisfied bonds; heat bath
+ * (Eq. 4): words k = 0..6 hold floor(2^32 / (1 + exp(-2 beta (2k - 6))));
+ * Potts models: words d = 0..12 hold floor(2^28 exp(-beta d)).  A threshold
+ * equal to 2^32 ("always") is stored as 0xFFFFFFFF with bit n of word 15 set
+ * (Ising).  SG_ISING_GEN (Eq. 2): word k + 16 phi holds the threshold of
+ * class (k, phi) and words 13, 29 the limits of the classes whose move is
+ * certain (their words are 0).  SG_E_INVALID for a bad model, algorithm,
+ * beta or field; SG_E_UNSUPPORTED if the Eq. 2 thresholds are not monotone.
+ */
+int sg_threshold_row(int32_t model, int32_t algo, double beta, double field, uint32_t row[32]);
+
+/* Host only: parallel-tempering factors of the temperature pair
+ * (beta_i, beta_next), F[b] = floor(2^32 exp(-|beta_i - beta_next| 2^b)),
+ * b = 0..23, and the sign of beta_i - beta_next (sec. 2.2 names parallel
+ * tempering; the integer swap test is the library's reading). */
+int sg_pt_factors(double beta_i, double beta_next, uint64_t F[24], int32_t *sign);
+
+/*
  * Create a job in the caller's device arena and upload its state (blocks
- * until the upload has finished).
+ * until the upload, which is ordered on `stream`, has finished).
  *   betas         [K] inverse temperatures >= 0, by temperature index;
  *   J             [S][3][N] int8, J[d][i] couples i and i + e_d: +-1 (Ising,
  *                 +-J Potts); for SG_GPOTTS the bytes are read as uint8
@@ -124,8 +165,9 @@ int sg_job_bytes(const sg_job_spec *spec, uint64_t *bytes);
  *                 [S][4][L^4] permutation bytes as for SG_GPOTTS;
  *   spins         [C][N] int8 +-1 (Ising models) or uint8 0..3 (Potts models);
  *                 an empty site keeps its spin (and still consumes its number);
- *   wheels        [C][NW][61];      ptwheels [S*R][61] (may be NULL if
- *                 pt_every == 0);
+ *   wheels        [C][NW][61];      ptwheels [S*R][61];
+ *   J, spins, wheels, ptwheels: NULL = generated from spec->seed as by
+ *                 sg_generate (a job is then created from its seed alone);
  *   slot_of_temp  [S*R][K] or NULL (identity);
  *   sweeps_done   sweeps already performed by this state (0 for a new job;
  *                 used to resume from exported state).
@@ -137,20 +179,31 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
                   const int32_t *slot_of_temp, uint64_t sweeps_done, void *d_arena,
                   uint64_t arena_bytes, void *stream, sg_job **out);
 
-/* Replace the K inverse temperatures (rebuilds the integer tables). (sync) */
+/* Replace the K inverse temperatures: rebuilds the integer threshold tables
+ * of sec. 2.2 / Eq. 4 on the host and uploads them. (sync) */
 int sg_job_set_betas(sg_job *job, const double *betas, void *stream);
 
-/* Run n sweeps of every copy, with parallel-tempering steps after every
- * multiple of pt_every sweeps (counted since the start of the job). */
+/* Run n sweeps of every copy: checkerboard half-sweeps (sec. 3.1), each site
+ * update drawing one Parisi-Rapuano number (sec. 3.3, Eq. 5) and accepting
+ * by the integer rule of sec. 2.2 / Eq. 4; parallel-tempering steps (sec.
+ * 2.2) after every multiple of pt_every sweeps, counted since the start of
+ * the job.  Asynchronous. */
 int sg_job_sweep(sg_job *job, uint64_t n_sweeps, void *stream);
 
-/* Energy of every copy by chain and temperature index, E[(s*R + r)*K + k]
- * (may be NULL), and overlap of replicas 0 and 1 at every temperature,
- * Q[s*K + k] (may be NULL; needs R >= 2): Ising sum_i s^a_i s^b_i, Potts number
- * of equal sites. (sync) */
+/* sweep(beta, n): set the single inverse temperature of a K = 1 job to beta
+ * (tables rebuilt only if it changed) and run n sweeps as sg_job_sweep.
+ * SG_E_INVALID if the job has K > 1. */
+int sg_job_sweep_beta(sg_job *job, double beta, uint64_t n_sweeps, void *stream);
+
+/* Measurement (sec. 4.1 measures energies and the overlap q between replicas
+ * at the same temperature): energy of every copy by chain and temperature
+ * index, E[(s*R + r)*K + k] (may be NULL), and overlap of replicas 0 and 1
+ * at every temperature, Q[s*K + k] (may be NULL; needs R >= 2): Ising
+ * sum_i s^a_i s^b_i, Potts number of equal sites. (sync) */
 int sg_job_measure(sg_job *job, int64_t *E, int64_t *Q, void *stream);
 
-/* Energy of every slot (copy order), as left by the last sweep or measure. (sync) */
+/* Energy of every slot (copy order), as left by the last sweep or measure
+ * (sec. 4.1). (sync) */
 int sg_job_energies(sg_job *job, int64_t *E_slot, void *stream);
 
 /* SG_ISING_GEN (Eq. 2): field sum M = sum_i x_i f_i s_i of every copy by
@@ -158,18 +211,36 @@ int sg_job_energies(sg_job *job, int64_t *E_slot, void *stream);
  * current spins; SG_E_STATE for other models. (sync) */
 int sg_job_field_sums(sg_job *job, int64_t *M, void *stream);
 
-/* Canonical export of the state. (sync) */
+/* Canonical export of the state (sec. 4.1 copies configurations to the host
+ * periodically). (sync) */
 int sg_job_get_spins(sg_job *job, void *spins_out /* [C][N] */, void *stream);
 int sg_job_get_wheels(sg_job *job, uint32_t *wheels_out /* [C][NW][61] */,
                       uint32_t *ptwheels_out /* [S*R][61] or NULL */, void *stream);
 int sg_job_get_perm(sg_job *job, int32_t *slot_of_temp_out /* [S*R][K] */, void *stream);
-/* Accepted parallel-tempering swaps per (chain, pair), [S*R][K-1]. (sync) */
+/* Accepted parallel-tempering swaps per (chain, pair), [S*R][K-1] (sec. 2.2).
+ * (sync) */
 int sg_job_get_pt_accepts(sg_job *job, uint64_t *out, void *stream);
 /* Sweeps performed so far. */
 int sg_job_sweeps_done(const sg_job *job, uint64_t *out);
 
-/* Test hook: the next n (<= 4096) numbers of sweep wheel `wheel` of copy
- * `copy`, computed on the device; the job's state is not advanced. (sync) */
+/*
+ * Checkpoint and restore (sec. 4.1: configurations go to the host
+ * periodically; a long run resumes from them).  The checkpoint is an opaque
+ * host blob of sg_job_checkpoint_bytes() bytes holding the specification,
+ * the inverse temperatures, the sweep counter, every spin, sweep wheel and
+ * parallel-tempering wheel, the temperature permutation, the swap counters,
+ * the energies and a 64-bit digest of the couplings.  sg_job_restore loads
+ * it into a job of the same specification and couplings (SG_E_STATE
+ * otherwise; SG_E_INVALID for a blob that is not a checkpoint); the job then
+ * continues bit for bit as the checkpointed one would. (sync)
+ */
+int sg_job_checkpoint_bytes(const sg_job *job, uint64_t *bytes);
+int sg_job_checkpoint(sg_job *job, void *host_buf, uint64_t bytes, void *stream);
+int sg_job_restore(sg_job *job, const void *host_buf, uint64_t bytes, void *stream);
+
+/* Test hook: the next n (<= 4096) numbers (Eq. 5, sec. 3.3) of sweep wheel
+ * `wheel` of copy `copy`, computed on the device; the job's state is not
+ * advanced. (sync) */
 int sg_job_debug_rng(sg_job *job, int32_t copy, int32_t wheel, uint32_t n, uint32_t *out,
                      void *stream);
 
@@ -177,11 +248,16 @@ int sg_job_destroy(sg_job *job);
 
 /*
  * Batches: many jobs (mixed L, models, temperatures) advanced together by one
- * fused sweep launch per period, replayed from a captured hipGraph.  Jobs can
- * be added and removed between runs (continuous batching); a job's results do
- * not depend on the batch it runs in.
+ * fused sweep launch per period, replayed from a captured hipGraph.  The
+ * paper fills its update cells with two replicas per FPGA and runs many
+ * samples on many FPGAs (sec. 3.2, sec. 4.2); here samples, replicas and
+ * temperatures of many jobs share one launch.  Jobs can be added and removed
+ * between runs (continuous batching); a job's results do not depend on the
+ * batch it runs in.  A removed job's arena must stay valid until the periods
+ * already enqueued on the caller's stream have finished.
  */
-int sg_batch_create(sg_ctx *ctx, sg_batch **out);
+/* Create a batch holding the n jobs of `jobs` (n may be 0, jobs NULL). */
+int sg_batch_create(sg_ctx *ctx, sg_job *const *jobs, int32_t n, sg_batch **out);
 int sg_batch_add(sg_batch *b, sg_job *job);
 int sg_batch_remove(sg_batch *b, sg_job *job);
 /* Threads per workgroup of the fused launch (multiple of 64, <= 1024;
@@ -194,7 +270,9 @@ int sg_batch_set_block(sg_batch *b, int32_t threads);
  * This lets jobs of different lengths share one launch and stop exactly. */
 int sg_batch_set_budget(sg_batch *b, sg_job *job, uint64_t sweeps);
 int sg_batch_get_budget(sg_batch *b, sg_job *job, uint64_t *sweeps);
-/* Advance every job of the batch by n sweeps (parallel tempering included). */
+/* Advance every job of the batch by n sweeps (sec. 3.1 / 3.3 / 2.2 as
+ * sg_job_sweep, parallel tempering included).  After membership changes the
+ * call first waits for the work already enqueued on `stream`. */
 int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream);
 /* Threads per workgroup chosen for the current membership. */
 int sg_batch_block(sg_batch *b, int32_t *threads);

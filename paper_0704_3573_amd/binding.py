@@ -30,7 +30,8 @@ EXPORTS = (
     "sg_job_sweeps_done", "sg_job_debug_rng", "sg_job_destroy", "sg_batch_create",
     "sg_batch_add", "sg_batch_remove", "sg_batch_set_block", "sg_batch_run", "sg_batch_block",
     "sg_batch_set_timing", "sg_batch_sweep_ms", "sg_batch_set_budget", "sg_batch_get_budget",
-    "sg_batch_destroy",
+    "sg_batch_destroy", "sg_generate", "sg_threshold_row", "sg_pt_factors", "sg_job_sweep_beta",
+    "sg_job_checkpoint_bytes", "sg_job_checkpoint", "sg_job_restore",
 )
 
 
@@ -43,7 +44,7 @@ class SgError(RuntimeError):
 class Spec(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "model", "algo", "q", "L", "n_samples", "n_replicas", "n_temps", "pt_every")] + [
-        ("field", C.c_double)]
+        ("field", C.c_double), ("seed", C.c_uint64), ("sample0", C.c_uint64)]
 
 
 _lib = None
@@ -79,7 +80,14 @@ def lib():
         L.sg_job_sweeps_done.argtypes = [vp, C.POINTER(u64)]
         L.sg_job_debug_rng.argtypes = [vp, i32, i32, C.c_uint32, vp, vp]
         L.sg_job_destroy.argtypes = [vp]
-        L.sg_batch_create.argtypes = [vp, C.POINTER(vp)]
+        L.sg_batch_create.argtypes = [vp, vp, i32, C.POINTER(vp)]
+        L.sg_generate.argtypes = [C.POINTER(Spec), vp, vp, vp, vp]
+        L.sg_threshold_row.argtypes = [i32, i32, C.c_double, C.c_double, vp]
+        L.sg_pt_factors.argtypes = [C.c_double, C.c_double, vp, C.POINTER(i32)]
+        L.sg_job_sweep_beta.argtypes = [vp, C.c_double, u64, vp]
+        L.sg_job_checkpoint_bytes.argtypes = [vp, C.POINTER(u64)]
+        L.sg_job_checkpoint.argtypes = [vp, vp, u64, vp]
+        L.sg_job_restore.argtypes = [vp, vp, u64, vp]
         L.sg_batch_add.argtypes = [vp, vp]
         L.sg_batch_remove.argtypes = [vp, vp]
         L.sg_batch_set_block.argtypes = [vp, i32]
@@ -116,6 +124,41 @@ def wheels_per_copy(L: int, model: int = ISING) -> int:
     return int(lib().sg_model_wheels_per_copy(model, L))
 
 
+def _rows(model) -> int:
+    return {ISING_GEN: 5, GPOTTS4: 4}.get(model, 3)
+
+
+def generate(spec: Spec):
+    """The seeded instance of a specification, generated by the library
+    (host only): dict with J, spins, wheels, ptwheels in canonical formats."""
+    S, R, K = spec.n_samples, spec.n_replicas, spec.n_temps
+    N = spec.L ** (4 if spec.model == GPOTTS4 else 3)
+    NW = wheels_per_copy(spec.L, spec.model)
+    ising = spec.model in (ISING, ISING_GEN)
+    J = np.zeros((S, _rows(spec.model), N), np.uint8 if spec.model in (GPOTTS, GPOTTS4) else np.int8)
+    spins = np.zeros((S * R * K, N), np.int8 if ising else np.uint8)
+    wheels = np.zeros((S * R * K, NW, 61), np.uint32)
+    ptwheels = np.zeros((S * R, 61), np.uint32)
+    _chk(lib().sg_generate(C.byref(spec), _ptr(J), _ptr(spins), _ptr(wheels), _ptr(ptwheels)))
+    return {"J": J, "spins": spins, "wheels": wheels, "ptwheels": ptwheels}
+
+
+def threshold_row(model, algo, beta: float, field: float = 0.0) -> np.ndarray:
+    """The 32-word integer threshold row the library uploads for one
+    temperature (host only)."""
+    row = np.zeros(32, np.uint32)
+    _chk(lib().sg_threshold_row(model, algo, float(beta), float(field), _ptr(row)))
+    return row
+
+
+def pt_factors(beta_i: float, beta_next: float):
+    """(F[24], sign) of the parallel-tempering pair (host only)."""
+    F = np.zeros(24, np.uint64)
+    sgn = C.c_int32()
+    _chk(lib().sg_pt_factors(float(beta_i), float(beta_next), _ptr(F), C.byref(sgn)))
+    return F, sgn.value
+
+
 def job_bytes(spec: Spec) -> int:
     n = C.c_uint64()
     _chk(lib().sg_job_bytes(C.byref(spec), C.byref(n)))
@@ -148,13 +191,16 @@ class Job:
     object.  Arrays follow the canonical formats of include/sg.h.
     """
 
-    def __init__(self, ctx: Context, model, algo, L, betas, J, spins, wheels, ptwheels=None,
-                 *, n_samples=1, n_replicas=1, pt_every=0, slot_of_temp=None, sweeps_done=0,
-                 stream=None, arena=None, field=0.0):
+    def __init__(self, ctx: Context, model, algo, L, betas, J=None, spins=None, wheels=None,
+                 ptwheels=None, *, n_samples=1, n_replicas=1, pt_every=0, slot_of_temp=None,
+                 sweeps_done=0, stream=None, arena=None, field=0.0, seed=0, sample0=0):
+        """J, spins, wheels, ptwheels: canonical arrays, or None to have the
+        library generate them from (seed, sample0)."""
         import torch
         betas = np.ascontiguousarray(betas, dtype=np.float64)
         K = betas.shape[0]
-        self.spec = Spec(model, algo, 4, L, n_samples, n_replicas, K, pt_every, float(field))
+        self.spec = Spec(model, algo, 4, L, n_samples, n_replicas, K, pt_every, float(field),
+                         int(seed), int(sample0))
         self.model, self.algo, self.L = model, algo, L
         self.S, self.R, self.K = n_samples, n_replicas, K
         self.C = n_samples * n_replicas * K
@@ -167,12 +213,15 @@ class Job:
         # +-1 couplings as int8; glassy-Potts permutation bytes as uint8 (same
         # width); Ising-like models: rows J_x, J_y, J_z, x, f
         self.ising_spins = model in (ISING, ISING_GEN)
-        J = np.ascontiguousarray(J, dtype=np.uint8 if model in (GPOTTS, GPOTTS4) else np.int8)
-        spins = np.ascontiguousarray(spins, dtype=np.int8 if self.ising_spins else np.uint8)
-        wheels = np.ascontiguousarray(wheels, dtype=np.uint32)
-        rows = {ISING_GEN: 5, GPOTTS4: 4}.get(model, 3)
-        assert J.size == self.S * rows * self.N and spins.size == self.C * self.N
-        assert wheels.size == self.C * self.NW * 61
+        if J is not None:
+            J = np.ascontiguousarray(J, dtype=np.uint8 if model in (GPOTTS, GPOTTS4) else np.int8)
+            assert J.size == self.S * _rows(model) * self.N
+        if spins is not None:
+            spins = np.ascontiguousarray(spins, dtype=np.int8 if self.ising_spins else np.uint8)
+            assert spins.size == self.C * self.N
+        if wheels is not None:
+            wheels = np.ascontiguousarray(wheels, dtype=np.uint32)
+            assert wheels.size == self.C * self.NW * 61
         pw = None if ptwheels is None else np.ascontiguousarray(ptwheels, dtype=np.uint32)
         if pw is not None:
             assert pw.size == self.S * self.R * 61
@@ -202,6 +251,20 @@ class Job:
 
     def sweep(self, n: int, stream=None):
         _chk(lib().sg_job_sweep(self.h, n, _stream(stream)))
+
+    def sweep_beta(self, beta: float, n: int, stream=None):
+        _chk(lib().sg_job_sweep_beta(self.h, float(beta), n, _stream(stream)))
+
+    def checkpoint(self, stream=None) -> bytes:
+        n = C.c_uint64()
+        _chk(lib().sg_job_checkpoint_bytes(self.h, C.byref(n)))
+        buf = np.zeros(n.value, np.uint8)
+        _chk(lib().sg_job_checkpoint(self.h, _ptr(buf), n.value, _stream(stream)))
+        return buf.tobytes()
+
+    def restore(self, blob: bytes, stream=None):
+        buf = np.frombuffer(blob, np.uint8).copy()
+        _chk(lib().sg_job_restore(self.h, _ptr(buf), buf.size, _stream(stream)))
 
     def measure(self, stream=None, overlap=True):
         E = np.zeros(self.C, dtype=np.int64)
@@ -255,14 +318,14 @@ class Batch:
     """Jobs advanced together by one fused launch per period (hipGraph replay)."""
 
     def __init__(self, ctx: Context, jobs=(), block: int = 0):
+        jobs = list(jobs)
+        hs = (C.c_void_p * max(1, len(jobs)))(*[j.h for j in jobs])
         h = C.c_void_p()
-        _chk(lib().sg_batch_create(ctx.h, C.byref(h)))
+        _chk(lib().sg_batch_create(ctx.h, hs if jobs else None, len(jobs), C.byref(h)))
         self.h = h
-        self.jobs = []
+        self.jobs = jobs
         if block:
             self.set_block(block)
-        for j in jobs:
-            self.add(j)
 
     def add(self, job: Job):
         _chk(lib().sg_batch_add(self.h, job.h))

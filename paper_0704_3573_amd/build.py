@@ -20,7 +20,7 @@ DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-pa
 def build(verbose: bool = False) -> str:
     objs = []
     jobs = []
-    for src, dev in (("sg_kernels.hip", True), ("sg_host.cpp", False)):
+    for src, dev in (("sg_kernels.hip", True), ("sg_host.cpp", False), ("sg_seed.cpp", False)):
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
         if dev:
             cmd = [HIPCC] + COMMON + DEVICE + ["-x", "hip"]

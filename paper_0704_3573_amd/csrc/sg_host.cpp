@@ -613,6 +613,14 @@ static void unpack_wheels(const sg_job *j, const uint32_t *in, uint64_t k0, uint
     }
 }
 
+// Parallel-tempering factors of the pair (beta_i, beta_next):
+// F[b] = floor(2^32 exp(-|dbeta| 2^b)), b < 24, and the sign of dbeta.
+static void pt_factors(double bi, double bn, uint64_t F[24], int32_t *sgn) {
+  const double db = bi - bn;
+  *sgn = db > 0 ? 1 : (db < 0 ? -1 : 0);
+  for (int b = 0; b < 24; b++) F[b] = scaled_floor(std::exp(-std::fabs(db) * std::ldexp(1.0, b)), 32);
+}
+
 static int tables_upload_host(const sg_job *j, std::vector<uint32_t> &thr, std::vector<uint64_t> &F,
                               std::vector<int32_t> &sgn) {
   const int K = j->K, K1 = K > 1 ? K - 1 : 1;
@@ -628,12 +636,7 @@ static int tables_upload_host(const sg_job *j, std::vector<uint32_t> &thr, std::
   }
   F.assign((size_t)K1 * 24, 0);
   sgn.assign((size_t)K1, 0);
-  for (int i = 0; i + 1 < K; i++) {
-    const double db = j->betas[i] - j->betas[i + 1];
-    sgn[i] = db > 0 ? 1 : (db < 0 ? -1 : 0);
-    for (int b = 0; b < 24; b++)
-      F[(size_t)i * 24 + b] = scaled_floor(std::exp(-std::fabs(db) * std::ldexp(1.0, b)), 32);
-  }
+  for (int i = 0; i + 1 < K; i++) pt_factors(j->betas[i], j->betas[i + 1], &F[(size_t)i * 24], &sgn[i]);
   return SG_OK;
 }
 
@@ -667,6 +670,31 @@ int32_t sg_wheels_per_copy(int32_t L) { return sg::supported_L(L) ? sg::geom(L).
 int32_t sg_model_wheels_per_copy(int32_t model, int32_t L) {
   if (model == SG_GPOTTS4) return sg::potts4_supported_L(L) ? sg::geom4(L).NW : 0;
   return sg_wheels_per_copy(L);
+}
+
+int sg_threshold_row(int32_t model, int32_t algo, double beta, double field, uint32_t row[32]) {
+  GUARD_BEGIN
+  if (!row) return fail(SG_E_INVALID, "row is NULL");
+  if (model < SG_ISING || model > SG_GPOTTS4) return fail(SG_E_INVALID, "bad model %d", model);
+  if (algo != SG_METROPOLIS && algo != SG_HEATBATH) return fail(SG_E_INVALID, "bad algo %d", algo);
+  if (is_potts(model) && algo != SG_HEATBATH)
+    return fail(SG_E_UNSUPPORTED, "the Potts models are built for heat bath only");
+  if (!(beta >= 0.0) || std::isinf(beta)) return fail(SG_E_INVALID, "beta must be finite and >= 0");
+  if (model == SG_ISING_GEN) {
+    if (!(field >= 0.0) || std::isinf(field)) return fail(SG_E_INVALID, "field must be finite and >= 0");
+    return gen_threshold_row(algo, beta, field, row);
+  }
+  threshold_row(model, algo, beta, row);
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_pt_factors(double beta_i, double beta_next, uint64_t F[24], int32_t *sign) {
+  if (!F || !sign) return fail(SG_E_INVALID, "NULL argument");
+  if (!(beta_i >= 0.0) || !(beta_next >= 0.0) || std::isinf(beta_i) || std::isinf(beta_next))
+    return fail(SG_E_INVALID, "betas must be finite and >= 0");
+  pt_factors(beta_i, beta_next, F, sign);
+  return SG_OK;
 }
 
 int sg_ctx_create(int device, sg_ctx **out) {
@@ -714,9 +742,6 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   if (!ctx || !out) return fail(SG_E_INVALID, "ctx or out is NULL");
   int rc = check_spec(spec);
   if (rc) return rc;
-  if (!J || !spins || !wheels) return fail(SG_E_INVALID, "J, spins and wheels are required");
-  if (spec->pt_every > 0 && spec->n_temps > 1 && !ptwheels)
-    return fail(SG_E_INVALID, "parallel tempering needs ptwheels");
   rc = check_betas(betas, spec->n_temps);
   if (rc) return rc;
   const Layout lay = layout(spec);
@@ -728,14 +753,41 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   if (lay.spins_bytes >= (1ull << 32) || lay.wheels_bytes >= (1ull << 32) || lay.J_bytes >= (1ull << 32))
     return fail(SG_E_UNSUPPORTED, "job too large for one device buffer (split it into several jobs)");
   const uint64_t N = sites_of(spec->model, spec->L);
-  // validate host inputs
   const uint64_t S = spec->n_samples, R = spec->n_replicas, K = spec->n_temps, C = S * R * K;
+  const uint64_t NW = (uint64_t)geom_of(spec->model, spec->L).NW;
+  const bool pt = spec->pt_every > 0 && spec->n_temps > 1;
+  // inputs passed as NULL come from the spec's seed
+  const uint64_t rows = spec->model == SG_ISING_GEN ? 5 : spec->model == SG_GPOTTS4 ? 4 : 3;
+  std::vector<int8_t> genJ;
+  std::vector<uint8_t> genS;
+  std::vector<uint32_t> genW, genP;
+  if (!J) {
+    genJ.resize(S * rows * N);
+    J = genJ.data();
+  }
+  if (!spins) {
+    genS.resize(C * N);
+    spins = genS.data();
+  }
+  if (!wheels) {
+    genW.resize(C * NW * 61);
+    wheels = genW.data();
+  }
+  if (!ptwheels && pt) {
+    genP.resize(S * R * 61);
+    ptwheels = genP.data();
+  }
+  if (!genJ.empty() || !genS.empty() || !genW.empty() || !genP.empty()) {
+    rc = sg_generate(spec, genJ.empty() ? nullptr : genJ.data(), genS.empty() ? nullptr : genS.data(),
+                     genW.empty() ? nullptr : genW.data(), genP.empty() ? nullptr : genP.data());
+    if (rc) return fail(rc, "instance generation failed");
+  }
+  // validate host inputs
   int perm_num[256];
   permutation_numbers(perm_num);
   if (spec->model == SG_GPOTTS || spec->model == SG_GPOTTS4) {
     const uint8_t *P = (const uint8_t *)J;
-    const uint64_t dims = spec->model == SG_GPOTTS4 ? 4 : 3;
-    for (uint64_t i = 0; i < S * dims * N; i++)
+    for (uint64_t i = 0; i < S * rows * N; i++)
       if (perm_num[P[i]] < 0) return fail(SG_E_INVALID, "coupling byte %u is not a permutation", P[i]);
   } else if (spec->model == SG_ISING_GEN) {
     for (uint64_t s = 0; s < S; s++)
@@ -791,60 +843,51 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   hipStream_t st = S_(stream);
   HIPCHK(hipSetDevice(ctx->device));
 
-  // pack on the host, upload
-  std::vector<uint8_t> buf;
+  // pack on the host; every upload is ordered on the caller's stream and the
+  // host buffers live until the final stream synchronisation
+  std::vector<uint32_t> spw, jw, wv, pw((size_t)S * R * 64, 0);
+  std::vector<uint8_t> spb;
   if (!is_potts(spec->model)) {
-    std::vector<uint32_t> sp((size_t)C * j->g.CS);
+    spw.resize((size_t)C * j->g.CS);
     for (uint64_t c = 0; c < C; c++)
-      pack_ising_spins(j->g, (const int8_t *)spins + c * N, &sp[c * j->g.CS]);
-    std::vector<uint32_t> jw((size_t)lay.J_bytes / 4);
+      pack_ising_spins(j->g, (const int8_t *)spins + c * N, &spw[c * j->g.CS]);
+    jw.resize((size_t)lay.J_bytes / 4);
     if (spec->model == SG_ISING)
       for (uint64_t s = 0; s < S; s++) pack_ising_J(j->g, J + s * 3 * N, &jw[s * sg::ising_js(j->L)]);
     else
       for (uint64_t s = 0; s < S; s++) pack_gen_J(j->g, J + s * 5 * N, &jw[s * sg::gen_js(j->L)]);
-    HIPCHK(hipMemcpy(j->at<void>(lay.spins), sp.data(), lay.spins_bytes, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(j->at<void>(lay.J), jw.data(), lay.J_bytes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(j->at<void>(lay.spins), spw.data(), lay.spins_bytes, hipMemcpyHostToDevice, st));
   } else {
-    std::vector<uint8_t> sp((size_t)C * N);
+    spb.resize((size_t)C * N);
     for (uint64_t c = 0; c < C; c++)
       if (spec->model == SG_GPOTTS4)
-        pack_potts4_spins(j->L, (const uint8_t *)spins + c * N, &sp[c * N]);
+        pack_potts4_spins(j->L, (const uint8_t *)spins + c * N, &spb[c * N]);
       else
-        pack_potts_spins(j->L, (const uint8_t *)spins + c * N, &sp[c * N]);
-    std::vector<uint32_t> jp((size_t)lay.J_bytes / 4);
+        pack_potts_spins(j->L, (const uint8_t *)spins + c * N, &spb[c * N]);
+    jw.resize((size_t)lay.J_bytes / 4);
     if (spec->model == SG_POTTS) {
-      for (uint64_t s = 0; s < S; s++) pack_potts_J(j->g, J + s * 3 * N, &jp[s * sg::potts_js(j->L)]);
+      for (uint64_t s = 0; s < S; s++) pack_potts_J(j->g, J + s * 3 * N, &jw[s * sg::potts_js(j->L)]);
     } else if (spec->model == SG_GPOTTS4) {
       for (uint64_t s = 0; s < S; s++)
-        pack_gpotts4_J(j->g, (const uint8_t *)J + s * 4 * N, perm_num, &jp[s * sg::gpotts4_js(j->L)]);
+        pack_gpotts4_J(j->g, (const uint8_t *)J + s * 4 * N, perm_num, &jw[s * sg::gpotts4_js(j->L)]);
     } else {
       for (uint64_t s = 0; s < S; s++)
-        pack_gpotts_J(j->g, (const uint8_t *)J + s * 3 * N, perm_num, &jp[s * sg::gpotts_js(j->L)]);
+        pack_gpotts_J(j->g, (const uint8_t *)J + s * 3 * N, perm_num, &jw[s * sg::gpotts_js(j->L)]);
     }
-    HIPCHK(hipMemcpy(j->at<void>(lay.spins), sp.data(), lay.spins_bytes, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(j->at<void>(lay.J), jp.data(), lay.J_bytes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(j->at<void>(lay.spins), spb.data(), lay.spins_bytes, hipMemcpyHostToDevice, st));
   }
-  {
-    const uint64_t k0 = sweeps_done * (uint64_t)j->g.RHO * j->L;
-    std::vector<uint32_t> wv((size_t)lay.wheels_bytes / 4, 0);
-    pack_wheels(j, wheels, k0, wv.data());
-    HIPCHK(hipMemcpy(j->at<void>(lay.wheels), wv.data(), lay.wheels_bytes, hipMemcpyHostToDevice));
-  }
-  {
-    std::vector<uint32_t> pw((size_t)S * R * 64, 0);
-    if (ptwheels)
-      for (uint64_t ch = 0; ch < S * R; ch++) std::memcpy(&pw[ch * 64], ptwheels + ch * 61, 61 * 4);
-    HIPCHK(hipMemcpy(j->at<void>(lay.ptw), pw.data(), pw.size() * 4, hipMemcpyHostToDevice));
-  }
-  HIPCHK(hipMemcpy(j->at<void>(lay.sot), sot.data(), sot.size() * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(j->at<void>(lay.tos), tos.data(), tos.size() * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(j->at<void>(lay.done), &sweeps_done, 8, hipMemcpyHostToDevice));
-  {
-    std::vector<uint8_t> z((size_t)(lay.done - lay.E), 0);  // E, Q, accepts
-    HIPCHK(hipMemcpy(j->at<void>(lay.E), z.data(), z.size(), hipMemcpyHostToDevice));
-  }
-  rc = upload_tables(j, st);
-  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.J), jw.data(), lay.J_bytes, hipMemcpyHostToDevice, st));
+  wv.assign((size_t)lay.wheels_bytes / 4, 0);
+  pack_wheels(j, wheels, sweeps_done * (uint64_t)j->g.RHO * j->L, wv.data());
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.wheels), wv.data(), lay.wheels_bytes, hipMemcpyHostToDevice, st));
+  if (ptwheels)
+    for (uint64_t ch = 0; ch < S * R; ch++) std::memcpy(&pw[ch * 64], ptwheels + ch * 61, 61 * 4);
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.ptw), pw.data(), pw.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.sot), sot.data(), sot.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.tos), tos.data(), tos.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.done), &j->sweeps_done, 8, hipMemcpyHostToDevice, st));
+  std::vector<uint8_t> zero((size_t)(lay.done - lay.E), 0);  // E, Q, accepts
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.E), zero.data(), zero.size(), hipMemcpyHostToDevice, st));
   // own launch plan
   int tpb = 512;
   if (j->g.NW > tpb) tpb = j->g.NW;
@@ -855,13 +898,14 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   xcd_order(j->works);
   j->tpb = ((G * j->g.NW + 63) / 64) * 64;
   j->lds = item_lds(j, G);
-  HIPCHK(hipMemcpy(j->at<void>(lay.works), j->works.data(), j->works.size() * sizeof(Work), hipMemcpyHostToDevice));
-  {
-    std::vector<PtWork> pw;
-    make_pt_works(j, pw);
-    HIPCHK(hipMemcpy(j->at<void>(lay.ptworks), pw.data(), pw.size() * sizeof(PtWork), hipMemcpyHostToDevice));
-  }
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.works), j->works.data(), j->works.size() * sizeof(Work),
+                        hipMemcpyHostToDevice, st));
+  std::vector<PtWork> ptw;
+  make_pt_works(j, ptw);
+  HIPCHK(hipMemcpyAsync(j->at<void>(lay.ptworks), ptw.data(), ptw.size() * sizeof(PtWork),
+                        hipMemcpyHostToDevice, st));
+  rc = upload_tables(j, st);  // ends with a synchronisation of the stream
+  if (rc) return rc;
   *out = owner.release();
   return SG_OK;
   GUARD_END
@@ -915,6 +959,18 @@ int sg_job_sweep(sg_job *job, uint64_t n_sweeps, void *stream) {
     }
   }
   return SG_OK;
+  GUARD_END
+}
+
+int sg_job_sweep_beta(sg_job *job, double beta, uint64_t n_sweeps, void *stream) {
+  GUARD_BEGIN
+  if (!job) return fail(SG_E_INVALID, "job is NULL");
+  if (job->K != 1) return fail(SG_E_INVALID, "sweep(beta, n) is for jobs with one temperature (K = %d)", job->K);
+  if (job->betas[0] != beta) {
+    const int rc = sg_job_set_betas(job, &beta, stream);
+    if (rc) return rc;
+  }
+  return sg_job_sweep(job, n_sweeps, stream);
   GUARD_END
 }
 
@@ -1041,6 +1097,186 @@ int sg_job_sweeps_done(const sg_job *job, uint64_t *out) {
   return SG_OK;
 }
 
+// ------------------------------------------------------------ checkpoint --
+// Blob (8-byte items first, so every section is aligned in an aligned
+// buffer): header, betas [K] (double), swap counters [S*R][max(K-1, 1)],
+// energies per slot [C], canonical spins [C][N] (1 byte per site), sweep
+// wheels [C][NW][61], parallel-tempering wheels [S*R][61], slot_of_temp
+// [S*R][K].
+struct CkHeader {
+  char magic[8];
+  uint32_t conventions, header_bytes;
+  int32_t model, algo, q, L, S, R, K, pt_every;
+  double field;
+  uint64_t sweeps_done, J_digest, total_bytes;
+};
+static const char CK_MAGIC[8] = {'S', 'G', 'C', 'K', 'P', 'T', '0', '1'};
+static const uint32_t CONVENTIONS_VERSION = 1;
+
+static uint64_t ck_bytes(const sg_job *j) {
+  const uint64_t K1 = j->K > 1 ? j->K - 1 : 1;
+  return sizeof(CkHeader) + (uint64_t)j->K * 8 + (uint64_t)j->C * j->N +
+         (uint64_t)j->C * j->g.NW * 61 * 4 + (uint64_t)j->chains * 61 * 4 +
+         (uint64_t)j->chains * j->K * 4 + (uint64_t)j->chains * K1 * 8 + (uint64_t)j->C * 8;
+}
+
+// 64-bit FNV-1a of the job's device couplings (identifies the instance)
+static int J_digest(sg_job *j, hipStream_t st, uint64_t *out) {
+  std::vector<uint8_t> raw((size_t)j->lay.J_bytes);
+  HIPCHK(hipMemcpyAsync(raw.data(), j->at<void>(j->lay.J), raw.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (uint8_t b : raw) h = (h ^ b) * 0x100000001b3ull;
+  *out = h;
+  return SG_OK;
+}
+
+int sg_job_checkpoint_bytes(const sg_job *job, uint64_t *bytes) {
+  if (!job || !bytes) return fail(SG_E_INVALID, "NULL argument");
+  *bytes = ck_bytes(job);
+  return SG_OK;
+}
+
+int sg_job_checkpoint(sg_job *job, void *host_buf, uint64_t bytes, void *stream) {
+  GUARD_BEGIN
+  if (!job || !host_buf) return fail(SG_E_INVALID, "NULL argument");
+  if (bytes < ck_bytes(job))
+    return fail(SG_E_NOMEM, "checkpoint needs %llu bytes, buffer has %llu",
+                (unsigned long long)ck_bytes(job), (unsigned long long)bytes);
+  hipStream_t st = S_(stream);
+  CkHeader h{};
+  std::memcpy(h.magic, CK_MAGIC, 8);
+  h.conventions = CONVENTIONS_VERSION;
+  h.header_bytes = sizeof(CkHeader);
+  h.model = job->sp.model;
+  h.algo = job->sp.algo;
+  h.q = job->sp.q;
+  h.L = job->L;
+  h.S = job->S;
+  h.R = job->R;
+  h.K = job->K;
+  h.pt_every = job->sp.pt_every;
+  h.field = job->sp.field;
+  h.sweeps_done = job->sweeps_done;
+  h.total_bytes = ck_bytes(job);
+  int rc = J_digest(job, st, &h.J_digest);
+  if (rc) return rc;
+  uint8_t *p = (uint8_t *)host_buf;
+  std::memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  std::memcpy(p, job->betas.data(), (size_t)job->K * 8);
+  p += (size_t)job->K * 8;
+  rc = sg_job_get_pt_accepts(job, (uint64_t *)p, stream);
+  if (rc) return rc;
+  p += (size_t)job->chains * (job->K > 1 ? job->K - 1 : 1) * 8;
+  rc = sg_job_energies(job, (int64_t *)p, stream);
+  if (rc) return rc;
+  p += (size_t)job->C * 8;
+  rc = sg_job_get_spins(job, p, stream);
+  if (rc) return rc;
+  p += (size_t)job->C * job->N;
+  uint32_t *wh = (uint32_t *)p;
+  uint32_t *ptw = wh + (size_t)job->C * job->g.NW * 61;
+  rc = sg_job_get_wheels(job, wh, ptw, stream);
+  if (rc) return rc;
+  return sg_job_get_perm(job, (int32_t *)(ptw + (size_t)job->chains * 61), stream);
+  GUARD_END
+}
+
+int sg_job_restore(sg_job *j, const void *host_buf, uint64_t bytes, void *stream) {
+  GUARD_BEGIN
+  if (!j || !host_buf) return fail(SG_E_INVALID, "NULL argument");
+  CkHeader h;
+  if (bytes < sizeof h) return fail(SG_E_INVALID, "not a checkpoint (too short)");
+  std::memcpy(&h, host_buf, sizeof h);
+  if (std::memcmp(h.magic, CK_MAGIC, 8) != 0 || h.header_bytes != sizeof h)
+    return fail(SG_E_INVALID, "not a checkpoint of this library");
+  if (h.conventions != CONVENTIONS_VERSION)
+    return fail(SG_E_STATE, "checkpoint of conventions version %u, library has %u", h.conventions,
+                CONVENTIONS_VERSION);
+  if (h.model != j->sp.model || h.algo != j->sp.algo || h.L != j->L || h.S != j->S || h.R != j->R ||
+      h.K != j->K || h.pt_every != j->sp.pt_every || h.field != j->sp.field)
+    return fail(SG_E_STATE, "checkpoint of another job specification");
+  if (h.total_bytes != ck_bytes(j) || bytes < h.total_bytes)
+    return fail(SG_E_INVALID, "checkpoint size %llu does not match the job", (unsigned long long)bytes);
+  hipStream_t st = S_(stream);
+  uint64_t dig = 0;
+  int rc = J_digest(j, st, &dig);
+  if (rc) return rc;
+  if (dig != h.J_digest) return fail(SG_E_STATE, "checkpoint of other couplings");
+  const uint8_t *p = (const uint8_t *)host_buf + sizeof h;
+  std::vector<double> betas((size_t)j->K);
+  std::memcpy(betas.data(), p, betas.size() * 8);
+  rc = check_betas(betas.data(), j->K);
+  if (rc) return rc;
+  p += (size_t)j->K * 8;
+  const int K1 = j->K > 1 ? j->K - 1 : 1;
+  const uint8_t *acc = p;
+  p += (size_t)j->chains * K1 * 8;
+  const uint8_t *E = p;
+  p += (size_t)j->C * 8;
+  const uint8_t *spins = p;
+  p += (size_t)j->C * j->N;
+  const uint8_t *wh = p;
+  p += (size_t)j->C * j->g.NW * 61 * 4;
+  const uint8_t *ptw = p;
+  p += (size_t)j->chains * 61 * 4;
+  std::vector<int32_t> sot_in((size_t)j->chains * j->K);
+  std::memcpy(sot_in.data(), p, sot_in.size() * 4);
+  // validate before touching the device
+  const bool ising = !is_potts(j->sp.model);
+  for (uint64_t i = 0; i < (uint64_t)j->C * j->N; i++)
+    if (ising ? ((int8_t)spins[i] != 1 && (int8_t)spins[i] != -1) : spins[i] > 3)
+      return fail(SG_E_INVALID, "checkpoint holds invalid spins");
+  std::vector<int32_t> sot((size_t)j->chains * j->K), tos((size_t)j->C);
+  for (int ch = 0; ch < j->chains; ch++) {
+    std::vector<int> seen((size_t)j->K, 0);
+    for (int k = 0; k < j->K; k++) {
+      const int32_t v = sot_in[(size_t)ch * j->K + k];
+      if (v < 0 || v >= j->K || seen[v]) return fail(SG_E_INVALID, "checkpoint permutation is invalid");
+      seen[v] = 1;
+      sot[(size_t)ch * j->K + k] = v;
+      tos[(size_t)ch * j->K + v] = k;
+    }
+  }
+  // pack and upload, ordered on the stream
+  std::vector<uint32_t> spw, wv((size_t)j->lay.wheels_bytes / 4, 0), pw((size_t)j->chains * 64, 0);
+  std::vector<uint8_t> spb;
+  if (ising) {
+    spw.resize((size_t)j->C * j->g.CS);
+    for (int c = 0; c < j->C; c++)
+      pack_ising_spins(j->g, (const int8_t *)spins + (size_t)c * j->N, &spw[(size_t)c * j->g.CS]);
+    HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.spins), spw.data(), j->lay.spins_bytes, hipMemcpyHostToDevice, st));
+  } else {
+    spb.resize((size_t)j->C * j->N);
+    for (int c = 0; c < j->C; c++)
+      if (j->sp.model == SG_GPOTTS4)
+        pack_potts4_spins(j->L, spins + (size_t)c * j->N, &spb[(size_t)c * j->N]);
+      else
+        pack_potts_spins(j->L, spins + (size_t)c * j->N, &spb[(size_t)c * j->N]);
+    HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.spins), spb.data(), j->lay.spins_bytes, hipMemcpyHostToDevice, st));
+  }
+  {
+    std::vector<uint32_t> words((size_t)j->C * j->g.NW * 61);
+    std::memcpy(words.data(), wh, words.size() * 4);
+    pack_wheels(j, words.data(), h.sweeps_done * (uint64_t)j->g.RHO * j->L, wv.data());
+  }
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.wheels), wv.data(), j->lay.wheels_bytes, hipMemcpyHostToDevice, st));
+  for (int ch = 0; ch < j->chains; ch++) std::memcpy(&pw[(size_t)ch * 64], ptw + (size_t)ch * 61 * 4, 61 * 4);
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.ptw), pw.data(), pw.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.sot), sot.data(), sot.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.tos), tos.data(), tos.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.acc), acc, (size_t)j->chains * K1 * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.E), E, (size_t)j->C * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.done), &h.sweeps_done, 8, hipMemcpyHostToDevice, st));
+  j->betas = betas;
+  rc = upload_tables(j, st);  // ends with a synchronisation of the stream
+  if (rc) return rc;
+  j->sweeps_done = h.sweeps_done;
+  return SG_OK;
+  GUARD_END
+}
+
 int sg_job_debug_rng(sg_job *job, int32_t copy, int32_t wheel, uint32_t n, uint32_t *out, void *stream) {
   if (!job || !out) return fail(SG_E_INVALID, "NULL argument");
   if (copy < 0 || copy >= job->C || wheel < 0 || wheel >= job->g.NW || n > 4096)
@@ -1105,6 +1341,8 @@ struct sg_batch {
   hipEvent_t fork = nullptr, join[NGROUP - 1] = {};
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the fused sweep launch
+  bool ran = false;                // periods have been enqueued ...
+  hipStream_t last_stream = nullptr;  // ... on this stream (by the last run)
 };
 
 static void drop_graphs(sg_batch *b) {
@@ -1130,8 +1368,19 @@ static double idle_fraction(const sg_batch *b, int tpb) {
   return total > 0 ? 1.0 - used / total : 0.0;
 }
 
+// Plan of the current membership.  Periods already enqueued (on the stream
+// of the last run) may still read the launch tables and the parallel-
+// tempering tables, so a re-plan first waits for them: the caller may add
+// and remove jobs between runs without synchronising.
+static int wait_enqueued(sg_batch *b) {
+  if (b->ran) HIPCHK(hipStreamSynchronize(b->last_stream));
+  return SG_OK;
+}
+
 static int plan(sg_batch *b) {
   if (!b->dirty) return SG_OK;
+  int rc = wait_enqueued(b);
+  if (rc) return rc;
   drop_graphs(b);
   int tpb = b->block_req;
   if (tpb <= 0) {
@@ -1221,7 +1470,9 @@ static int apply_caps(sg_batch *b, uint64_t chunk, hipStream_t st) {
     if (cap[i] != b->run_cap[i]) changed = true;
   }
   if (!changed) return SG_OK;
-  HIPCHK(hipStreamSynchronize(st));  // earlier periods may still read the tables
+  (void)st;
+  int rc = wait_enqueued(b);  // earlier periods may still read the tables
+  if (rc) return rc;
   b->run_cap = cap;
   std::map<const sg_job *, int32_t> by_job;
   for (size_t i = 0; i < b->jobs.size(); i++) by_job[b->jobs[i]] = cap[i];
@@ -1323,14 +1574,18 @@ static int batch_streams(sg_batch *b) {
 
 extern "C" {
 
-int sg_batch_create(sg_ctx *ctx, sg_batch **out) {
+int sg_batch_create(sg_ctx *ctx, sg_job *const *jobs, int32_t n, sg_batch **out) {
   GUARD_BEGIN
   if (!ctx || !out) return fail(SG_E_INVALID, "NULL argument");
+  if (n < 0 || (n > 0 && !jobs)) return fail(SG_E_INVALID, "bad job list");
   sg_batch *b = new sg_batch;
   b->ctx = ctx;
-  const int rc = batch_streams(b);
+  int rc = batch_streams(b);
+  for (int32_t i = 0; rc == SG_OK && i < n; i++) rc = sg_batch_add(b, jobs[i]);
   if (rc) {
+    const std::string msg = g_err;
     sg_batch_destroy(b);  // releases whatever was created
+    g_err = msg;
     return rc;
   }
   *out = b;
@@ -1402,9 +1657,14 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
   GUARD_BEGIN
   if (!b) return fail(SG_E_INVALID, "batch is NULL");
   if (b->jobs.empty() || n_sweeps == 0) return SG_OK;
+  hipStream_t st = S_(stream);
+  // periods enqueued by earlier runs on another stream are waited for here;
+  // those on `st` are waited for wherever the tables change
+  if (b->ran && b->last_stream != st) HIPCHK(hipStreamSynchronize(b->last_stream));
+  b->last_stream = st;
+  b->ran = true;
   int rc = plan(b);
   if (rc) return rc;
-  hipStream_t st = S_(stream);
   uint64_t left = n_sweeps;
   while (left > 0) {
     uint64_t chunk = std::min<uint64_t>(left, 1u << 20);

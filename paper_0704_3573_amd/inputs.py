@@ -220,3 +220,24 @@ def linear_temperatures(K: int, t_min: float = 0.7, t_max: float = 1.6) -> np.nd
         return np.array([t_min])
     i = np.arange(K, dtype=np.float64)
     return t_min + (t_max - t_min) * i / (K - 1)
+
+
+def job_stream(n_jobs: int, rate: float, seed: int = 5, sweeps_lo: float = 3.0,
+               sweeps_hi: float = 5.0, sizes=(8, 16, 24, 32, 48), t_range=(0.7, 1.6),
+               seed0: int = 5000):
+    """Parameters of a stream of simulation jobs: exponential inter-arrival
+    times (rate per second), model "ising" (Metropolis) or "potts" (heat bath)
+    with probability 1/2, L uniform in `sizes`, T uniform in t_range,
+    sweeps = floor(10^U[sweeps_lo, sweeps_hi]), job seed seed0 + j.  Returns
+    dicts with keys rid, model, L, T, sweeps, seed, arrival.  The job
+    parameters do not depend on the rate."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0, size=n_jobs)
+    t = np.cumsum(gaps / rate) if rate > 0 else np.zeros(n_jobs)
+    out = []
+    for j in range(n_jobs):
+        out.append({"rid": j, "model": "ising" if rng.random() < 0.5 else "potts",
+                    "L": int(rng.choice(sizes)), "T": float(rng.uniform(*t_range)),
+                    "sweeps": int(np.floor(10 ** rng.uniform(sweeps_lo, sweeps_hi))),
+                    "seed": seed0 + j, "arrival": float(t[j])})
+    return out

@@ -179,17 +179,10 @@ def poisson_stream(n_jobs: int, rate: float, seed: int = 5, sweeps_lo: float = 3
                    seed0: int = 5000):
     """Requests with exponential inter-arrival times (rate per second); model
     Ising or Potts with probability 1/2, L uniform in `sizes`, T uniform in
-    t_range, sweeps = floor(10^U[sweeps_lo, sweeps_hi]), job seed seed0 + j."""
-    rng = np.random.default_rng(seed)
-    t = np.cumsum(rng.exponential(1.0 / rate, size=n_jobs)) if rate > 0 else np.zeros(n_jobs)
-    out = []
-    for j in range(n_jobs):
-        out.append(Request(
-            rid=j, model="ising" if rng.random() < 0.5 else "potts",
-            L=int(rng.choice(sizes)), T=float(rng.uniform(*t_range)),
-            sweeps=int(np.floor(10 ** rng.uniform(sweeps_lo, sweeps_hi))),
-            seed=seed0 + j, arrival=float(t[j])))
-    return out
+    t_range, sweeps = floor(10^U[sweeps_lo, sweeps_hi]), job seed seed0 + j
+    (parameters from inputs.job_stream)."""
+    return [Request(**p) for p in inputs.job_stream(n_jobs, rate, seed, sweeps_lo, sweeps_hi,
+                                                      sizes, t_range, seed0)]
 
 
 def summary(done, wall: float):

@@ -1,0 +1,193 @@
+"""GPU parity at full length and full population: libsg against fixtures the
+CPU oracle wrote (tests/golden/make_golden.py calls only the oracle and the
+seeded-input module).  Every job here is created from its seed alone, so the
+library also generates its own inputs (the CPU suite shows they equal the
+seeded-input module's).  Integers are compared exactly; spin, wheel and
+energy arrays through 64-bit BLAKE2b digests of their canonical bytes.
+
+  C2  EA L = 64, 2 replicas, 10^4 sweeps, all 100 energy/overlap measurements;
+  C3  the benchmark's batched parallel-tempering workload in its launch
+      configuration (one fused launch per period, 512 threads): samples 5
+      and 63 of every L at 10^4 sweeps (energies by temperature and overlaps
+      every 1000 sweeps, temperature permutations, swap counters, both
+      wheels), and every copy of all 256 samples after 100 sweeps;
+  C4  q = 4 +-J Potts, 10^4 sweeps, measurements every 100: all 128 samples
+      at L = 16, samples 0, 8, ..., 120 at L = 32 (the whole 128-sample job
+      runs on the device);
+  C5  50 jobs of the 2000-job serving stream, run alone.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from tests.golden.make_golden import C3_K, C3_L, C3_PE, C3_R, C3_S, C3_SEED, c3_betas, digest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} has not been generated (tests/golden/make_golden.py)")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_0704_3573_amd import binding as B
+    return B.Context(0)
+
+
+def test_c2_full_length_all_measurements(ctx):
+    from paper_0704_3573_amd import binding as B
+    g = load("c2_full.json")
+    job = B.Job(ctx, B.ISING, B.METROPOLIS, 64, [1 / 1.1], n_replicas=2, seed=2)
+    Es, Qs = [], []
+    for _ in range(g["sweeps"] // g["measure_every"]):
+        job.sweep(g["measure_every"])
+        E, Q = job.measure()
+        Es.append(E.tolist())
+        Qs.append(int(Q[0]))
+    for m, (a, b) in enumerate(zip(Es, g["E_log"])):
+        assert a == b, f"energies differ at measurement {m}"
+    assert Qs == g["Q_log"]
+    sp = job.spins()
+    wh, _ = job.wheels()
+    assert [digest(sp[c]) for c in range(2)] == g["spins"]
+    assert [digest(wh[c]) for c in range(2)] == g["wheels"]
+
+
+def c3_jobs(ctx, B):
+    return [B.Job(ctx, B.ISING, B.METROPOLIS, L, c3_betas(), n_samples=C3_S, n_replicas=C3_R,
+                  pt_every=C3_PE, seed=C3_SEED, sample0=C3_S * i) for i, L in enumerate(C3_L)]
+
+
+def test_c3_full_length_chains(ctx):
+    from paper_0704_3573_amd import binding as B
+    g = load("c3_chains.json")
+    jobs = c3_jobs(ctx, B)
+    batch = B.Batch(ctx, jobs, block=512)
+    cps = C3_R * C3_K
+    recs = {(r["L"], r["job_sample"]): r for r in g["records"]}
+    me = g["measure_every"]
+    logs = {key: ([], []) for key in recs}
+    for _ in range(g["sweeps"] // me):
+        batch.run(me)
+        for L, job in zip(C3_L, jobs):
+            E, Q = job.measure()
+            for s in (5, 63):
+                logs[(L, s)][0].append(E[s * cps:(s + 1) * cps].tolist())
+                logs[(L, s)][1].append(Q[s * C3_K:(s + 1) * C3_K].tolist())
+    for L, job in zip(C3_L, jobs):
+        sp = job.spins()
+        wh, pw = job.wheels()
+        Es = job.energies()
+        perm, acc = job.perm(), job.pt_accepts()
+        for s in (5, 63):
+            r, what = recs[(L, s)], f"L={L} sample {s}"
+            c0 = s * cps
+            assert logs[(L, s)][0] == r["E_log"], what
+            assert logs[(L, s)][1] == r["Q_log"], what
+            assert Es[c0:c0 + cps].tolist() == r["E"], what
+            assert perm[s * C3_R:(s + 1) * C3_R].tolist() == r["slot_of_temp"], what
+            assert acc[s * C3_R:(s + 1) * C3_R].tolist() == r["pt_accepts"], what
+            assert [digest(sp[c0 + c]) for c in range(cps)] == r["spins"], what
+            assert [digest(wh[c0 + c]) for c in range(cps)] == r["wheels"], what
+            assert [digest(pw[s * C3_R + h]) for h in range(C3_R)] == r["ptwheels"], what
+
+
+def test_c3_every_copy_after_100_sweeps(ctx):
+    from paper_0704_3573_amd import binding as B
+    g = load("c3_all_copies.json")
+    jobs = c3_jobs(ctx, B)
+    batch = B.Batch(ctx, jobs, block=512)
+    batch.run(g["sweeps"])
+    cps = C3_R * C3_K
+    for L, job, gj in zip(C3_L, jobs, g["jobs"]):
+        assert gj["L"] == L
+        sp = job.spins()
+        wh, pw = job.wheels()
+        Es, perm = job.energies(), job.perm()
+        bad = []
+        for s, r in enumerate(gj["samples"]):
+            c, h = slice(s * cps, (s + 1) * cps), slice(s * C3_R, (s + 1) * C3_R)
+            got = {"spins": digest(sp[c]), "wheels": digest(wh[c]), "E": digest(Es[c]),
+                   "slot_of_temp": digest(perm[h]), "ptwheels": digest(pw[h])}
+            bad += [(s, k) for k in got if got[k] != r[k]]
+        assert not bad, f"L={L}: (sample, array) differing: {bad[:10]}"
+        assert int(Es.sum()) == gj["E_sum"]
+
+
+def test_c4_potts_full_length(ctx):
+    from paper_0704_3573_amd import binding as B
+    g = load("c4_potts.json")
+    me, S, R = g["measure_every"], 128, 2
+    for gj in g["jobs"]:
+        L = gj["L"]
+        job = B.Job(ctx, B.POTTS, B.HEATBATH, L, [1 / 0.9], n_samples=S, n_replicas=R, seed=4000)
+        Elog, Qlog = [], []
+        for _ in range(g["sweeps"] // me):
+            job.sweep(me)
+            E, Q = job.measure()
+            Elog.append(E)
+            Qlog.append(Q)
+        Elog, Qlog = np.array(Elog), np.array(Qlog)  # [meas][S*R], [meas][S]
+        sp = job.spins()
+        wh, _ = job.wheels()
+        for r in gj["records"]:
+            s, what = r["sample"], f"L={L} sample {r['sample']}"
+            c = slice(s * R, (s + 1) * R)
+            assert Elog[-1, c].tolist() == r["E"] and int(Qlog[-1, s]) == r["Q"], what
+            assert digest(Elog[:, c]) == r["E_log"], what
+            assert digest(Qlog[:, s]) == r["Q_log"], what
+            assert digest(sp[c]) == r["spins"] and digest(wh[c]) == r["wheels"], what
+        del job
+
+
+def test_c5_sampled_jobs_alone(ctx):
+    from paper_0704_3573_amd import binding as B
+    from tests.golden.make_golden import c5_sampled
+    g = load("c5_sampled_jobs.json")
+    params = c5_sampled()
+    assert len(params) == len(g["jobs"]) == 50
+    for p, r in zip(params, g["jobs"]):
+        assert {k: p[k] for k in ("rid", "model", "L", "sweeps", "seed")} == \
+            {k: r[k] for k in ("rid", "model", "L", "sweeps", "seed")}
+        ising = p["model"] == "ising"
+        job = B.Job(ctx, B.ISING if ising else B.POTTS, B.METROPOLIS if ising else B.HEATBATH,
+                    p["L"], [1.0 / p["T"]], n_replicas=2, seed=p["seed"])
+        job.sweep(p["sweeps"])
+        E, Q = job.measure()
+        what = f"job {p['rid']} ({p['model']} L={p['L']}, {p['sweeps']} sweeps)"
+        assert E.tolist() == r["E"] and int(Q[0]) == r["Q"], what
+        assert digest(job.spins()) == r["spins"] and digest(job.wheels()[0]) == r["wheels"], what
+        job.close()
+
+
+def test_c5_sampled_jobs_served_in_the_mix(ctx):
+    """The same 50 jobs through the continuous-batching server (at most 12
+    resident, so later jobs are admitted while earlier ones are mid-run and
+    share their fused launches): every result equals the oracle's."""
+    from paper_0704_3573_amd import serving
+    g = load("c5_sampled_jobs.json")
+    reqs = [serving.Request(r["rid"], r["model"], r["L"], r["T"], r["sweeps"], r["seed"],
+                            arrival=0.001 * i) for i, r in enumerate(g["jobs"])]
+    srv = serving.Server(serving.DeviceBackend(ctx), hbm_budget=64 << 20, max_slots=12,
+                         period=2000)
+    done = {r.rid: r for r in srv.serve(reqs)}
+    assert len(done) == 50
+    assert srv.peak_slots >= 2
+    # continuous batching: some job was admitted while another was running
+    assert any(a.t_admit < b.t_admit < a.t_done for a in done.values() for b in done.values())
+    for r in g["jobs"]:
+        got = done[r["rid"]]
+        what = f"job {r['rid']} ({r['model']} L={r['L']}, {r['sweeps']} sweeps)"
+        assert got.E.tolist() == r["E"] and got.Q == r["Q"], what
+        assert got.spins_hash == int.from_bytes(bytes.fromhex(r["spins"]), "little"), what

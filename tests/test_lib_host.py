@@ -3,6 +3,7 @@ include/sg.h declares, and validates specifications (no GPU calls)."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_0704_3573_amd import binding as B
@@ -90,3 +91,30 @@ def test_job_bytes_and_validation():
             B.job_bytes(spec)
         assert e.value.code == code
         assert B.lib().sg_last_error().decode()
+
+
+MODEL_NAMES = {"ising": B.ISING, "potts": B.POTTS, "gpotts": B.GPOTTS, "gpotts4": B.GPOTTS4,
+               "isinggen": B.ISING_GEN}
+
+
+@pytest.mark.parametrize("name", sorted(MODEL_NAMES))
+def test_library_generates_the_seeded_instances(name):
+    """A job created from its seed alone gets exactly the inputs of the
+    seeded-input module (couplings, spins, sweep and parallel-tempering
+    wheels), numbered from the job's first sample."""
+    from paper_0704_3573_amd import inputs
+    model = MODEL_NAMES[name]
+    Ls = (2, 4, 8) if name == "gpotts4" else (2, 4, 8, 16)
+    for L in Ls:
+        for S, R, K, seed, s0 in ((1, 1, 1, 1, 0), (2, 2, 3, 12345, 7)):
+            algo = B.METROPOLIS if name in ("ising", "isinggen") else B.HEATBATH
+            spec = B.Spec(model, algo, 4, L, S, R, K, 0, 0.0, seed, s0)
+            got = B.generate(spec)
+            want = inputs.make_instance(name, L, S, R, K, seed, s0)
+            for key in ("J", "spins", "wheels", "ptwheels"):
+                assert np.array_equal(got[key], want[key].reshape(got[key].shape)), (name, L, key)
+
+
+def test_generate_rejects_bad_specs():
+    with pytest.raises(B.SgError):
+        B.generate(B.Spec(B.ISING, B.METROPOLIS, 4, 12, 1, 1, 1, 0))
