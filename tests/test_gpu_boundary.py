@@ -75,7 +75,8 @@ def test_sweep_beta_equals_set_betas_then_sweep(ctx):
 def test_checkpoint_restore_is_bit_exact(ctx, name, algo, L, pe):
     from paper_0704_3573_amd import binding as B
     S, R, K = 2, 2, 3
-    betas = 1.0 / np.linspace(0.8, 1.4, K)
+    # close temperatures, so that swaps are accepted within a few steps
+    betas = 1.0 / np.linspace(1.0, 1.02, K)
     kw = dict(n_samples=S, n_replicas=R, pt_every=pe, seed=515,
               field=0.4 if name == "isinggen" else 0.0)
     full = B.Job(ctx, lib_model(name), algo, L, betas, **kw)
