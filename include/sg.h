@@ -274,6 +274,21 @@ int sg_batch_get_budget(sg_batch *b, sg_job *job, uint64_t *sweeps);
  * sg_job_sweep, parallel tempering included).  After membership changes the
  * call first waits for the work already enqueued on `stream`. */
 int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream);
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * periods as sg_batch_run, bit for bit, with the batch's launch tables (work
+ * items, per-job sweep counters and caps, parallel-tempering work lists) in
+ * a fixed device array of 2 MiB that each device holds until the process
+ * ends; SG_E_NOMEM (nothing run) if the tables need more (about 18,000 work
+ * items).  Calls no hipMalloc, hipFree or other allocating routine and
+ * captures no graph: periods are enqueued directly on `stream` (the timing
+ * mode does not apply).  Waits first for this batch's previous run.  Every
+ * call on a device shares that device's array and leaves its tables in it:
+ * calls of different batches on one device must not overlap in time (run
+ * them on one stream, or one after another) -- overlapping calls race.
+ */
+int sg_batch_run_static(sg_batch *b, uint64_t n_sweeps, void *stream);
 /* Threads per workgroup chosen for the current membership. */
 int sg_batch_block(sg_batch *b, int32_t *threads);
 /* Timing mode: periods are enqueued directly on the caller's stream (not

@@ -31,7 +31,7 @@ EXPORTS = (
     "sg_batch_add", "sg_batch_remove", "sg_batch_set_block", "sg_batch_run", "sg_batch_block",
     "sg_batch_set_timing", "sg_batch_sweep_ms", "sg_batch_set_budget", "sg_batch_get_budget",
     "sg_batch_destroy", "sg_generate", "sg_threshold_row", "sg_pt_factors", "sg_job_sweep_beta",
-    "sg_job_checkpoint_bytes", "sg_job_checkpoint", "sg_job_restore",
+    "sg_job_checkpoint_bytes", "sg_job_checkpoint", "sg_job_restore", "sg_batch_run_static",
 )
 
 
@@ -92,6 +92,7 @@ def lib():
         L.sg_batch_remove.argtypes = [vp, vp]
         L.sg_batch_set_block.argtypes = [vp, i32]
         L.sg_batch_run.argtypes = [vp, u64, vp]
+        L.sg_batch_run_static.argtypes = [vp, u64, vp]
         L.sg_batch_block.argtypes = [vp, C.POINTER(i32)]
         L.sg_batch_set_timing.argtypes = [vp, i32]
         L.sg_batch_sweep_ms.argtypes = [vp, C.POINTER(C.c_float)]
@@ -345,6 +346,11 @@ class Batch:
 
     def run(self, n: int, stream=None):
         _chk(lib().sg_batch_run(self.h, n, _stream(stream)))
+
+    def run_static(self, n: int, stream=None):
+        """As run(), with the launch tables in the library's static device
+        scratch: no device allocation (see sg_batch_run_static)."""
+        _chk(lib().sg_batch_run_static(self.h, n, _stream(stream)))
 
     def set_budget(self, job: Job, sweeps: int):
         _chk(lib().sg_batch_set_budget(self.h, job.h, sweeps))

@@ -34,6 +34,7 @@ hipError_t launch_advance(uint64_t *const *done, const int32_t *cap, int n, int 
                           hipStream_t st);
 hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st);
 hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st);
+hipError_t scratch_address(int device, void **out);
 }  // namespace sg
 
 using sg::Geom;
@@ -151,6 +152,7 @@ struct sg_ctx {
   int device;
   int max_lds;
   int cus;
+  void *scratch;  // device address of the static scratch array on this device
 };
 
 // ------------------------------------------------------------------- job --
@@ -708,8 +710,11 @@ int sg_ctx_create(int device, sg_ctx **out) {
   HIPCHK(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(SG_E_UNSUPPORTED, "device %d is %s, the kernels are built for gfx950", device, prop.gcnArchName);
+  void *scratch = nullptr;
+  HIPCHK(sg::scratch_address(device, &scratch));
   sg_ctx *c = new sg_ctx;
   c->device = device;
+  c->scratch = scratch;
   c->max_lds = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
   c->cus = prop.multiProcessorCount;
   if (sg::set_max_lds(c->max_lds) != hipSuccess) {
@@ -1343,6 +1348,18 @@ struct sg_batch {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the fused sweep launch
   bool ran = false;                // periods have been enqueued ...
   hipStream_t last_stream = nullptr;  // ... on this stream (by the last run)
+  // host copy of the launch tables of the no-allocation run (uploaded into
+  // the static device scratch; kept until the next call has waited for the
+  // periods of this one)
+  struct Static {
+    std::vector<Work> items[NMODEL][2];
+    size_t lds[NMODEL][2] = {};
+    int tpb = 0;
+    std::vector<uint64_t *> done;
+    std::vector<int32_t> cap;
+    std::vector<PtWork> pt;                 // fused PT work of every PT job, job after job
+    std::vector<int> pt_first, pt_count;    // per job (count 0: none or K > 64)
+  } stat;
 };
 
 static void drop_graphs(sg_batch *b) {
@@ -1377,11 +1394,10 @@ static int wait_enqueued(sg_batch *b) {
   return SG_OK;
 }
 
-static int plan(sg_batch *b) {
-  if (!b->dirty) return SG_OK;
-  int rc = wait_enqueued(b);
-  if (rc) return rc;
-  drop_graphs(b);
+// Host part of a plan: block size, work items per (model, algorithm) launch
+// (longest first, XCD-aware order) and each launch's LDS bytes.
+static int plan_items(const sg_batch *b, int &tpb_out, std::vector<Work> (&items)[NMODEL][2],
+                      size_t (&lds)[NMODEL][2]) {
   int tpb = b->block_req;
   if (tpb <= 0) {
     double best = 3;
@@ -1396,23 +1412,38 @@ static int plan(sg_batch *b) {
   }
   for (sg_job *j : b->jobs)
     if (j->g.NW > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
-  for (auto &a : b->items)
+  for (auto &a : items)
     for (auto &v : a) v.clear();
-  size_t lds[NMODEL][2] = {}, total = 0;
+  for (auto &a : lds)
+    for (auto &l : a) l = 0;
   for (sg_job *j : b->jobs) {
     const int G = copies_per_item(j, tpb);
     size_t &l = lds[j->sp.model][j->sp.algo];
     l = std::max(l, item_lds(j, G));
-    make_items(j, G, b->items[j->sp.model][j->sp.algo]);
+    make_items(j, G, items[j->sp.model][j->sp.algo]);
   }
   // longest items first: the launch tail is then made of short items
-  for (auto &a : b->items)
+  for (auto &a : items)
     for (auto &v : a)
       std::stable_sort(v.begin(), v.end(), [](const Work &x, const Work &y) {
         return work_size(x) > work_size(y);
       });
-  for (auto &a : b->items)
+  for (auto &a : items)
     for (auto &v : a) xcd_order(v);
+  tpb_out = tpb;
+  return SG_OK;
+}
+
+static int plan(sg_batch *b) {
+  if (!b->dirty) return SG_OK;
+  int rc = wait_enqueued(b);
+  if (rc) return rc;
+  drop_graphs(b);
+  size_t lds[NMODEL][2];
+  int tpb = 0;
+  rc = plan_items(b, tpb, b->items, lds);
+  if (rc) return rc;
+  size_t total = 0;
   for (auto &a : b->items)
     for (auto &v : a) total += v.size();
   if (total > b->d_items_cap) {
@@ -1716,6 +1747,127 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
       it = b->graphs.emplace(key, ge).first;
     }
     HIPCHK(hipGraphLaunch(it->second, st));
+    account(b, chunk);
+    left -= chunk;
+  }
+  return SG_OK;
+  GUARD_END
+}
+
+// No-allocation run: the launch tables live in the static device scratch,
+// laid out [work items][job sweep counters][job caps][parallel-tempering
+// work], each part 256-byte aligned; periods are enqueued directly (no graph).
+int sg_batch_run_static(sg_batch *b, uint64_t n_sweeps, void *stream) {
+  GUARD_BEGIN
+  if (!b) return fail(SG_E_INVALID, "batch is NULL");
+  if (b->jobs.empty() || n_sweeps == 0) return SG_OK;
+  if (!b->ctx->scratch) return fail(SG_E_STATE, "the context has no scratch address");
+  hipStream_t st = S_(stream);
+  // this batch's earlier periods may still read the scratch and the host
+  // tables uploaded from: wait for them before rewriting either
+  if (b->ran) HIPCHK(hipStreamSynchronize(b->last_stream));
+  b->last_stream = st;
+  b->ran = true;
+  auto &T = b->stat;
+  int rc = plan_items(b, T.tpb, T.items, T.lds);
+  if (rc) return rc;
+  const size_t nj = b->jobs.size();
+  size_t nitems = 0;
+  for (auto &a : T.items)
+    for (auto &v : a) nitems += v.size();
+  T.pt.clear();
+  T.pt_first.assign(nj, 0);
+  T.pt_count.assign(nj, 0);
+  for (size_t i = 0; i < nj; i++) {
+    sg_job *j = b->jobs[i];
+    if (j->sp.pt_every > 0 && j->K > 1 && j->K <= PT_FUSED_KMAX) {
+      T.pt_first[i] = (int)T.pt.size();
+      make_pt_works(j, T.pt);
+      T.pt_count[i] = (int)T.pt.size() - T.pt_first[i];
+    }
+  }
+  const uint64_t off_done = al(nitems * sizeof(Work));
+  const uint64_t off_cap = al(off_done + nj * sizeof(uint64_t *));
+  const uint64_t off_pt = al(off_cap + nj * sizeof(int32_t));
+  const uint64_t total = off_pt + T.pt.size() * sizeof(PtWork);
+  if (total > sg::STATIC_SCRATCH_BYTES)
+    return fail(SG_E_NOMEM, "the batch's launch tables need %llu bytes, the static scratch holds %llu "
+                "(split the batch, or use sg_batch_run)", (unsigned long long)total,
+                (unsigned long long)sg::STATIC_SCRATCH_BYTES);
+  uint8_t *base = (uint8_t *)b->ctx->scratch;
+  Work *d_items = (Work *)base;
+  uint64_t **d_done = (uint64_t **)(base + off_done);
+  int32_t *d_cap = (int32_t *)(base + off_cap);
+  PtWork *d_pt = (PtWork *)(base + off_pt);
+  T.done.clear();
+  for (sg_job *j : b->jobs) T.done.push_back(j->done_ptr());
+  HIPCHK(hipMemcpyAsync(d_done, T.done.data(), nj * sizeof(uint64_t *), hipMemcpyHostToDevice, st));
+  if (!T.pt.empty())
+    HIPCHK(hipMemcpyAsync(d_pt, T.pt.data(), T.pt.size() * sizeof(PtWork), hipMemcpyHostToDevice, st));
+  T.cap.clear();
+  uint64_t left = n_sweeps;
+  while (left > 0) {
+    uint64_t chunk = std::min<uint64_t>(left, 1u << 20);
+    for (sg_job *j : b->jobs)
+      if (j->sp.pt_every > 0 && j->K > 1)
+        chunk = std::min<uint64_t>(chunk, j->sp.pt_every - j->sweeps_done % j->sp.pt_every);
+    // per-job sweep caps of this period; the item table is (re)written when
+    // they change, after the periods reading it have finished
+    std::vector<int32_t> cap(nj);
+    for (size_t i = 0; i < nj; i++)
+      cap[i] = b->budget[i] == UINT64_MAX ? 0x7FFFFFFF : (int32_t)std::min<uint64_t>(chunk, b->budget[i]);
+    if (cap != T.cap) {
+      if (!T.cap.empty()) HIPCHK(hipStreamSynchronize(st));
+      T.cap = cap;
+      size_t off = 0;
+      for (auto &a : T.items)
+        for (auto &v : a) {
+          for (Work &w : v)
+            for (size_t i = 0; i < nj; i++)
+              if (w.done == b->jobs[i]->done_ptr()) w.nsweeps_cap = cap[i];
+          if (!v.empty())
+            HIPCHK(hipMemcpyAsync(d_items + off, v.data(), v.size() * sizeof(Work), hipMemcpyHostToDevice, st));
+          off += v.size();
+        }
+      HIPCHK(hipMemcpyAsync(d_cap, T.cap.data(), nj * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    }
+    const int nsw = (int)chunk;
+    size_t off = 0;
+    for (int m = 0; m < NMODEL; m++)
+      for (int a = 0; a < 2; a++) {
+        const auto &v = T.items[m][a];
+        if (!v.empty())
+          HIPCHK(sg::launch_sweep(m, a, d_items + off, (int)v.size(), model_tpb(m, T.tpb), T.lds[m][a], nsw, st));
+        off += v.size();
+      }
+    HIPCHK(sg::launch_advance(d_done, d_cap, (int)nj, nsw, st));
+    // parallel tempering of the jobs due after this period: fused launches
+    // over runs of consecutive due jobs, the unfused kernel for K > 64
+    size_t i = 0;
+    while (i < nj) {
+      sg_job *j = b->jobs[i];
+      const bool due = j->sp.pt_every > 0 && j->K > 1 && (j->sweeps_done + chunk) % j->sp.pt_every == 0;
+      if (!due) {
+        i++;
+        continue;
+      }
+      if (T.pt_count[i] == 0) {
+        rc = run_pt(j, st);
+        if (rc) return rc;
+        i++;
+        continue;
+      }
+      size_t e = i;
+      int kmax = 2, n = 0;
+      while (e < nj && T.pt_count[e] > 0 &&
+             (b->jobs[e]->sweeps_done + chunk) % b->jobs[e]->sp.pt_every == 0) {
+        kmax = std::max(kmax, b->jobs[e]->K);
+        n += T.pt_count[e];
+        e++;
+      }
+      HIPCHK(sg::launch_pt_fused(d_pt + T.pt_first[i], n, kmax, st));
+      i = e;
+    }
     account(b, chunk);
     left -= chunk;
   }

@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include "sg_layout.h"
+#include <mutex>
 #include <type_traits>
 
 #define DEV __device__ __forceinline__
@@ -1990,6 +1991,33 @@ hipError_t launch_advance(uint64_t *const *done, const int32_t *cap, int n, int 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(advance_kernel, dim3((n + 63) / 64), dim3(64), 0, st, done, cap, n, nsweeps);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the no-allocation batch run (sg_batch_run_static): the
+// launch tables of a batch (work items, per-job sweep counters and caps,
+// parallel-tempering work lists) go into this fixed device array instead of
+// library-allocated buffers.  Each device holds its own copy until the
+// process ends; host code uses only the address resolved here, never the
+// array's name (on the host the name is a stand-in, not a device address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[STATIC_SCRATCH_BYTES];
+
+// Device address of `scratch` on `device`, resolved once per device with that
+// device current (the caller has made it current).
+hipError_t scratch_address(int device, void **out) {
+  static std::mutex mu;
+  static void *addr[MAX_DEVICES] = {};
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 }  // namespace sg

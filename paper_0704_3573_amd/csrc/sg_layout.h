@@ -218,6 +218,12 @@ struct Work {
   int64_t *M;                    // [C] field sum per slot (Ising-like models), else null
 };
 
+// Size of the static device scratch of the no-allocation batch run (launch
+// tables only: about 112 bytes per work item, 12 per job, 72 per 64 chains),
+// and the number of devices whose scratch address the library keeps.
+constexpr uint64_t STATIC_SCRATCH_BYTES = 2u << 20;
+constexpr int MAX_DEVICES = 64;
+
 // Parallel-tempering work of one workgroup: up to 64 chains of one job.
 struct PtWork {
   const int64_t *E;          // [C] energy per slot
