@@ -170,6 +170,16 @@ static Geom geom_of(int model, int L) {
   if (model == SG_GPOTTS4) return sg::geom4(L);
   return model == SG_ISING || model == SG_ISING_GEN ? sg::igeom(L) : sg::geom(L);
 }
+// Lanes serving one copy, and the fused launch (sweep kernel) of a job: the
+// 3D Potts models run four lanes per wheel where the layout allows it.
+static int wheel_lanes(int model, int L) {
+  return model == SG_POTTS || model == SG_GPOTTS ? sg::potts_wheel_lanes(L) : 1;
+}
+static int launch_group(int model, int L) {
+  if (wheel_lanes(model, L) == 4) return model == SG_POTTS ? sg::LAUNCH_POTTS_QUAD : sg::LAUNCH_GPOTTS_QUAD;
+  return model;
+}
+
 static uint64_t sites_of(int model, int L) {
   const uint64_t N = (uint64_t)L * L * L;
   return model == SG_GPOTTS4 ? N * L : N;
@@ -256,6 +266,8 @@ struct sg_job {
     return (T *)(arena + off);
   }
   uint64_t *done_ptr() const { return at<uint64_t>(lay.done); }
+  int lanes() const { return g.NW * wheel_lanes(sp.model, L); }  // lanes per copy
+  int group() const { return launch_group(sp.model, L); }       // fused launch of the job
 };
 
 // lanes and LDS bytes of a work item of G copies
@@ -275,7 +287,7 @@ static size_t item_lds(const sg_job *j, int G) {
     return (size_t)48 * 4 + (size_t)G * sg::potts4_lds_copy(j->L) + (size_t)G * sg::POTTS4_W_WORDS * 4 +
            (size_t)G * 4 + dummy4;
   }
-  const size_t dummy = j->g.NW % 64 ? (size_t)j->g.RHO * j->L * j->L : 0;
+  const size_t dummy = j->lanes() % 64 ? (size_t)j->g.RHO * j->L * j->L : 0;
   return (size_t)sg::POTTS_TAB_WORDS * 4 + (size_t)G * sg::potts_lds_copy(j->L) +
          (size_t)G * sg::POTTS_W_WORDS * 4 + (size_t)G * 4 + dummy;
 }
@@ -286,7 +298,7 @@ static int model_tpb(int model, int tpb) {
 }
 
 static int copies_per_item(const sg_job *j, int tpb) {
-  int G = model_tpb(j->sp.model, tpb) / j->g.NW;
+  int G = model_tpb(j->sp.model, tpb) / j->lanes();
   G = std::min(G, j->C);
   while (G > 1 && item_lds(j, G) > (size_t)j->ctx->max_lds) G--;
   return G;
@@ -895,13 +907,13 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   HIPCHK(hipMemcpyAsync(j->at<void>(lay.E), zero.data(), zero.size(), hipMemcpyHostToDevice, st));
   // own launch plan
   int tpb = 512;
-  if (j->g.NW > tpb) tpb = j->g.NW;
+  if (j->lanes() > tpb) tpb = j->lanes();
   int G = copies_per_item(j, tpb);
   if (G < 1 || item_lds(j, 1) > (size_t)ctx->max_lds)
     return fail(SG_E_UNSUPPORTED, "one copy of L = %d needs more LDS than the device offers", spec->L);
   make_items(j, G, j->works);
   xcd_order(j->works);
-  j->tpb = ((G * j->g.NW + 63) / 64) * 64;
+  j->tpb = ((G * j->lanes() + 63) / 64) * 64;
   j->lds = item_lds(j, G);
   HIPCHK(hipMemcpyAsync(j->at<void>(lay.works), j->works.data(), j->works.size() * sizeof(Work),
                         hipMemcpyHostToDevice, st));
@@ -939,7 +951,7 @@ static int run_pt(sg_job *j, hipStream_t st) {
 
 // own-plan sweep launch of `n` sweeps plus the counter update
 static int launch_own(sg_job *j, int n, hipStream_t st) {
-  HIPCHK(sg::launch_sweep(j->sp.model, j->sp.algo, j->at<Work>(j->lay.works), (int)j->works.size(), j->tpb,
+  HIPCHK(sg::launch_sweep(j->group(), j->sp.algo, j->at<Work>(j->lay.works), (int)j->works.size(), j->tpb,
                           j->lds, n, st));
   return SG_OK;
 }
@@ -1319,7 +1331,8 @@ struct PtTable {
 };
 
 // fused launches of a period: one per (model, algorithm)
-static const int NMODEL = 5, NGROUP = 2 * NMODEL;
+// launch groups: the five models, then the four-lanes-per-wheel Potts kernels
+static const int NMODEL = 7, NGROUP = 2 * NMODEL;
 
 struct sg_batch {
   sg_ctx *ctx;
@@ -1375,12 +1388,13 @@ static void drop_graphs(sg_batch *b) {
 static double idle_fraction(const sg_batch *b, int tpb) {
   double used = 0, total = 0;
   for (sg_job *j : b->jobs) {
-    if (j->g.NW > tpb) return 2.0;
+    if (j->lanes() > tpb) return 2.0;
     const int G = copies_per_item(j, tpb);
     if (G < 1) return 2.0;
     const double items = std::ceil((double)j->C / G);
-    used += (double)j->C * j->g.NW * j->g.RHO;  // weight by draws per sweep per lane
-    total += items * ((model_tpb(j->sp.model, tpb) + 63) / 64 * 64) * j->g.RHO;
+    const double per_lane = (double)j->g.RHO / wheel_lanes(j->sp.model, j->L);  // draws per lane, in L/2
+    used += (double)j->C * j->lanes() * per_lane;
+    total += items * ((model_tpb(j->sp.model, tpb) + 63) / 64 * 64) * per_lane;
   }
   return total > 0 ? 1.0 - used / total : 0.0;
 }
@@ -1411,16 +1425,16 @@ static int plan_items(const sg_batch *b, int &tpb_out, std::vector<Work> (&items
     if (tpb <= 0) return fail(SG_E_UNSUPPORTED, "no block size fits the batch");
   }
   for (sg_job *j : b->jobs)
-    if (j->g.NW > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
+    if (j->lanes() > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
   for (auto &a : items)
     for (auto &v : a) v.clear();
   for (auto &a : lds)
     for (auto &l : a) l = 0;
   for (sg_job *j : b->jobs) {
     const int G = copies_per_item(j, tpb);
-    size_t &l = lds[j->sp.model][j->sp.algo];
+    size_t &l = lds[j->group()][j->sp.algo];
     l = std::max(l, item_lds(j, G));
-    make_items(j, G, items[j->sp.model][j->sp.algo]);
+    make_items(j, G, items[j->group()][j->sp.algo]);
   }
   // longest items first: the launch tail is then made of short items
   for (auto &a : items)

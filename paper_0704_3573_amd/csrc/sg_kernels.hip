@@ -437,6 +437,29 @@ struct Drive {
   int kmod;
 };
 
+// Kernels whose wheels are served by several lanes (K::QUAD) load and store
+// their register rings themselves; the others use ring_load / ring_store.
+template <class K, class = void>
+struct is_quad : std::false_type {};
+template <class K>
+struct is_quad<K, std::void_t<decltype(K::QUAD)>> : std::bool_constant<K::QUAD> {};
+
+template <class K>
+DEV void ring_in(const K &k, uint32_t (&ring)[K::M], const Drive &d) {
+  if constexpr (is_quad<K>::value)
+    k.load_ring(ring, d);
+  else
+    ring_load<K::M>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+}
+
+template <class K, int LAST>
+DEV void ring_out(const K &k, const uint32_t (&ring)[K::M], const Drive &d) {
+  if constexpr (is_quad<K>::value)
+    k.template store_ring<LAST>(ring, d);
+  else
+    ring_store<K::M, LAST>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+}
+
 template <class K, int VI>
 DEV bool drive_chain(K &k, uint32_t (&ring)[K::M], Drive &d) {
   // every lane of a wave that holds at least one wheel runs the block (lanes
@@ -448,7 +471,7 @@ DEV bool drive_chain(K &k, uint32_t (&ring)[K::M], Drive &d) {
     __syncthreads();
     d.p ^= 1;
     if (d.p == 0 && ++d.s == d.nsweeps) {
-      if (d.active) ring_store<K::M, (VI + 1) * K::B - 1>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+      if (d.active) ring_out<K, (VI + 1) * K::B - 1>(k, ring, d);
       return true;
     }
   }
@@ -486,7 +509,7 @@ DEV void drive(K &k, Drive &d) {
     return;
   }
   uint32_t ring[K::M];
-  if (d.active) ring_load<K::M>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+  if (d.active) ring_in(k, ring, d);
   // wait for the ring once here: with loads still in flight on entry, the
   // sweep loop would carry a vector-memory wait in front of every draw
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
@@ -496,10 +519,10 @@ DEV void drive(K &k, Drive &d) {
         drive_half<K, 0>(k, ring, p);
         __syncthreads();
       }
-    if (d.active) ring_store<K::M, K::M - 1>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+    if (d.active) ring_out<K, K::M - 1>(k, ring, d);
   } else if constexpr ((2 * K::NBLK) % K::V == 0) {
     for (int s = 0; s < d.nsweeps; s++) drive_sweep<K, 0>(k, ring);
-    if (d.active) ring_store<K::M, K::M - 1>(ring, d.rwh, d.widx, d.wstride, d.kmod);
+    if (d.active) ring_out<K, K::M - 1>(k, ring, d);
   } else {
     d.p = 0;
     d.blk = 0;
@@ -1243,23 +1266,11 @@ struct PottsK {
   }
 };
 
-template <int L, bool GLASSY>
-DEV void potts_run(const Work &w, uint32_t *lds) {
-  using G = GC<L>;
-  constexpr int N3 = L * L * L;
-  constexpr int CW = potts_lds_copy(L) / 4;  // LDS words per copy
-  constexpr int GW = G::RHO * L * L / 4;     // HBM words per row group
-  const int t = threadIdx.x;
-  const int nthr = blockDim.x;
-  const int lanes = w.ncopies * G::NW;
-  const bool active = t < lanes;
-  uint32_t *tab = lds;                                  // [64][7] rotation bases
-  uint32_t *cp = lds + POTTS_TAB_WORDS;                 // [ncopies][CW] spins
-  uint32_t *Wt = cp + w.ncopies * CW;                   // [ncopies][POTTS_W_WORDS]
-  int *Hcnt = (int *)(Wt + w.ncopies * POTTS_W_WORDS);  // [ncopies]
-  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);       // RHO L^2 bytes if NW % 64 != 0
-  const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
-  const uint32_t sbase = (uint32_t)w.copy0 * N3;
+// LDS table of the Potts kernels: the vote words of the 24 permutations
+// (glassy model) or the rotation bases of the 64 coupling patterns (+-J).
+template <bool GLASSY>
+DEV void potts_tables(uint32_t *tab) {
+  const int t = threadIdx.x, nthr = blockDim.x;
   if constexpr (GLASSY) {
     // vote words of the 24 permutations (lexicographic order): pi, then pi^-1
     for (int i = t; i < 48; i += nthr) {
@@ -1284,6 +1295,26 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
       tab[i] = d < 6 && ((pat >> d) & 1) ? 0x04040400u : 4u;
     }
   }
+}
+
+template <int L, bool GLASSY>
+DEV void potts_run(const Work &w, uint32_t *lds) {
+  using G = GC<L>;
+  constexpr int N3 = L * L * L;
+  constexpr int CW = potts_lds_copy(L) / 4;  // LDS words per copy
+  constexpr int GW = G::RHO * L * L / 4;     // HBM words per row group
+  const int t = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int lanes = w.ncopies * G::NW;
+  const bool active = t < lanes;
+  uint32_t *tab = lds;                                  // [64][7] rotation bases
+  uint32_t *cp = lds + POTTS_TAB_WORDS;                 // [ncopies][CW] spins
+  uint32_t *Wt = cp + w.ncopies * CW;                   // [ncopies][POTTS_W_WORDS]
+  int *Hcnt = (int *)(Wt + w.ncopies * POTTS_W_WORDS);  // [ncopies]
+  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);       // RHO L^2 bytes if NW % 64 != 0
+  const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
+  const uint32_t sbase = (uint32_t)w.copy0 * N3;
+  potts_tables<GLASSY>(tab);
   for (int i = t; i < w.ncopies * POTTS_W_WORDS; i += nthr) {
     const int c = w.copy0 + i / POTTS_W_WORDS;
     Wt[i] = w.thr[w.temp_of_slot[c] * THR_WORDS + i % POTTS_W_WORDS];
@@ -1337,15 +1368,348 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
   for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = -(int64_t)Hcnt[i];
 }
 
+// ---------------------------------------------------------------------------
+// q = 4 Potts heat bath (+-J glass and glassy model) with four lanes per
+// wheel.  Sec. 3.3 lets one wheel emit many numbers per clock, because the
+// recurrence I(k) = I(k-24) + I(k-55) reaches back at least 24 outputs: any
+// 24 consecutive outputs can be formed at once.  Here the four lanes of a
+// quad share a wheel: lane l forms the outputs k = k0 + 4 s + l (step s),
+// so the numbers, their order and every site's number are those of the
+// one-lane kernel.  Per step and lane:
+//   I(k-24) is the lane's own output of step s - 6;
+//   I(k-55) is the output of step s - 14 of lane l + 1 (step s - 13 of lane
+//     0 for l = 3), I(k-61) that of step s - 15 of lane l - 1 (step s - 16
+//     of lane 3 for l = 0): each lane exposes the right word (one bit-select
+//     on lane-constant masks) and the reader takes it with a DPP quad
+//     permutation;
+// so each lane keeps its outputs of steps s - 1 .. s - 16 in registers (a
+// ring of RL >= 16 words, static indices) and the site it updates is the
+// draw's: within a block of B draws (as in the one-lane kernel) lane l
+// updates draws l, l + 4, l + 8, ...  Everything else (fields, weights,
+// multiply, selection, the LDS layout and the HBM state) is the one-lane
+// kernel's.  Used for L = 8, 16, 24, 32 (L/2 a multiple of 4, a copy's
+// 4 NW lanes within one workgroup; potts_wheel_lanes).
+// ---------------------------------------------------------------------------
+template <int L, bool GLASSY>
+struct PottsQK {
+  using G = GC<L>;
+  static constexpr bool QUAD = true;
+  static constexpr int S = 4;
+  static_assert(G::B % S == 0 && G::H % S == 0, "four lanes per wheel need B, L/2 multiples of 4");
+  static constexpr int B = G::B / S;                 // steps per block (draws per lane)
+  static constexpr int RL = ((16 + B - 1) / B) * B;  // register ring of a lane (steps)
+  static constexpr int M = RL, V = RL / B;           // as the drive expects them
+  static constexpr int NBLK = G::NBLK, H = G::H, RPB = G::RPB, RHO = G::RHO, NW = G::NW;
+  static constexpr int MS = G::M;                    // HBM ring slots of a wheel
+  static constexpr int BQ = GLASSY ? B : potts_bq(L);  // coupling words per block and lane
+  uint8_t *sp;          // LDS bytes of the lane's copy, [y][x][z] (rows at row(y)), 8 sigma
+  uint8_t *wp;          // where the lane stores its new spins: sp, or the dummy region
+  const uint32_t *tab;  // LDS table: rotation bases (+-J) or vote words (glassy)
+  const uint8_t *Wb;    // LDS weight table of the lane's temperature
+  rsrc_t rJ;            // coupling words of the job
+  uint32_t voff;        // byte offset of the lane's coupling words
+  bool active;
+  int z, zp, zm, g, sub;  // wheel plane, row group and the lane's place in its quad
+  uint32_t m0, m3;        // all ones in lanes with sub == 0 (== 3)
+  uint32_t sh;            // 8 sub: the lane's byte of a +-J pattern word
+  int kmod0, kmod1;       // first draw of the launch (and of the next one) mod MS
+  uint32_t nextpat[BQ];
+
+  static DEV int row(int y) { return y * L * L + (y / RHO) * 2 * L; }
+
+  DEV void fetch(int p, int blk) {
+    if constexpr (GLASSY) {
+      // one word per draw: the lane's draws 4 i + sub of the block
+      const uint32_t s0 = __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * G::B) * NW * 4u);
+#pragma unroll
+      for (int i = 0; i < B; i++) nextpat[i] = bload(rJ, voff, s0 + (uint32_t)(4 * i) * NW * 4u);
+    } else {
+      // four draws per word (the lane uses byte sub of each)
+      const uint32_t s0 = __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * BQ) * NW * 4u);
+#pragma unroll
+      for (int q = 0; q < BQ; q++) nextpat[q] = bload(rJ, voff, s0 + (uint32_t)q * NW * 4u);
+    }
+  }
+
+  // HBM slot of the output at draw offset `off` from the launch's first draw
+  DEV uint32_t slot_of(int kmod, int off) const { return (uint32_t)((kmod + 4 * MS + off) % MS); }
+
+  // outputs of steps -16 .. -1 (draws k0 - 64 + 4 i + sub; the one at
+  // k0 - 64 + sub is dead for sub < 3 and never read)
+  DEV void load_ring(uint32_t (&ring)[RL], const Drive &d) const {
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const int st = i - 16;
+      ring[(st + RL) % RL] = bload(d.rwh, d.widx + slot_of(kmod0, 4 * st + sub) * d.wstride);
+    }
+  }
+
+  // LAST: the register of the launch's last step; the live words are the
+  // outputs of the last 15 steps and, for sub == 3, the 16th
+  template <int LAST>
+  DEV void store_ring(const uint32_t (&ring)[RL], const Drive &d) const {
+#pragma unroll
+    for (int ds = 0; ds < 16; ds++) {
+      const int i = (LAST - ds + RL) % RL;
+      if (ds < 15 || sub == 3)
+        bstore(d.rwh, ring[i], d.widx + slot_of(kmod1, -4 - 4 * ds + sub) * d.wstride);
+    }
+  }
+
+  template <int VI>
+  DEV void block(uint32_t (&ring)[M], int p, int blk) {
+    uint32_t pat[BQ];
+#pragma unroll
+    for (int q = 0; q < BQ; q++) pat[q] = nextpat[q];
+    if (blk + 1 < NBLK)
+      fetch(p, blk + 1);
+    else
+      fetch(p ^ 1, 0);
+    rows<VI>(ring, pat, p, g * RHO + blk * RPB, sp, wp, tab, Wb);
+  }
+
+  template <int VI>
+  DEV void rows(uint32_t (&ring)[M], const uint32_t (&pat)[BQ], int p, int y0,
+                const uint8_t *__restrict__ rd, uint8_t *__restrict__ wr,
+                const uint32_t *__restrict__ tb, const uint8_t *__restrict__ wt) const {
+    // per row of the block: the lane's first site (j = sub), the periodic x
+    // neighbour at the row's ends, and the y neighbours' rows
+    int base[RPB], bxw[RPB], byp[RPB], bym[RPB];
+#pragma unroll
+    for (int rr = 0; rr < RPB; rr++) {
+      const int y = y0 + rr;
+      const int e = (p + y + z) & 1;
+      const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+      const int lane = 2 * sub * L;
+      base[rr] = row(y) + e * L + z + lane;
+      bxw[rr] = row(y) + z + (e ? 0 : (L - 1) * L);
+      byp[rr] = row(yp) + e * L + z + lane;
+      bym[rr] = row(ym) + e * L + z + lane;
+    }
+    const int dzp = zp - z, dzm = zm - z;
+    uint32_t nb[B][6], rb[B][6], w[B][4];
+
+    // step i: draw 4 i + sub of the block, row rr = 4 i / H, in-row index
+    // j = 4 i mod H + sub (H is a multiple of 4)
+    auto request_site = [&](int i) {
+      const int rr = 4 * i / H, jb = 4 * i - rr * H, o = 2 * jb * L;
+      if constexpr (GLASSY) {
+#pragma unroll
+        for (int d = 0; d < 6; d++) rb[i][d] = tb[(d & 1) * 24 + ((pat[i] >> (5 * d)) & 31u)];
+      } else {
+        const uint32_t *r6 = tb + POTTS_TAB_STRIDE * ((pat[i] >> sh) & 0xFFu);
+#pragma unroll
+        for (int d = 0; d < 6; d++) rb[i][d] = r6[d];
+      }
+      const int c = base[rr] + o;
+      const int xp = jb == H - 4 ? (int)bfi(m3, (uint32_t)bxw[rr], (uint32_t)(c + L)) : c + L;
+      const int xm = jb == 0 ? (int)bfi(m0, (uint32_t)bxw[rr], (uint32_t)(c - L)) : c - L;
+      nb[i][0] = rd[xp];
+      nb[i][1] = rd[xm];
+      nb[i][2] = rd[byp[rr] + o];
+      nb[i][3] = rd[bym[rr] + o];
+      nb[i][4] = rd[c + dzp];
+      nb[i][5] = rd[c + dzm];
+    };
+    auto request_weights = [&](int i) {
+      uint32_t c, c0, c1, c2, c3;
+      if constexpr (GLASSY) {
+        c = 0;
+#pragma unroll
+        for (int d = 0; d < 6; d++) c += 4u << ((rb[i][d] >> nb[i][d]) & 31u);
+        c0 = c & 0xFFu, c1 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c3 = c >> 24;
+      } else {
+        c = __builtin_rotateright32(rb[i][0], nb[i][0]) + __builtin_rotateright32(rb[i][1], nb[i][1]) +
+            __builtin_rotateright32(rb[i][2], nb[i][2]) + __builtin_rotateright32(rb[i][3], nb[i][3]) +
+            __builtin_rotateright32(rb[i][4], nb[i][4]) + __builtin_rotateright32(rb[i][5], nb[i][5]);
+        c0 = c & 0xFFu, c3 = (c >> 8) & 0xFFu, c2 = (c >> 16) & 0xFFu, c1 = c >> 24;
+      }
+      const uint8_t *wm = wt + max(max(c0, c3), max(c2, c1));
+      w[i][0] = *(const uint32_t *)(wm - c0);
+      w[i][1] = *(const uint32_t *)(wm - c1);
+      w[i][2] = *(const uint32_t *)(wm - c2);
+      w[i][3] = *(const uint32_t *)(wm - c3);
+    };
+    auto finish_site = [&](int i) {
+      const int rr = 4 * i / H, jb = 4 * i - rr * H;
+      const int st = VI * B + i;  // register of this step (static)
+      const uint32_t e55 = bfi(m0, ring[(st + RL - 13) % RL], ring[(st + RL - 14) % RL]);
+      const uint32_t e61 = bfi(m3, ring[(st + RL - 16) % RL], ring[(st + RL - 15) % RL]);
+      // quad permutations: lane l reads lane (l + 1) & 3, resp. (l + 3) & 3
+      const uint32_t x55 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e55, 0x39, 0xF, 0xF, false);
+      const uint32_t x61 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e61, 0x93, 0xF, 0xF, false);
+      ring[st % RL] = ring[(st + RL - 6) % RL] + x55;
+      const uint32_t r = ring[st % RL] ^ x61;
+      const uint32_t C1 = w[i][0] + w[i][1], C2 = C1 + w[i][2];
+      const uint32_t t = __umulhi(r, C2 + w[i][3]);
+      const uint32_t nt = ~t;
+      const uint32_t v = (((w[i][0] + nt) >> 31) + ((C1 + nt) >> 31) + ((C2 + nt) >> 31)) << 3;
+      wr[base[rr] + 2 * jb * L] = (uint8_t)v;
+    };
+
+    request_site(0);
+    if constexpr (B > 1) request_site(1);
+    __builtin_amdgcn_sched_barrier(0);
+    request_weights(0);
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (i + 2 < B) request_site(i + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      if (i + 1 < B) request_weights(i + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      finish_site(i);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // sum over the lane's colour-0 sites of h_{sigma_i} = sum_j J_ij delta(sigma_i, sigma_j)
+  DEV int lane_bond_sum() const {
+    int hsum = 0;
+    for (int blk = 0; blk < NBLK; blk++) {
+      const int y0 = g * RHO + blk * RPB;
+      for (int i = 0; i < B; i++) {
+        const int kb = 4 * i + sub, rr = kb / H, j = kb - rr * H;
+        const int y = y0 + rr;
+        const int e = (y + z) & 1;
+        const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+        const int c = row(y) + (2 * j + e) * L + z;
+        const int xpi = (2 * j + e + 1) % L, xmi = (2 * j + e + L - 1) % L;
+        const int nb[6] = {row(y) + xpi * L + z, row(y) + xmi * L + z,
+                           row(yp) + (2 * j + e) * L + z, row(ym) + (2 * j + e) * L + z,
+                           c - z + zp, c - z + zm};
+        const uint32_t si = sp[c];
+        if constexpr (GLASSY) {
+          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * G::B + 4 * i) * NW) * 4u);
+          for (int d = 0; d < 6; d++) {
+            const uint32_t vote = tab[(d & 1) * 24 + ((pw >> (5 * d)) & 31u)];
+            hsum += ((vote >> sp[nb[d]]) & 31u) == si;
+          }
+        } else {
+          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * BQ + i) * NW) * 4u);
+          const uint32_t pt = (pw >> sh) & 0xFFu;
+          for (int d = 0; d < 6; d++)
+            if (sp[nb[d]] == si) hsum += ((pt >> d) & 1u) ? -1 : 1;
+        }
+      }
+    }
+    return hsum;
+  }
+};
+
+template <int L, bool GLASSY>
+DEV void potts_quad_run(const Work &w, uint32_t *lds) {
+  using G = GC<L>;
+  using K = PottsQK<L, GLASSY>;
+  constexpr int N3 = L * L * L;
+  constexpr int CW = potts_lds_copy(L) / 4;  // LDS words per copy
+  constexpr int GW = G::RHO * L * L / 4;     // HBM words per row group
+  constexpr int LPC = 4 * G::NW;             // lanes per copy
+  const int t = threadIdx.x;
+  const int nthr = blockDim.x;
+  const bool active = t < w.ncopies * LPC;
+  uint32_t *tab = lds;
+  uint32_t *cp = lds + POTTS_TAB_WORDS;
+  uint32_t *Wt = cp + w.ncopies * CW;
+  int *Hcnt = (int *)(Wt + w.ncopies * POTTS_W_WORDS);
+  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);  // RHO L^2 bytes if LPC % 64 != 0
+  const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
+  const uint32_t sbase = (uint32_t)w.copy0 * N3;
+  potts_tables<GLASSY>(tab);
+  for (int i = t; i < w.ncopies * POTTS_W_WORDS; i += nthr) {
+    const int c = w.copy0 + i / POTTS_W_WORDS;
+    Wt[i] = w.thr[w.temp_of_slot[c] * THR_WORDS + i % POTTS_W_WORDS];
+  }
+  stage_words<8>(
+      w.ncopies * (N3 / 4), [&](int i) { return bload(rsp, i * 4, sbase); },
+      [&](int i, uint32_t v) {
+        const int c = i / (N3 / 4), u = i - c * (N3 / 4);
+        cp[c * CW + u + (u / GW) * L / 2] = v;
+      });
+  for (int i = t; i < w.ncopies; i += nthr) Hcnt[i] = 0;
+
+  // lanes without a wheel (whole quads) run wheel (z = (t / 4) mod L, row
+  // group 0) of the first copy and store into the dummy region
+  K k;
+  const int cl = active ? t / LPC : 0;
+  const int rem = active ? t - cl * LPC : 4 * ((t >> 2) % L) + (t & 3);
+  const int wl = rem >> 2;
+  const int copy = w.copy0 + cl;
+  k.sub = t & 3;
+  k.m0 = k.sub == 0 ? ~0u : 0u;
+  k.m3 = k.sub == 3 ? ~0u : 0u;
+  k.sh = 8u * (uint32_t)k.sub;
+  k.sp = (uint8_t *)(cp + cl * CW);
+  k.wp = active ? k.sp : dummy;
+  k.tab = tab;
+  k.Wb = (const uint8_t *)(Wt + cl * POTTS_W_WORDS);
+  k.active = active;
+  k.g = wl / L;
+  k.z = wl - k.g * L;
+  k.zp = k.z + 1 == L ? 0 : k.z + 1;
+  k.zm = k.z == 0 ? L - 1 : k.z - 1;
+  k.rJ = make_rsrc(w.J, w.J_bytes);
+  k.voff = ((uint32_t)(copy / w.RK) * (GLASSY ? gpotts_js(L) : potts_js(L)) + wl) * 4u;
+  if constexpr (GLASSY) k.voff += (uint32_t)(k.sub * G::NW) * 4u;
+  const uint64_t per_sweep = (uint64_t)G::RHO * L;
+  const uint64_t done = *w.done;
+  k.kmod0 = (int)__builtin_amdgcn_readfirstlane((uint32_t)((done * per_sweep) % G::M));
+  k.kmod1 = (int)__builtin_amdgcn_readfirstlane(
+      (uint32_t)(((done + (uint64_t)max(w.nsweeps_cap, 0)) * per_sweep) % G::M));
+
+  Drive d;
+  d.nsweeps = w.nsweeps_cap;
+  d.active = active;
+  d.rwh = make_rsrc(w.wheels, w.wheels_bytes);
+  d.wstride = (uint32_t)w.C * G::NW * 4u;
+  d.widx = ((uint32_t)copy * G::NW + wl) * 4u;
+  d.kmod = k.kmod0;
+  __syncthreads();
+  k.fetch(0, 0);
+  drive(k, d);
+
+  if (active) atomicAdd(&Hcnt[cl], k.lane_bond_sum());
+  __syncthreads();
+  if (w.nsweeps_cap > 0)
+    for (int i = t; i < w.ncopies * (N3 / 4); i += nthr) {
+      const int c = i / (N3 / 4), u = i - c * (N3 / 4);
+      bstore(rsp, cp[c * CW + u + (u / GW) * L / 2], i * 4, sbase);
+    }
+  for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = -(int64_t)Hcnt[i];
+}
+
+template <bool GLASSY>
+DEV void potts_quad_dispatch(const Work &w, uint32_t *lds) {
+  switch (w.L) {
+    case 8: potts_quad_run<8, GLASSY>(w, lds); break;
+    case 16: potts_quad_run<16, GLASSY>(w, lds); break;
+    case 24: potts_quad_run<24, GLASSY>(w, lds); break;
+    case 32: potts_quad_run<32, GLASSY>(w, lds); break;
+    default: break;
+  }
+}
+
+__global__ __launch_bounds__(POTTS_MAX_TPB) void potts_quad_kernel(const Work *__restrict__ works,
+                                                                   int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  potts_quad_dispatch<false>(w, lds);
+}
+
+__global__ __launch_bounds__(POTTS_MAX_TPB) void gpotts_quad_kernel(const Work *__restrict__ works,
+                                                                    int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  potts_quad_dispatch<true>(w, lds);
+}
+
 template <bool GLASSY>
 DEV void potts_dispatch(const Work &w, uint32_t *lds) {
   switch (w.L) {
     case 2: potts_run<2, GLASSY>(w, lds); break;
     case 4: potts_run<4, GLASSY>(w, lds); break;
-    case 8: potts_run<8, GLASSY>(w, lds); break;
-    case 16: potts_run<16, GLASSY>(w, lds); break;
-    case 24: potts_run<24, GLASSY>(w, lds); break;
-    case 32: potts_run<32, GLASSY>(w, lds); break;
     case 40: potts_run<40, GLASSY>(w, lds); break;
     case 48: potts_run<48, GLASSY>(w, lds); break;
     default: break;
@@ -1914,7 +2278,11 @@ hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st) {
 hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, int tpb,
                         size_t lds, int nsweeps, hipStream_t st) {
   if (nworks <= 0) return hipSuccess;
-  if (model == 4)
+  if (model == LAUNCH_POTTS_QUAD)
+    hipLaunchKernelGGL(potts_quad_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == LAUNCH_GPOTTS_QUAD)
+    hipLaunchKernelGGL(gpotts_quad_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == 4)
     hipLaunchKernelGGL(gpotts4_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == 3 && algo == 0)
     hipLaunchKernelGGL(gen_sweep_kernel<0>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
@@ -1936,6 +2304,12 @@ hipError_t set_max_lds(int bytes) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)gpotts_sweep_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)potts_quad_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)gpotts_quad_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)gpotts4_sweep_kernel,
