@@ -98,33 +98,64 @@ def build_c3(ctx, B, inputs, algo=None):
     return jobs
 
 
-def serving_bench(ctx, n_jobs, seed=5):
-    """Continuous-batching request loop: calibrate the saturated capacity with a
-    burst, then serve a Poisson stream at 1.2x that rate.  Jobs: EA Ising
-    (Metropolis) or q=4 Potts (heat bath) with probability 1/2, L uniform in
-    {8,16,24,32,48}, T uniform in [0.7, 1.6], 2 replicas, sweeps log-uniform in
-    10^2.5 .. 10^4 (the 10^3 .. 10^5 range scaled down to fit a short run)."""
+def c5_mean_updates_per_job():
+    """Mean site updates of a job of the serving workload: 2 replicas x L^3
+    (L uniform in {8,16,24,32,48}) x 10^U sweeps (U uniform in [3, 5])."""
+    import math
+    e_sites = 2 * sum(L ** 3 for L in (8, 16, 24, 32, 48)) / 5
+    e_sweeps = (10 ** 5 - 10 ** 3) / (2 * math.log(10))
+    return e_sites * e_sweeps
+
+
+def serving_bench(ctx, n_jobs=2000, cap_s=60.0, calib_s=5.0, seed=5):
+    """Continuous-batching request loop on the serving workload: Poisson jobs,
+    EA Ising (Metropolis) or q=4 Potts (heat bath) with probability 1/2, L
+    uniform in {8,16,24,32,48}, T uniform in [0.7, 1.6], 2 replicas, sweeps
+    floor(10^U[3,5]), job seed 5000 + j, arrivals seed 5, admitted by HBM
+    budget and slots.  The saturated capacity is measured first: 512 jobs of
+    the same distribution arrive at once and run for calib_s seconds of wall
+    clock (while most are still resident; the burst's last, longest jobs
+    would otherwise run nearly alone); the stream then arrives at 1.2x that
+    capacity (jobs/s = updates/ns / mean updates per job).  The stream (n_jobs jobs, about
+    1.4e9 updates each) is far longer than a measurement, so it runs for
+    cap_s seconds of wall clock: jobs arrived, started and completed,
+    latency percentiles of the completed ones, all updates performed per ns,
+    and the share of the wall clock with a period on the device."""
     from paper_0704_3573_amd import serving
-    lo, hi = 2.5, 4.0
+    mean_upd = c5_mean_updates_per_job()
     be = serving.DeviceBackend(ctx)
-    burst = serving.poisson_stream(max(16, n_jobs // 3), rate=0.0, seed=seed + 1, sweeps_lo=lo,
-                                   sweeps_hi=hi, seed0=9000)
-    srv = serving.Server(be, hbm_budget=64 << 30, max_slots=512, period=500)
+    burst = serving.poisson_stream(512, rate=0.0, seed=seed + 1, seed0=9000)
+    srv = serving.Server(be, hbm_budget=64 << 30, max_slots=512)
     t = time.perf_counter()
-    srv.serve(burst)
-    cap = len(burst) / (time.perf_counter() - t)
-    rate = 1.2 * cap
-    reqs = serving.poisson_stream(n_jobs, rate=rate, seed=seed, sweeps_lo=lo, sweeps_hi=hi)
-    srv = serving.Server(be, hbm_budget=64 << 30, max_slots=512, period=500)
-    t = time.perf_counter()
-    done = srv.serve(reqs)
+    srv.serve(burst, cap_s=calib_s)
     wall = time.perf_counter() - t
-    out = serving.summary(done, wall)
-    out.update({"capacity_jobs_per_s": round(cap, 3), "arrival_rate_per_s": round(rate, 3),
-                "peak_resident_jobs": srv.peak_slots, "periods": srv.periods,
+    cap_ups = srv.updates_done() / (wall * 1e9)
+    cap_jobs = cap_ups * 1e9 / mean_upd
+    rate = 1.2 * cap_jobs
+    log(f"[bench] serving capacity: {cap_ups:.1f} updates/ns in {wall:.1f}s "
+        f"({srv.periods} periods, {len(srv.done)} burst jobs done) -> {cap_jobs:.3f} jobs/s")
+    reqs = serving.poisson_stream(n_jobs, rate=rate, seed=seed)
+    srv = serving.Server(be, hbm_budget=64 << 30, max_slots=512)
+    be.busy = []
+    t = time.perf_counter()
+    done = srv.serve(reqs, cap_s=cap_s)
+    wall = time.perf_counter() - t
+    busy_s = be.busy_seconds()
+    be.close()
+    arrived = sum(1 for r in reqs if r.arrival <= wall)
+    out = serving.summary(done, wall, updates=srv.updates_done())
+    out.update({"capacity_updates_per_ns": round(cap_ups, 3),
+                "capacity_jobs_per_s": round(cap_jobs, 4), "arrival_rate_per_s": round(rate, 4),
+                "cap_s": cap_s, "jobs_in_stream": n_jobs, "jobs_arrived": arrived,
+                "jobs_started": arrived - len(srv.pending) - len(srv.creating),
+                "jobs_completed": len(done), "peak_resident_jobs": srv.peak_slots,
+                "periods": srv.periods, "device_busy_share": round(busy_s / wall, 4),
+                "mean_updates_per_job": round(mean_upd, -6),
+                "latency_note": "percentiles over the jobs completed within the cap",
                 "workload": f"{n_jobs} Poisson jobs, Ising-Metropolis/Potts-heat-bath 1:1, "
-                            f"L in {{8,16,24,32,48}}, T~U[0.7,1.6], sweeps 10^U[{lo},{hi}], "
-                            f"2 replicas, HBM budget 64 GiB, 512 slots"})
+                            "L in {8,16,24,32,48}, T~U[0.7,1.6], sweeps 10^U[3,5], 2 replicas, "
+                            "HBM budget 64 GiB, 512 slots, rate 1.2x the measured capacity, "
+                            f"{cap_s:.0f} s wall-clock cap"})
     return out
 
 
@@ -360,8 +391,12 @@ def main():
                     help="timed plain steps (100 sweeps + measurement each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--serving-jobs", type=int, default=120,
+    ap.add_argument("--serving-jobs", type=int, default=2000,
                     help="jobs in the serving stream (0 = skip the serving measurement)")
+    ap.add_argument("--serving-cap", type=float, default=60.0,
+                    help="wall-clock seconds the serving stream runs for")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="time only the serving workload (profiling runs)")
     ap.add_argument("--potts-sweeps", type=int, default=200,
                     help="sweeps per timed Potts period (0 = skip the Potts measurement)")
     ap.add_argument("--gen-sweeps", type=int, default=50,
@@ -406,6 +441,10 @@ def main():
         return
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
+
+    if args.serving_only:
+        log(f"[bench] serving only: {serving_bench(ctx, args.serving_jobs, args.serving_cap)}")
+        return
 
     if args.gen_only:
         log(f"[bench] Ising-like only: {ising_like(ctx, B, inputs, np, torch, stream, args.gen_sweeps)}")
@@ -514,7 +553,7 @@ def main():
 
     serving_stats = None
     if args.serving_jobs > 0:
-        serving_stats = serving_bench(ctx, args.serving_jobs)
+        serving_stats = serving_bench(ctx, args.serving_jobs, args.serving_cap)
         log(f"[bench] serving: {serving_stats}")
 
     cpu = None

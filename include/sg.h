@@ -270,6 +270,12 @@ int sg_batch_set_block(sg_batch *b, int32_t threads);
  * This lets jobs of different lengths share one launch and stop exactly. */
 int sg_batch_set_budget(sg_batch *b, sg_job *job, uint64_t sweeps);
 int sg_batch_get_budget(sg_batch *b, sg_job *job, uint64_t *sweeps);
+/* Per-run cap of a job in the batch: every run of n sweeps advances the job
+ * by min(n, cap, budget) (UINT64_MAX = no cap, the default); the cap is not
+ * consumed.  Jobs whose sweeps cost different device time can so share one
+ * launch for the same time each (the serving loop sets caps from its cost
+ * estimate).  For jobs without parallel tempering. */
+int sg_batch_set_period_cap(sg_batch *b, sg_job *job, uint64_t sweeps);
 /* Advance every job of the batch by n sweeps (sec. 3.1 / 3.3 / 2.2 as
  * sg_job_sweep, parallel tempering included).  After membership changes the
  * call first waits for the work already enqueued on `stream`. */

@@ -32,6 +32,7 @@ EXPORTS = (
     "sg_batch_set_timing", "sg_batch_sweep_ms", "sg_batch_set_budget", "sg_batch_get_budget",
     "sg_batch_destroy", "sg_generate", "sg_threshold_row", "sg_pt_factors", "sg_job_sweep_beta",
     "sg_job_checkpoint_bytes", "sg_job_checkpoint", "sg_job_restore", "sg_batch_run_static",
+    "sg_batch_set_period_cap",
 )
 
 
@@ -98,6 +99,7 @@ def lib():
         L.sg_batch_sweep_ms.argtypes = [vp, C.POINTER(C.c_float)]
         L.sg_batch_set_budget.argtypes = [vp, vp, u64]
         L.sg_batch_get_budget.argtypes = [vp, vp, C.POINTER(u64)]
+        L.sg_batch_set_period_cap.argtypes = [vp, vp, u64]
         L.sg_batch_destroy.argtypes = [vp]
         for n in EXPORTS:
             if n not in ("sg_last_error", "sg_wheels_per_copy", "sg_model_wheels_per_copy"):
@@ -354,6 +356,9 @@ class Batch:
 
     def set_budget(self, job: Job, sweeps: int):
         _chk(lib().sg_batch_set_budget(self.h, job.h, sweeps))
+
+    def set_period_cap(self, job: Job, sweeps: int):
+        _chk(lib().sg_batch_set_period_cap(self.h, job.h, sweeps))
 
     def budget(self, job: Job) -> int:
         n = C.c_uint64()

@@ -13,6 +13,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sg.h"
@@ -1330,21 +1331,28 @@ struct PtTable {
   int n, kmax;
 };
 
-// fused launches of a period: one per (model, algorithm)
-// launch groups: the five models, then the four-lanes-per-wheel Potts kernels
-static const int NMODEL = 7, NGROUP = 2 * NMODEL;
+// One fused sweep launch of a period: the work items of one kernel (launch
+// group: the five models, then the four-lanes-per-wheel Potts kernels; and
+// algorithm) that run with one block size.  Items much smaller than the
+// batch's block get workgroups of their own size, so that small jobs do not
+// hold a large workgroup's wave slots for a few active lanes.
+struct Launch {
+  int group, algo, tpb;
+  size_t lds;
+  std::vector<Work> items;
+};
 
 struct sg_batch {
   sg_ctx *ctx;
   std::vector<sg_job *> jobs;
   std::vector<uint64_t> budget;  // remaining sweeps per job (UINT64_MAX = unlimited)
+  std::vector<uint64_t> pcap;    // sweeps per run per job (UINT64_MAX = unlimited)
   std::vector<int32_t> run_cap;  // sweeps each job runs in the current period
   int block_req = 0;  // 0 = automatic
   // plan
   bool dirty = true;
-  int tpb = 0;
-  size_t lds[NMODEL][2] = {};  // per (model, algo) launch
-  std::vector<Work> items[NMODEL][2];  // [model][algo]
+  int tpb = 0;                    // the batch's block size
+  std::vector<Launch> launches;   // fused launches of a period
   Work *d_items = nullptr;
   size_t d_items_cap = 0;
   uint64_t **d_done = nullptr;
@@ -1355,8 +1363,9 @@ struct sg_batch {
   std::vector<void *> graph_bufs;  // device buffers referenced by captured graphs
   std::map<std::vector<int>, PtTable> pt_cache;
   hipStream_t cap_stream = nullptr;
-  hipStream_t side[NGROUP - 1] = {};  // parallel branches while capturing
-  hipEvent_t fork = nullptr, join[NGROUP - 1] = {};
+  std::vector<hipStream_t> side;  // parallel branches while capturing
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the fused sweep launch
   bool ran = false;                // periods have been enqueued ...
@@ -1365,8 +1374,7 @@ struct sg_batch {
   // the static device scratch; kept until the next call has waited for the
   // periods of this one)
   struct Static {
-    std::vector<Work> items[NMODEL][2];
-    size_t lds[NMODEL][2] = {};
+    std::vector<Launch> launches;
     int tpb = 0;
     std::vector<uint64_t *> done;
     std::vector<int32_t> cap;
@@ -1408,10 +1416,9 @@ static int wait_enqueued(sg_batch *b) {
   return SG_OK;
 }
 
-// Host part of a plan: block size, work items per (model, algorithm) launch
-// (longest first, XCD-aware order) and each launch's LDS bytes.
-static int plan_items(const sg_batch *b, int &tpb_out, std::vector<Work> (&items)[NMODEL][2],
-                      size_t (&lds)[NMODEL][2]) {
+// Host part of a plan: block size and the fused launches (work items
+// longest first, XCD-aware order; each launch's LDS bytes).
+static int plan_items(const sg_batch *b, int &tpb_out, std::vector<Launch> &launches) {
   int tpb = b->block_req;
   if (tpb <= 0) {
     double best = 3;
@@ -1426,24 +1433,28 @@ static int plan_items(const sg_batch *b, int &tpb_out, std::vector<Work> (&items
   }
   for (sg_job *j : b->jobs)
     if (j->lanes() > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
-  for (auto &a : items)
-    for (auto &v : a) v.clear();
-  for (auto &a : lds)
-    for (auto &l : a) l = 0;
+  std::map<std::tuple<int, int, int>, Launch> by_key;
   for (sg_job *j : b->jobs) {
     const int G = copies_per_item(j, tpb);
-    size_t &l = lds[j->group()][j->sp.algo];
-    l = std::max(l, item_lds(j, G));
-    make_items(j, G, items[j->group()][j->sp.algo]);
+    int blk = model_tpb(j->sp.model, tpb);
+    const int need = (G * j->lanes() + 63) / 64 * 64;
+    if (need <= blk / 2) blk = need;
+    Launch &l = by_key[std::make_tuple(j->group(), j->sp.algo, blk)];
+    l.group = j->group();
+    l.algo = j->sp.algo;
+    l.tpb = blk;
+    l.lds = std::max(l.lds, item_lds(j, G));
+    make_items(j, G, l.items);
   }
-  // longest items first: the launch tail is then made of short items
-  for (auto &a : items)
-    for (auto &v : a)
-      std::stable_sort(v.begin(), v.end(), [](const Work &x, const Work &y) {
-        return work_size(x) > work_size(y);
-      });
-  for (auto &a : items)
-    for (auto &v : a) xcd_order(v);
+  launches.clear();
+  for (auto &kv : by_key) {
+    Launch &l = kv.second;
+    // longest items first: the launch tail is then made of short items
+    std::stable_sort(l.items.begin(), l.items.end(),
+                     [](const Work &x, const Work &y) { return work_size(x) > work_size(y); });
+    xcd_order(l.items);
+    launches.push_back(std::move(l));
+  }
   tpb_out = tpb;
   return SG_OK;
 }
@@ -1453,13 +1464,11 @@ static int plan(sg_batch *b) {
   int rc = wait_enqueued(b);
   if (rc) return rc;
   drop_graphs(b);
-  size_t lds[NMODEL][2];
   int tpb = 0;
-  rc = plan_items(b, tpb, b->items, lds);
+  rc = plan_items(b, tpb, b->launches);
   if (rc) return rc;
   size_t total = 0;
-  for (auto &a : b->items)
-    for (auto &v : a) total += v.size();
+  for (auto &l : b->launches) total += l.items.size();
   if (total > b->d_items_cap) {
     if (b->d_items) HIPCHK(hipFree(b->d_items));
     b->d_items = nullptr;
@@ -1467,11 +1476,20 @@ static int plan(sg_batch *b) {
     b->d_items_cap = total;
   }
   size_t off = 0;
-  for (auto &a : b->items)
-    for (auto &v : a) {
-      if (!v.empty()) HIPCHK(hipMemcpy(b->d_items + off, v.data(), v.size() * sizeof(Work), hipMemcpyHostToDevice));
-      off += v.size();
-    }
+  for (auto &l : b->launches) {
+    if (!l.items.empty())
+      HIPCHK(hipMemcpy(b->d_items + off, l.items.data(), l.items.size() * sizeof(Work), hipMemcpyHostToDevice));
+    off += l.items.size();
+  }
+  // one capture branch per launch beyond the first
+  while (b->side.size() + 1 < b->launches.size()) {
+    hipStream_t sst;
+    hipEvent_t ev;
+    HIPCHK(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking));
+    b->side.push_back(sst);
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->join.push_back(ev);
+  }
   if (b->jobs.size() > b->d_jobs_cap) {
     if (b->d_done) HIPCHK(hipFree(b->d_done));
     if (b->d_cap) HIPCHK(hipFree(b->d_cap));
@@ -1491,15 +1509,16 @@ static int plan(sg_batch *b) {
   }
   b->run_cap.assign(b->jobs.size(), 0x7FFFFFFF);
   b->tpb = tpb;
-  for (int m = 0; m < NMODEL; m++)
-    for (int a = 0; a < 2; a++) b->lds[m][a] = lds[m][a];
   b->dirty = false;
   return SG_OK;
 }
 
+// sweeps job i may still run in one run call (UINT64_MAX = no limit)
+static uint64_t limit(const sg_batch *b, size_t i) { return std::min(b->budget[i], b->pcap[i]); }
+
 static void account(sg_batch *b, uint64_t chunk) {
   for (size_t i = 0; i < b->jobs.size(); i++) {
-    const uint64_t ran = std::min<uint64_t>(chunk, b->budget[i]);
+    const uint64_t ran = std::min<uint64_t>(chunk, limit(b, i));
     b->jobs[i]->sweeps_done += ran;
     if (b->budget[i] != UINT64_MAX) b->budget[i] -= ran;
   }
@@ -1510,8 +1529,8 @@ static int apply_caps(sg_batch *b, uint64_t chunk, hipStream_t st) {
   std::vector<int32_t> cap(b->jobs.size());
   bool changed = false;
   for (size_t i = 0; i < b->jobs.size(); i++) {
-    const uint64_t c = std::min<uint64_t>(chunk, b->budget[i]);
-    cap[i] = b->budget[i] == UINT64_MAX ? 0x7FFFFFFF : (int32_t)c;
+    const uint64_t c = std::min<uint64_t>(chunk, limit(b, i));
+    cap[i] = limit(b, i) == UINT64_MAX ? 0x7FFFFFFF : (int32_t)c;
     if (cap[i] != b->run_cap[i]) changed = true;
   }
   if (!changed) return SG_OK;
@@ -1519,19 +1538,16 @@ static int apply_caps(sg_batch *b, uint64_t chunk, hipStream_t st) {
   int rc = wait_enqueued(b);  // earlier periods may still read the tables
   if (rc) return rc;
   b->run_cap = cap;
-  std::map<const sg_job *, int32_t> by_job;
-  for (size_t i = 0; i < b->jobs.size(); i++) by_job[b->jobs[i]] = cap[i];
+  // items carry the job's arena pointers; find the job by its counter
+  std::map<const uint64_t *, int32_t> by_counter;
+  for (size_t i = 0; i < b->jobs.size(); i++) by_counter[b->jobs[i]->done_ptr()] = cap[i];
   size_t off = 0;
-  for (auto &a : b->items)
-    for (auto &v : a) {
-      for (Work &w : v) {
-        // items carry the job's arena pointers; find the job by its counter
-        for (size_t i = 0; i < b->jobs.size(); i++)
-          if (w.done == b->jobs[i]->done_ptr()) w.nsweeps_cap = cap[i];
-      }
-      if (!v.empty()) HIPCHK(hipMemcpy(b->d_items + off, v.data(), v.size() * sizeof(Work), hipMemcpyHostToDevice));
-      off += v.size();
-    }
+  for (auto &l : b->launches) {
+    for (Work &w : l.items) w.nsweeps_cap = by_counter[w.done];
+    if (!l.items.empty())
+      HIPCHK(hipMemcpy(b->d_items + off, l.items.data(), l.items.size() * sizeof(Work), hipMemcpyHostToDevice));
+    off += l.items.size();
+  }
   HIPCHK(hipMemcpy(b->d_cap, cap.data(), cap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   return SG_OK;
 }
@@ -1542,33 +1558,24 @@ static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs,
   const bool capturing = st == b->cap_stream;
   const bool timed = b->timing && !capturing;
   if (timed) HIPCHK(hipEventRecord(b->ev0, st));
-  // one fused launch per (model, algorithm) group; while capturing, groups
-  // become parallel branches of the graph
-  int groups = 0;
-  for (auto &a : b->items)
-    for (auto &v : a) groups += !v.empty();
-  const bool fork = capturing && groups > 1;
+  // the fused launches; while capturing, they become parallel branches of
+  // the graph
+  const bool fork = capturing && b->launches.size() > 1;
   if (fork) HIPCHK(hipEventRecord(b->fork, st));
-  int g = 0;
-  for (int m = 0; m < NMODEL; m++)
-    for (int a = 0; a < 2; a++) {
-      const auto &v = b->items[m][a];
-      if (!v.empty()) {
-        hipStream_t s = st;
-        if (fork && g > 0) {
-          s = b->side[g - 1];
-          HIPCHK(hipStreamWaitEvent(s, b->fork, 0));
-        }
-        HIPCHK(sg::launch_sweep(m, a, b->d_items + off, (int)v.size(), model_tpb(m, b->tpb),
-                                b->lds[m][a], nsw, s));
-        if (fork && g > 0) {
-          HIPCHK(hipEventRecord(b->join[g - 1], s));
-          HIPCHK(hipStreamWaitEvent(st, b->join[g - 1], 0));
-        }
-        g++;
-      }
-      off += v.size();
+  for (size_t g = 0; g < b->launches.size(); g++) {
+    const Launch &l = b->launches[g];
+    hipStream_t s = st;
+    if (fork && g > 0) {
+      s = b->side[g - 1];
+      HIPCHK(hipStreamWaitEvent(s, b->fork, 0));
     }
+    HIPCHK(sg::launch_sweep(l.group, l.algo, b->d_items + off, (int)l.items.size(), l.tpb, l.lds, nsw, s));
+    if (fork && g > 0) {
+      HIPCHK(hipEventRecord(b->join[g - 1], s));
+      HIPCHK(hipStreamWaitEvent(st, b->join[g - 1], 0));
+    }
+    off += l.items.size();
+  }
   if (timed) HIPCHK(hipEventRecord(b->ev1, st));
   HIPCHK(sg::launch_advance(b->d_done, b->d_cap, (int)b->jobs.size(), nsw, st));
   // parallel tempering of every due job in one fused launch (buffers prepared
@@ -1609,10 +1616,6 @@ static int prepare_pt(sg_batch *b, const std::vector<int> &pt_jobs) {
 static int batch_streams(sg_batch *b) {
   HIPCHK(hipSetDevice(b->ctx->device));
   HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-  for (int i = 0; i < NGROUP - 1; i++) {
-    HIPCHK(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming));
-  }
   HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
   return SG_OK;
 }
@@ -1646,6 +1649,7 @@ int sg_batch_add(sg_batch *b, sg_job *job) {
     return fail(SG_E_STATE, "job is already in the batch");
   b->jobs.push_back(job);
   b->budget.push_back(UINT64_MAX);
+  b->pcap.push_back(UINT64_MAX);
   b->dirty = true;
   return SG_OK;
   GUARD_END
@@ -1657,6 +1661,7 @@ int sg_batch_remove(sg_batch *b, sg_job *job) {
   auto it = std::find(b->jobs.begin(), b->jobs.end(), job);
   if (it == b->jobs.end()) return fail(SG_E_STATE, "job is not in the batch");
   b->budget.erase(b->budget.begin() + (it - b->jobs.begin()));
+  b->pcap.erase(b->pcap.begin() + (it - b->jobs.begin()));
   b->jobs.erase(it);
   b->dirty = true;
   return SG_OK;
@@ -1670,6 +1675,16 @@ int sg_batch_set_budget(sg_batch *b, sg_job *job, uint64_t sweeps) {
   if (sweeps != UINT64_MAX && job->sp.pt_every > 0 && job->K > 1)
     return fail(SG_E_INVALID, "sweep budgets are for jobs without parallel tempering");
   b->budget[it - b->jobs.begin()] = sweeps;
+  return SG_OK;
+}
+
+int sg_batch_set_period_cap(sg_batch *b, sg_job *job, uint64_t sweeps) {
+  if (!b || !job) return fail(SG_E_INVALID, "NULL argument");
+  auto it = std::find(b->jobs.begin(), b->jobs.end(), job);
+  if (it == b->jobs.end()) return fail(SG_E_STATE, "job is not in the batch");
+  if (sweeps != UINT64_MAX && job->sp.pt_every > 0 && job->K > 1)
+    return fail(SG_E_INVALID, "per-run caps are for jobs without parallel tempering");
+  b->pcap[it - b->jobs.begin()] = sweeps;
   return SG_OK;
 }
 
@@ -1783,12 +1798,11 @@ int sg_batch_run_static(sg_batch *b, uint64_t n_sweeps, void *stream) {
   b->last_stream = st;
   b->ran = true;
   auto &T = b->stat;
-  int rc = plan_items(b, T.tpb, T.items, T.lds);
+  int rc = plan_items(b, T.tpb, T.launches);
   if (rc) return rc;
   const size_t nj = b->jobs.size();
   size_t nitems = 0;
-  for (auto &a : T.items)
-    for (auto &v : a) nitems += v.size();
+  for (auto &l : T.launches) nitems += l.items.size();
   T.pt.clear();
   T.pt_first.assign(nj, 0);
   T.pt_count.assign(nj, 0);
@@ -1829,31 +1843,28 @@ int sg_batch_run_static(sg_batch *b, uint64_t n_sweeps, void *stream) {
     // they change, after the periods reading it have finished
     std::vector<int32_t> cap(nj);
     for (size_t i = 0; i < nj; i++)
-      cap[i] = b->budget[i] == UINT64_MAX ? 0x7FFFFFFF : (int32_t)std::min<uint64_t>(chunk, b->budget[i]);
+      cap[i] = limit(b, i) == UINT64_MAX ? 0x7FFFFFFF : (int32_t)std::min<uint64_t>(chunk, limit(b, i));
     if (cap != T.cap) {
       if (!T.cap.empty()) HIPCHK(hipStreamSynchronize(st));
       T.cap = cap;
+      std::map<const uint64_t *, int32_t> by_counter;
+      for (size_t i = 0; i < nj; i++) by_counter[b->jobs[i]->done_ptr()] = cap[i];
       size_t off = 0;
-      for (auto &a : T.items)
-        for (auto &v : a) {
-          for (Work &w : v)
-            for (size_t i = 0; i < nj; i++)
-              if (w.done == b->jobs[i]->done_ptr()) w.nsweeps_cap = cap[i];
-          if (!v.empty())
-            HIPCHK(hipMemcpyAsync(d_items + off, v.data(), v.size() * sizeof(Work), hipMemcpyHostToDevice, st));
-          off += v.size();
-        }
+      for (auto &l : T.launches) {
+        for (Work &w : l.items) w.nsweeps_cap = by_counter[w.done];
+        if (!l.items.empty())
+          HIPCHK(hipMemcpyAsync(d_items + off, l.items.data(), l.items.size() * sizeof(Work),
+                                hipMemcpyHostToDevice, st));
+        off += l.items.size();
+      }
       HIPCHK(hipMemcpyAsync(d_cap, T.cap.data(), nj * sizeof(int32_t), hipMemcpyHostToDevice, st));
     }
     const int nsw = (int)chunk;
     size_t off = 0;
-    for (int m = 0; m < NMODEL; m++)
-      for (int a = 0; a < 2; a++) {
-        const auto &v = T.items[m][a];
-        if (!v.empty())
-          HIPCHK(sg::launch_sweep(m, a, d_items + off, (int)v.size(), model_tpb(m, T.tpb), T.lds[m][a], nsw, st));
-        off += v.size();
-      }
+    for (const Launch &l : T.launches) {
+      HIPCHK(sg::launch_sweep(l.group, l.algo, d_items + off, (int)l.items.size(), l.tpb, l.lds, nsw, st));
+      off += l.items.size();
+    }
     HIPCHK(sg::launch_advance(d_done, d_cap, (int)nj, nsw, st));
     // parallel tempering of the jobs due after this period: fused launches
     // over runs of consecutive due jobs, the unfused kernel for K > 64
@@ -1919,10 +1930,8 @@ int sg_batch_destroy(sg_batch *b) {
   if (b->d_done) (void)hipFree(b->d_done);
   if (b->d_cap) (void)hipFree(b->d_cap);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  for (int i = 0; i < NGROUP - 1; i++) {
-    if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
-    if (b->join[i]) (void)hipEventDestroy(b->join[i]);
-  }
+  for (hipStream_t sst : b->side) (void)hipStreamDestroy(sst);
+  for (hipEvent_t ev : b->join) (void)hipEventDestroy(ev);
   if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
   return SG_OK;

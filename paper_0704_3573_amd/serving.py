@@ -11,11 +11,24 @@ and slot go to the next waiting request.  A job's result does not depend on
 which other jobs shared its launches (the random numbers of every site are
 fixed by the job's own seed, copy, site and sweep).
 
+The loop never synchronises the whole device.  Jobs are created from their
+seed alone (the library generates the instance) by a worker thread on a
+stream of its own, while periods run; a period's end is a HIP event the loop
+polls; while the membership stays the same, a second period is enqueued
+behind the running one, so the device does not wait for the host.  Jobs of
+one period differ widely in the device time of a sweep (an L = 48 Potts copy
+against an L = 8 Ising one), so in each period every job runs about the same
+device time rather than the same number of sweeps: a period would otherwise
+last as long as its slowest job while the others' compute units idle.
+
 The loop runs in wall-clock time and records, per request, the arrival,
-admission and completion times; latency = completion - arrival.
+admission and completion times; latency = completion - arrival.  An optional
+wall-clock cap stops it with work still in flight (for streams far longer
+than a measurement); the sweeps performed by then are counted.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import dataclasses
 import hashlib
 import time
@@ -26,6 +39,7 @@ import numpy as np
 
 from . import binding as B
 from . import inputs
+
 
 def spins_fingerprint(spins: np.ndarray) -> int:
     """64-bit BLAKE2b fingerprint of the canonical spin bytes of a job."""
@@ -57,33 +71,54 @@ class Request:
         return 2 * self.L ** 3 * self.sweeps
 
 
-def make_job(ctx, req: Request, arena=None) -> B.Job:
-    model = B.ISING if req.model == "ising" else B.POTTS
-    algo = B.METROPOLIS if req.model == "ising" else B.HEATBATH
-    inst = inputs.make_instance(req.model, req.L, 1, 2, 1, req.seed)
-    return B.Job(ctx, model, algo, req.L, [1.0 / req.T], inst["J"], inst["spins"],
-                 inst["wheels"], n_samples=1, n_replicas=2, arena=arena)
+def _model_algo(req: Request):
+    return ((B.ISING, B.METROPOLIS) if req.model == "ising" else (B.POTTS, B.HEATBATH))
+
+
+def make_job(ctx, req: Request, arena=None, stream=None) -> B.Job:
+    """The job of a request, created from its seed alone (two replicas, one
+    temperature); its inputs are those of inputs.make_instance."""
+    model, algo = _model_algo(req)
+    return B.Job(ctx, model, algo, req.L, [1.0 / req.T], n_samples=1, n_replicas=2,
+                 arena=arena, stream=stream, seed=req.seed)
+
+
+def sweep_cost(req: Request) -> float:
+    """Relative device time of one sweep of a request's job: draws per lane
+    per sweep (min(8, L) rows of L sites per wheel, shared by the lanes of
+    the wheel: four for the Potts model at L = 8..32) times the cost of a
+    draw per lane (a Potts heat-bath update about eight Ising Metropolis
+    ones, from the measured per-lane rates of the two kernels).  Only a
+    scheduling estimate: it sets how many sweeps each job runs in a period."""
+    lanes = 4 if req.model == "potts" and req.L in (8, 16, 24, 32) else 1
+    return min(8, req.L) * req.L / lanes * (8.0 if req.model == "potts" else 1.0)
 
 
 def job_bytes(req: Request) -> int:
-    model = B.ISING if req.model == "ising" else B.POTTS
-    algo = B.METROPOLIS if req.model == "ising" else B.HEATBATH
+    model, algo = _model_algo(req)
     return B.job_bytes(B.Spec(model, algo, 4, req.L, 1, 2, 1, 0))
 
 
-def finish(job: B.Job, req: Request):
-    E, Q = job.measure()
+def finish(job: B.Job, req: Request, stream=None):
+    E, Q = job.measure(stream)
     req.E = E
     req.Q = int(Q[0])
-    req.spins_hash = spins_fingerprint(job.spins())
+    req.spins_hash = spins_fingerprint(job.spins(stream))
 
 
 class DeviceBackend:
-    """Jobs and batches of libsg on one GPU (arenas are torch tensors)."""
+    """Jobs and batches of libsg on one GPU (arenas are torch tensors).
+
+    Periods run on `stream` (a new non-blocking torch stream by default);
+    jobs are created by one worker thread on a creation stream of its own."""
 
     def __init__(self, ctx, stream=None):
+        import torch
         self.ctx = ctx
-        self.stream = stream
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.create_stream = torch.cuda.Stream()
+        self.pool = cf.ThreadPoolExecutor(max_workers=1)
+        self.busy = []  # timing events around each period
 
     def new_batch(self):
         return B.Batch(self.ctx)
@@ -91,39 +126,83 @@ class DeviceBackend:
     def job_bytes(self, req):
         return job_bytes(req)
 
-    def create(self, req):
+    def _create(self, req):
         import torch
-        arena = torch.empty(job_bytes(req), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
-        return make_job(self.ctx, req, arena)
+        with torch.cuda.stream(self.create_stream):
+            arena = torch.empty(job_bytes(req), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+            return make_job(self.ctx, req, arena, self.create_stream)
 
-    def run(self, batch, n):
+    def create_async(self, req):
+        return self.pool.submit(self._create, req)
+
+    @staticmethod
+    def ready(handle) -> bool:
+        return handle.done()
+
+    @staticmethod
+    def take(handle):
+        return handle.result()
+
+    def launch(self, batch, n):
         import torch
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(self.stream)
         batch.run(n, self.stream)
-        torch.cuda.synchronize()
+        t1.record(self.stream)
+        self.busy.append((t0, t1))
+        return t1
+
+    def busy_seconds(self) -> float:
+        """Device time of the periods launched so far (they run one after
+        another on one stream), waiting for them."""
+        total = 0.0
+        for t0, t1 in self.busy:
+            t1.synchronize()
+            total += t0.elapsed_time(t1) * 1e-3
+        return total
+
+    @staticmethod
+    def done(token) -> bool:
+        return token.query()
+
+    @staticmethod
+    def wait(token):
+        token.synchronize()
 
     def finish(self, job, req):
-        finish(job, req)
+        finish(job, req, self.stream)
+
+    def close(self):
+        self.pool.shutdown(wait=True)
 
 
 class Server:
     """Admission by slots and HBM budget + continuous batching."""
 
-    def __init__(self, backend, hbm_budget: int, max_slots: int = 512, period: int = 500):
+    def __init__(self, backend, hbm_budget: int, max_slots: int = 512, period: int = 64,
+                 depth: int = 2):
         self.be = backend
         self.budget = hbm_budget
         self.max_slots = max_slots
-        self.period = period
+        self.period = period        # sweeps of the slowest resident job per period
+        self.depth = depth          # periods in flight while the membership is unchanged
         self.batch = backend.new_batch()
         self.used = 0
         self.peak_used = 0
         self.peak_slots = 0
-        self.active = {}   # rid -> (job, req, bytes)
+        self.active = {}            # rid -> (job, req, bytes)
+        self.creating = deque()     # (req, handle, bytes), admission order
         self.pending = deque()
+        self.inflight = deque()     # events of enqueued periods
         self.done = []
         self.periods = 0
+        self.n = 1                  # sweeps per run (the largest per-run cap)
 
-    def _admit(self, now: float):
-        while self.pending and len(self.active) < self.max_slots:
+    def _admit(self):
+        """Reserve memory and a slot for waiting requests (FIFO) and start
+        creating their jobs."""
+        while self.pending and len(self.active) + len(self.creating) < self.max_slots:
             req = self.pending[0]
             nb = self.be.job_bytes(req)
             if nb > self.budget:
@@ -131,18 +210,29 @@ class Server:
             if self.used + nb > self.budget:
                 break
             self.pending.popleft()
-            job = self.be.create(req)
-            self.batch.add(job)
-            self.batch.set_budget(job, req.sweeps)
             self.used += nb
             self.peak_used = max(self.peak_used, self.used)
+            self.creating.append((req, self.be.create_async(req), nb))
+
+    def _ready(self):
+        return [c for c in self.creating if self.be.ready(c[1])]
+
+    def _join(self, ready, now):
+        for c in ready:
+            self.creating.remove(c)
+            req, h, nb = c
+            job = self.be.take(h)
+            self.batch.add(job)
+            self.batch.set_budget(job, req.sweeps)
             req.t_admit = now
             self.active[req.rid] = (job, req, nb)
-            self.peak_slots = max(self.peak_slots, len(self.active))
+        self.peak_slots = max(self.peak_slots, len(self.active))
 
-    def _harvest(self, now: float):
-        for rid in [r for r, (job, req, nb) in self.active.items()
-                    if job.sweeps_done() >= req.sweeps]:
+    def _finished(self):
+        return [r for r, (job, req, nb) in self.active.items() if job.sweeps_done() >= req.sweeps]
+
+    def _harvest(self, rids, now):
+        for rid in rids:
             job, req, nb = self.active.pop(rid)
             self.be.finish(job, req)
             req.t_done = now
@@ -151,26 +241,70 @@ class Server:
             self.used -= nb
             self.done.append(req)
 
-    def serve(self, requests, clock=time.perf_counter, sleep=time.sleep):
-        """Run a stream of requests (any order; served by arrival) to completion."""
+    def _drain(self):
+        if self.inflight:
+            self.be.wait(self.inflight[-1])
+            self.inflight.clear()
+
+    def _set_caps(self):
+        """Per-run caps after a membership change: the slowest resident job
+        (by sweep_cost) runs `period` sweeps per period, every other job as
+        many as take the same device time (its budget still stops it
+        exactly).  The caps stay until the next change, so consecutive periods
+        reuse the launch tables."""
+        if not self.active:
+            return
+        slow = max(sweep_cost(req) for _, req, _ in self.active.values())
+        self.n = 1
+        for job, req, _ in self.active.values():
+            cap = max(1, int(self.period * slow / sweep_cost(req)))
+            self.batch.set_period_cap(job, cap)
+            self.n = max(self.n, min(cap, req.sweeps))
+
+    def _launch(self):
+        self.inflight.append(self.be.launch(self.batch, self.n))
+        self.periods += 1
+
+    def updates_done(self) -> int:
+        """Site updates enqueued so far (finished jobs and the resident ones)."""
+        return sum(r.updates() for r in self.done) + sum(
+            2 * req.L ** 3 * job.sweeps_done() for job, req, _ in self.active.values())
+
+    def serve(self, requests, clock=time.perf_counter, sleep=time.sleep, cap_s=None):
+        """Run a stream of requests (any order; served by arrival) to completion,
+        or until cap_s seconds of wall clock (then the in-flight work is waited
+        for and the unfinished requests are left without t_done)."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         t0 = clock()
         i = 0
-        while i < len(reqs) or self.pending or self.active:
+        while i < len(reqs) or self.pending or self.creating or self.active:
             now = clock() - t0
+            if cap_s is not None and now >= cap_s:
+                break
             while i < len(reqs) and reqs[i].arrival <= now:
                 self.pending.append(reqs[i])
                 i += 1
-            self._admit(now)
-            if self.active:
-                # one period: every resident job advances min(period, its budget)
-                n = min(self.period, max(req.sweeps - job.sweeps_done()
-                                         for job, req, _ in self.active.values()))
-                self.be.run(self.batch, n)
-                self.periods += 1
-                self._harvest(clock() - t0)
-            elif i < len(reqs):
-                sleep(max(0.0, min(0.01, reqs[i].arrival - (clock() - t0))))
+            self._admit()
+            while self.inflight and self.be.done(self.inflight[0]):
+                self.inflight.popleft()
+            finished, ready = self._finished(), self._ready()
+            if finished or ready:
+                # membership changes at a period boundary: let the enqueued
+                # periods end, release finished jobs, add the new ones
+                self._drain()
+                now = clock() - t0
+                self._harvest(finished, now)
+                self._join(ready, now)
+                self._set_caps()
+                self._admit()
+            if self.active and len(self.inflight) < self.depth:
+                self._launch()
+            elif self.inflight:
+                self.be.wait(self.inflight[0])
+            elif i < len(reqs) or self.creating:
+                nxt = reqs[i].arrival - (clock() - t0) if i < len(reqs) else 0.0
+                sleep(max(0.0, min(0.002, nxt)))
+        self._drain()
         return self.done
 
 
@@ -185,9 +319,11 @@ def poisson_stream(n_jobs: int, rate: float, seed: int = 5, sweeps_lo: float = 3
                                                       sizes, t_range, seed0)]
 
 
-def summary(done, wall: float):
-    lat = np.array([r.latency for r in done])
-    upd = sum(r.updates() for r in done)
+def summary(done, wall: float, updates=None):
+    """Latency percentiles of the completed requests and throughput; updates
+    (if given) counts all the sweeps performed, finished jobs or not."""
+    lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+    upd = sum(r.updates() for r in done) if updates is None else updates
     return {"jobs": len(done), "wall_s": round(wall, 3),
             "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
             "p99_latency_s": round(float(np.percentile(lat, 99)), 4),

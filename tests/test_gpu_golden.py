@@ -180,7 +180,7 @@ def test_c5_sampled_jobs_served_in_the_mix(ctx):
     reqs = [serving.Request(r["rid"], r["model"], r["L"], r["T"], r["sweeps"], r["seed"],
                             arrival=0.001 * i) for i, r in enumerate(g["jobs"])]
     srv = serving.Server(serving.DeviceBackend(ctx), hbm_budget=64 << 20, max_slots=12,
-                         period=2000)
+                         period=64)
     done = {r.rid: r for r in srv.serve(reqs)}
     assert len(done) == 50
     assert srv.peak_slots >= 2

@@ -1,6 +1,7 @@
 """CPU tests of the serving loop's scheduling: admission by slots and memory
 budget, FIFO order, exact per-job sweep counts under continuous batching.
-A fake backend counts sweeps instead of launching kernels."""
+A fake backend counts sweeps instead of launching kernels (its jobs are
+created at once and its periods end at once)."""
 import pytest
 
 from paper_0704_3573_amd.serving import Request, Server, poisson_stream, summary
@@ -23,6 +24,7 @@ class FakeBatch:
     def __init__(self):
         self.jobs = []
         self.budgets = {}
+        self.caps = {}
         self.runs = []
 
     def add(self, j):
@@ -36,10 +38,13 @@ class FakeBatch:
     def set_budget(self, j, n):
         self.budgets[id(j)] = n
 
+    def set_period_cap(self, j, n):
+        self.caps[id(j)] = n
+
     def run(self, n):
         self.runs.append((n, len(self.jobs)))
         for j in self.jobs:
-            k = min(n, self.budgets[id(j)])
+            k = min(n, self.budgets[id(j)], self.caps.get(id(j), n))
             j.done += k
             self.budgets[id(j)] -= k
 
@@ -55,13 +60,30 @@ class FakeBackend:
     def job_bytes(self, req):
         return req.L ** 3  # stand-in size
 
-    def create(self, req):
+    def create_async(self, req):
         self.created.append(req.rid)
         return FakeJob(req)
 
-    def run(self, batch, n):
+    @staticmethod
+    def ready(handle):
+        return True
+
+    @staticmethod
+    def take(handle):
+        return handle
+
+    def launch(self, batch, n):
         batch.run(n)
         self.clock.t += 1e-6 * n * len(batch.jobs)
+        return object()
+
+    @staticmethod
+    def done(token):
+        return True
+
+    @staticmethod
+    def wait(token):
+        pass
 
     def finish(self, job, req):
         assert job.done == req.sweeps
@@ -126,3 +148,27 @@ def test_summary_percentiles():
     srv, be, done = run(reqs, budget=10 ** 9, slots=16, period=50)
     s = summary(done, wall=1.0)
     assert s["jobs"] == 30 and s["p99_latency_s"] >= s["p50_latency_s"] >= 0
+
+
+def test_periods_give_every_job_the_same_device_time():
+    from paper_0704_3573_amd.serving import sweep_cost
+    reqs = [Request(0, "ising", 8, 1.0, 700, 0), Request(1, "ising", 16, 1.0, 2000, 1),
+            Request(2, "potts", 48, 1.0, 90, 2)]
+    assert sweep_cost(reqs[2]) == 8 * 48 * 8 and sweep_cost(reqs[1]) == 2 * sweep_cost(reqs[0])
+    srv, be, done = run(reqs, budget=10 ** 9, slots=8, period=30)
+    # period 1: the L = 48 Potts job runs 30 sweeps; the L = 16 job 30 * 3072
+    # / 128 = 720, the L = 8 one 1440, capped at its 700
+    assert srv.batch.runs[0] == (720, 3)
+    assert [r.rid for r in done][0] == 0
+    assert all(r.E == [r.sweeps, -r.sweeps] for r in done) and len(done) == 3
+    assert srv.updates_done() == sum(r.updates() for r in done)
+
+
+def test_wall_clock_cap_stops_with_work_left():
+    reqs = [Request(0, "ising", 8, 1.0, 10 ** 6, 0), Request(1, "ising", 8, 1.0, 50, 1)]
+    clock = Clock()
+    be = FakeBackend(clock)
+    srv = Server(be, hbm_budget=10 ** 9, max_slots=4, period=100)
+    done = srv.serve(reqs, clock=clock, sleep=clock.sleep, cap_s=0.01)
+    assert [r.rid for r in done] == [1] and reqs[0].t_done is None
+    assert srv.updates_done() > reqs[1].updates()
