@@ -261,8 +261,10 @@ int sg_batch_create(sg_ctx *ctx, sg_job *const *jobs, int32_t n, sg_batch **out)
 int sg_batch_add(sg_batch *b, sg_job *job);
 int sg_batch_remove(sg_batch *b, sg_job *job);
 /* Threads per workgroup of the fused launch (multiple of 64, <= 1024;
- * 0 = automatic); the Potts and Ising-like launches use min(threads, 512).
- * Results do not depend on it. */
+ * 0 = automatic); the Potts and Ising-like launches use min(threads, 512)
+ * (768 for the Potts models at L = 40, 48); a copy needing more lanes than
+ * that runs in a workgroup of its own size, and items much smaller than it
+ * in workgroups of theirs.  Results do not depend on it. */
 int sg_batch_set_block(sg_batch *b, int32_t threads);
 /* Remaining sweep budget of a job in the batch: a run of n sweeps advances
  * the job by min(n, budget) and lowers the budget by that much

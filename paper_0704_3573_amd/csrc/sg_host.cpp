@@ -178,6 +178,7 @@ static int wheel_lanes(int model, int L) {
 }
 static int launch_group(int model, int L) {
   if (wheel_lanes(model, L) == 4) return model == SG_POTTS ? sg::LAUNCH_POTTS_QUAD : sg::LAUNCH_GPOTTS_QUAD;
+  if (wheel_lanes(model, L) == 2) return model == SG_POTTS ? sg::LAUNCH_POTTS_PAIR : sg::LAUNCH_GPOTTS_PAIR;
   return model;
 }
 
@@ -293,13 +294,22 @@ static size_t item_lds(const sg_job *j, int G) {
          (size_t)G * sg::POTTS_W_WORDS * 4 + (size_t)G * 4 + dummy;
 }
 
-// threads per workgroup of a model's launch for a requested block size
-static int model_tpb(int model, int tpb) {
-  return model != SG_ISING ? std::min(tpb, sg::POTTS_MAX_TPB) : tpb;
+// threads per workgroup of a launch group for a requested block size
+static int model_tpb(int group, int tpb) {
+  if (group == SG_ISING) return tpb;
+  if (group == sg::LAUNCH_POTTS_PAIR || group == sg::LAUNCH_GPOTTS_PAIR)
+    return std::min(tpb, sg::POTTS_PAIR_MAX_TPB);
+  return std::min(tpb, sg::POTTS_MAX_TPB);
+}
+
+// workgroup size of a job's items for a requested block size: the block,
+// limited by the launch group, or one copy's lanes if a copy needs more
+static int item_tpb(const sg_job *j, int tpb) {
+  return std::max(model_tpb(j->group(), tpb), (j->lanes() + 63) / 64 * 64);
 }
 
 static int copies_per_item(const sg_job *j, int tpb) {
-  int G = model_tpb(j->sp.model, tpb) / j->lanes();
+  int G = item_tpb(j, tpb) / j->lanes();
   G = std::min(G, j->C);
   while (G > 1 && item_lds(j, G) > (size_t)j->ctx->max_lds) G--;
   return G;
@@ -1402,7 +1412,7 @@ static double idle_fraction(const sg_batch *b, int tpb) {
     const double items = std::ceil((double)j->C / G);
     const double per_lane = (double)j->g.RHO / wheel_lanes(j->sp.model, j->L);  // draws per lane, in L/2
     used += (double)j->C * j->lanes() * per_lane;
-    total += items * ((model_tpb(j->sp.model, tpb) + 63) / 64 * 64) * per_lane;
+    total += items * item_tpb(j, tpb) * per_lane;
   }
   return total > 0 ? 1.0 - used / total : 0.0;
 }
@@ -1431,12 +1441,10 @@ static int plan_items(const sg_batch *b, int &tpb_out, std::vector<Launch> &laun
     }
     if (tpb <= 0) return fail(SG_E_UNSUPPORTED, "no block size fits the batch");
   }
-  for (sg_job *j : b->jobs)
-    if (j->lanes() > tpb) return fail(SG_E_INVALID, "block of %d threads is smaller than one copy of L = %d", tpb, j->L);
   std::map<std::tuple<int, int, int>, Launch> by_key;
   for (sg_job *j : b->jobs) {
     const int G = copies_per_item(j, tpb);
-    int blk = model_tpb(j->sp.model, tpb);
+    int blk = item_tpb(j, tpb);
     const int need = (G * j->lanes() + 63) / 64 * 64;
     if (need <= blk / 2) blk = need;
     Launch &l = by_key[std::make_tuple(j->group(), j->sp.algo, blk)];

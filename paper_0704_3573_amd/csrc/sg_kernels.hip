@@ -1369,35 +1369,45 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
 }
 
 // ---------------------------------------------------------------------------
-// q = 4 Potts heat bath (+-J glass and glassy model) with four lanes per
-// wheel.  Sec. 3.3 lets one wheel emit many numbers per clock, because the
-// recurrence I(k) = I(k-24) + I(k-55) reaches back at least 24 outputs: any
-// 24 consecutive outputs can be formed at once.  Here the four lanes of a
-// quad share a wheel: lane l forms the outputs k = k0 + 4 s + l (step s),
+// q = 4 Potts heat bath (+-J glass and glassy model) with S = 4 or 2 lanes
+// per wheel.  Sec. 3.3 lets one wheel emit many numbers per clock, because
+// the recurrence I(k) = I(k-24) + I(k-55) reaches back at least 24 outputs:
+// any 24 consecutive outputs can be formed at once.  Here the S lanes of a
+// group share a wheel: lane l forms the outputs k = k0 + S s + l (step s),
 // so the numbers, their order and every site's number are those of the
-// one-lane kernel.  Per step and lane:
-//   I(k-24) is the lane's own output of step s - 6;
-//   I(k-55) is the output of step s - 14 of lane l + 1 (step s - 13 of lane
-//     0 for l = 3), I(k-61) that of step s - 15 of lane l - 1 (step s - 16
-//     of lane 3 for l = 0): each lane exposes the right word (one bit-select
-//     on lane-constant masks) and the reader takes it with a DPP quad
-//     permutation;
-// so each lane keeps its outputs of steps s - 1 .. s - 16 in registers (a
-// ring of RL >= 16 words, static indices) and the site it updates is the
-// draw's: within a block of B draws (as in the one-lane kernel) lane l
-// updates draws l, l + 4, l + 8, ...  Everything else (fields, weights,
-// multiply, selection, the LDS layout and the HBM state) is the one-lane
-// kernel's.  Used for L = 8, 16, 24, 32 (L/2 a multiple of 4, a copy's
-// 4 NW lanes within one workgroup; potts_wheel_lanes).
+// one-lane kernel.  For a lag m = q S + r (0 <= r < S), I(k - m) is the
+// output of step s - q of lane l - r if l >= r, else of step s - q - 1 of
+// lane l - r + S: each lane exposes the word its reader needs (step s - q - 1
+// in lanes l >= S - r, else s - q: one bit-select on lane-constant masks)
+// and the reader takes it with a DPP quad permutation; lag 24 (r = 0) stays
+// in the lane.  Each lane keeps its outputs of the last D steps in registers
+// (D = 16 for S = 4, 31 for S = 2; a ring of RL >= D words, static indices),
+// and within a block of B draws (as in the one-lane kernel) lane l updates
+// draws l, l + S, l + 2S, ...  Everything else (fields, weights, multiply,
+// selection, the LDS layout and the HBM state) is the one-lane kernel's.
+// potts_wheel_lanes gives S: four at L = 8..32, two at L = 40, 48 (four
+// lanes per wheel would not fit one workgroup there).
 // ---------------------------------------------------------------------------
-template <int L, bool GLASSY>
-struct PottsQK {
+
+// DPP quad-permutation control: lane i of a group of S (S | 4) reads lane
+// (i - r) mod S of its group.
+constexpr int qp_ctrl(int S, int r) {
+  int c = 0;
+  for (int i = 0; i < 4; i++) c |= ((i / S) * S + ((i % S) - r + S) % S) << (2 * i);
+  return c;
+}
+
+template <int L, bool GLASSY, int S>
+struct PottsMK {
   using G = GC<L>;
-  static constexpr bool QUAD = true;
-  static constexpr int S = 4;
-  static_assert(G::B % S == 0 && G::H % S == 0, "four lanes per wheel need B, L/2 multiples of 4");
+  static constexpr bool QUAD = true;  // loads and stores its own ring
+  static_assert(S == 2 || S == 4, "two or four lanes per wheel");
+  static_assert(G::B % S == 0 && G::H % S == 0, "S lanes per wheel need B, L/2 multiples of S");
   static constexpr int B = G::B / S;                 // steps per block (draws per lane)
-  static constexpr int RL = ((16 + B - 1) / B) * B;  // register ring of a lane (steps)
+  static constexpr int Q24 = 24 / S, Q55 = 55 / S, R55 = 55 % S, Q61 = 61 / S, R61 = 61 % S;
+  static_assert(24 % S == 0 && R55 > 0 && R61 > 0, "lag 24 in-lane, lags 55 and 61 across lanes");
+  static constexpr int D = Q61 + 1;                  // steps of history a lane keeps
+  static constexpr int RL = ((D + B - 1) / B) * B;   // register ring of a lane (steps)
   static constexpr int M = RL, V = RL / B;           // as the drive expects them
   static constexpr int NBLK = G::NBLK, H = G::H, RPB = G::RPB, RHO = G::RHO, NW = G::NW;
   static constexpr int MS = G::M;                    // HBM ring slots of a wheel
@@ -1409,50 +1419,60 @@ struct PottsQK {
   rsrc_t rJ;            // coupling words of the job
   uint32_t voff;        // byte offset of the lane's coupling words
   bool active;
-  int z, zp, zm, g, sub;  // wheel plane, row group and the lane's place in its quad
-  uint32_t m0, m3;        // all ones in lanes with sub == 0 (== 3)
+  int z, zp, zm, g, sub;  // wheel plane, row group and the lane's place in its group
+  uint32_t m0, mlast;     // all ones in lanes with sub == 0 (== S - 1)
+  uint32_t x55, x61;      // all ones in lanes exposing the older word for lag 55 (61)
   uint32_t sh;            // 8 sub: the lane's byte of a +-J pattern word
   int kmod0, kmod1;       // first draw of the launch (and of the next one) mod MS
   uint32_t nextpat[BQ];
 
   static DEV int row(int y) { return y * L * L + (y / RHO) * 2 * L; }
 
+  DEV void init_lane(int t) {
+    sub = t % S;
+    m0 = sub == 0 ? ~0u : 0u;
+    mlast = sub == S - 1 ? ~0u : 0u;
+    x55 = sub >= S - R55 ? ~0u : 0u;
+    x61 = sub >= S - R61 ? ~0u : 0u;
+    sh = 8u * (uint32_t)sub;
+  }
+
   DEV void fetch(int p, int blk) {
     if constexpr (GLASSY) {
-      // one word per draw: the lane's draws 4 i + sub of the block
+      // one word per draw: the lane's draws S i + sub of the block
       const uint32_t s0 = __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * G::B) * NW * 4u);
 #pragma unroll
-      for (int i = 0; i < B; i++) nextpat[i] = bload(rJ, voff, s0 + (uint32_t)(4 * i) * NW * 4u);
+      for (int i = 0; i < B; i++) nextpat[i] = bload(rJ, voff, s0 + (uint32_t)(S * i) * NW * 4u);
     } else {
-      // four draws per word (the lane uses byte sub of each)
+      // four draws per word
       const uint32_t s0 = __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * BQ) * NW * 4u);
 #pragma unroll
       for (int q = 0; q < BQ; q++) nextpat[q] = bload(rJ, voff, s0 + (uint32_t)q * NW * 4u);
     }
   }
 
-  // HBM slot of the output at draw offset `off` from the launch's first draw
+  // HBM slot of the output at draw offset `off` from a launch's first draw
   DEV uint32_t slot_of(int kmod, int off) const { return (uint32_t)((kmod + 4 * MS + off) % MS); }
 
-  // outputs of steps -16 .. -1 (draws k0 - 64 + 4 i + sub; the one at
-  // k0 - 64 + sub is dead for sub < 3 and never read)
+  // outputs of steps -D .. -1 (draws k0 + S st + sub); the oldest are dead
+  // (before k0 - 61) in some lanes and never read
   DEV void load_ring(uint32_t (&ring)[RL], const Drive &d) const {
 #pragma unroll
-    for (int i = 0; i < 16; i++) {
-      const int st = i - 16;
-      ring[(st + RL) % RL] = bload(d.rwh, d.widx + slot_of(kmod0, 4 * st + sub) * d.wstride);
+    for (int i = 0; i < D; i++) {
+      const int st = i - D;
+      ring[(st + RL) % RL] = bload(d.rwh, d.widx + slot_of(kmod0, S * st + sub) * d.wstride);
     }
   }
 
-  // LAST: the register of the launch's last step; the live words are the
-  // outputs of the last 15 steps and, for sub == 3, the 16th
+  // LAST: the register of the launch's last step; live words are those of
+  // draws >= k_end - 61
   template <int LAST>
   DEV void store_ring(const uint32_t (&ring)[RL], const Drive &d) const {
 #pragma unroll
-    for (int ds = 0; ds < 16; ds++) {
+    for (int ds = 0; ds < D; ds++) {
       const int i = (LAST - ds + RL) % RL;
-      if (ds < 15 || sub == 3)
-        bstore(d.rwh, ring[i], d.widx + slot_of(kmod1, -4 - 4 * ds + sub) * d.wstride);
+      const int off = -S - S * ds + sub;
+      if (off >= -61) bstore(d.rwh, ring[i], d.widx + slot_of(kmod1, off) * d.wstride);
     }
   }
 
@@ -1489,20 +1509,22 @@ struct PottsQK {
     const int dzp = zp - z, dzm = zm - z;
     uint32_t nb[B][6], rb[B][6], w[B][4];
 
-    // step i: draw 4 i + sub of the block, row rr = 4 i / H, in-row index
-    // j = 4 i mod H + sub (H is a multiple of 4)
+    // step i: draw S i + sub of the block, row rr = S i / H, in-row index
+    // j = S i mod H + sub (H is a multiple of S)
     auto request_site = [&](int i) {
-      const int rr = 4 * i / H, jb = 4 * i - rr * H, o = 2 * jb * L;
+      const int rr = S * i / H, jb = S * i - rr * H, o = 2 * jb * L;
       if constexpr (GLASSY) {
 #pragma unroll
         for (int d = 0; d < 6; d++) rb[i][d] = tb[(d & 1) * 24 + ((pat[i] >> (5 * d)) & 31u)];
       } else {
-        const uint32_t *r6 = tb + POTTS_TAB_STRIDE * ((pat[i] >> sh) & 0xFFu);
+        // word (S i) / 4, byte (S i) mod 4 + sub
+        const uint32_t *r6 =
+            tb + POTTS_TAB_STRIDE * ((pat[(S * i) >> 2] >> (sh + 8 * ((S * i) & 3))) & 0xFFu);
 #pragma unroll
         for (int d = 0; d < 6; d++) rb[i][d] = r6[d];
       }
       const int c = base[rr] + o;
-      const int xp = jb == H - 4 ? (int)bfi(m3, (uint32_t)bxw[rr], (uint32_t)(c + L)) : c + L;
+      const int xp = jb == H - S ? (int)bfi(mlast, (uint32_t)bxw[rr], (uint32_t)(c + L)) : c + L;
       const int xm = jb == 0 ? (int)bfi(m0, (uint32_t)bxw[rr], (uint32_t)(c - L)) : c - L;
       nb[i][0] = rd[xp];
       nb[i][1] = rd[xm];
@@ -1531,15 +1553,14 @@ struct PottsQK {
       w[i][3] = *(const uint32_t *)(wm - c3);
     };
     auto finish_site = [&](int i) {
-      const int rr = 4 * i / H, jb = 4 * i - rr * H;
+      const int rr = S * i / H, jb = S * i - rr * H;
       const int st = VI * B + i;  // register of this step (static)
-      const uint32_t e55 = bfi(m0, ring[(st + RL - 13) % RL], ring[(st + RL - 14) % RL]);
-      const uint32_t e61 = bfi(m3, ring[(st + RL - 16) % RL], ring[(st + RL - 15) % RL]);
-      // quad permutations: lane l reads lane (l + 1) & 3, resp. (l + 3) & 3
-      const uint32_t x55 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e55, 0x39, 0xF, 0xF, false);
-      const uint32_t x61 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e61, 0x93, 0xF, 0xF, false);
-      ring[st % RL] = ring[(st + RL - 6) % RL] + x55;
-      const uint32_t r = ring[st % RL] ^ x61;
+      const uint32_t e55 = bfi(x55, ring[(st + RL - Q55 - 1) % RL], ring[(st + RL - Q55) % RL]);
+      const uint32_t e61 = bfi(x61, ring[(st + RL - Q61 - 1) % RL], ring[(st + RL - Q61) % RL]);
+      const uint32_t y55 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e55, qp_ctrl(S, R55), 0xF, 0xF, false);
+      const uint32_t y61 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e61, qp_ctrl(S, R61), 0xF, 0xF, false);
+      ring[st % RL] = ring[(st + RL - Q24) % RL] + y55;
+      const uint32_t r = ring[st % RL] ^ y61;
       const uint32_t C1 = w[i][0] + w[i][1], C2 = C1 + w[i][2];
       const uint32_t t = __umulhi(r, C2 + w[i][3]);
       const uint32_t nt = ~t;
@@ -1569,7 +1590,7 @@ struct PottsQK {
     for (int blk = 0; blk < NBLK; blk++) {
       const int y0 = g * RHO + blk * RPB;
       for (int i = 0; i < B; i++) {
-        const int kb = 4 * i + sub, rr = kb / H, j = kb - rr * H;
+        const int kb = S * i + sub, rr = kb / H, j = kb - rr * H;
         const int y = y0 + rr;
         const int e = (y + z) & 1;
         const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
@@ -1580,14 +1601,14 @@ struct PottsQK {
                            c - z + zp, c - z + zm};
         const uint32_t si = sp[c];
         if constexpr (GLASSY) {
-          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * G::B + 4 * i) * NW) * 4u);
+          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * G::B + S * i) * NW) * 4u);
           for (int d = 0; d < 6; d++) {
             const uint32_t vote = tab[(d & 1) * 24 + ((pw >> (5 * d)) & 31u)];
             hsum += ((vote >> sp[nb[d]]) & 31u) == si;
           }
         } else {
-          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * BQ + i) * NW) * 4u);
-          const uint32_t pt = (pw >> sh) & 0xFFu;
+          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * BQ + (kb >> 2)) * NW) * 4u);
+          const uint32_t pt = (pw >> (8 * (kb & 3))) & 0xFFu;
           for (int d = 0; d < 6; d++)
             if (sp[nb[d]] == si) hsum += ((pt >> d) & 1u) ? -1 : 1;
         }
@@ -1597,14 +1618,14 @@ struct PottsQK {
   }
 };
 
-template <int L, bool GLASSY>
-DEV void potts_quad_run(const Work &w, uint32_t *lds) {
+template <int L, bool GLASSY, int S>
+DEV void potts_multi_run(const Work &w, uint32_t *lds) {
   using G = GC<L>;
-  using K = PottsQK<L, GLASSY>;
+  using K = PottsMK<L, GLASSY, S>;
   constexpr int N3 = L * L * L;
   constexpr int CW = potts_lds_copy(L) / 4;  // LDS words per copy
   constexpr int GW = G::RHO * L * L / 4;     // HBM words per row group
-  constexpr int LPC = 4 * G::NW;             // lanes per copy
+  constexpr int LPC = S * G::NW;             // lanes per copy
   const int t = threadIdx.x;
   const int nthr = blockDim.x;
   const bool active = t < w.ncopies * LPC;
@@ -1628,17 +1649,14 @@ DEV void potts_quad_run(const Work &w, uint32_t *lds) {
       });
   for (int i = t; i < w.ncopies; i += nthr) Hcnt[i] = 0;
 
-  // lanes without a wheel (whole quads) run wheel (z = (t / 4) mod L, row
-  // group 0) of the first copy and store into the dummy region
+  // lanes without a wheel (whole groups of S) run wheel (z = (t / S) mod L,
+  // row group 0) of the first copy and store into the dummy region
   K k;
   const int cl = active ? t / LPC : 0;
-  const int rem = active ? t - cl * LPC : 4 * ((t >> 2) % L) + (t & 3);
-  const int wl = rem >> 2;
+  const int rem = active ? t - cl * LPC : S * ((t / S) % L) + t % S;
+  const int wl = rem / S;
   const int copy = w.copy0 + cl;
-  k.sub = t & 3;
-  k.m0 = k.sub == 0 ? ~0u : 0u;
-  k.m3 = k.sub == 3 ? ~0u : 0u;
-  k.sh = 8u * (uint32_t)k.sub;
+  k.init_lane(t);
   k.sp = (uint8_t *)(cp + cl * CW);
   k.wp = active ? k.sp : dummy;
   k.tab = tab;
@@ -1681,10 +1699,19 @@ DEV void potts_quad_run(const Work &w, uint32_t *lds) {
 template <bool GLASSY>
 DEV void potts_quad_dispatch(const Work &w, uint32_t *lds) {
   switch (w.L) {
-    case 8: potts_quad_run<8, GLASSY>(w, lds); break;
-    case 16: potts_quad_run<16, GLASSY>(w, lds); break;
-    case 24: potts_quad_run<24, GLASSY>(w, lds); break;
-    case 32: potts_quad_run<32, GLASSY>(w, lds); break;
+    case 8: potts_multi_run<8, GLASSY, 4>(w, lds); break;
+    case 16: potts_multi_run<16, GLASSY, 4>(w, lds); break;
+    case 24: potts_multi_run<24, GLASSY, 4>(w, lds); break;
+    case 32: potts_multi_run<32, GLASSY, 4>(w, lds); break;
+    default: break;
+  }
+}
+
+template <bool GLASSY>
+DEV void potts_pair_dispatch(const Work &w, uint32_t *lds) {
+  switch (w.L) {
+    case 40: potts_multi_run<40, GLASSY, 2>(w, lds); break;
+    case 48: potts_multi_run<48, GLASSY, 2>(w, lds); break;
     default: break;
   }
 }
@@ -1705,13 +1732,27 @@ __global__ __launch_bounds__(POTTS_MAX_TPB) void gpotts_quad_kernel(const Work *
   potts_quad_dispatch<true>(w, lds);
 }
 
+__global__ __launch_bounds__(POTTS_PAIR_MAX_TPB) void potts_pair_kernel(const Work *__restrict__ works,
+                                                                        int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  potts_pair_dispatch<false>(w, lds);
+}
+
+__global__ __launch_bounds__(POTTS_PAIR_MAX_TPB) void gpotts_pair_kernel(const Work *__restrict__ works,
+                                                                         int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  potts_pair_dispatch<true>(w, lds);
+}
+
 template <bool GLASSY>
 DEV void potts_dispatch(const Work &w, uint32_t *lds) {
   switch (w.L) {
     case 2: potts_run<2, GLASSY>(w, lds); break;
     case 4: potts_run<4, GLASSY>(w, lds); break;
-    case 40: potts_run<40, GLASSY>(w, lds); break;
-    case 48: potts_run<48, GLASSY>(w, lds); break;
     default: break;
   }
 }
@@ -2282,6 +2323,10 @@ hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, in
     hipLaunchKernelGGL(potts_quad_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == LAUNCH_GPOTTS_QUAD)
     hipLaunchKernelGGL(gpotts_quad_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == LAUNCH_POTTS_PAIR)
+    hipLaunchKernelGGL(potts_pair_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == LAUNCH_GPOTTS_PAIR)
+    hipLaunchKernelGGL(gpotts_pair_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == 4)
     hipLaunchKernelGGL(gpotts4_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == 3 && algo == 0)
@@ -2310,6 +2355,12 @@ hipError_t set_max_lds(int bytes) {
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)gpotts_quad_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)potts_pair_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)gpotts_pair_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)gpotts4_sweep_kernel,

@@ -165,13 +165,19 @@ constexpr int POTTS4_W_WORDS = 12;
 // groups and copies of a wave are consecutive modulo 256 bytes, i.e. they
 // fall on distinct LDS banks.
 constexpr int POTTS_MAX_TPB = 512;
-// Lanes per wheel of the 3D Potts kernels: four (the wheel's outputs are
-// formed four at a time, lane l taking those with index = l mod 4) where L/2
-// is a multiple of 4 and a copy's lanes fit one workgroup, else one.
-SG_HD constexpr int potts_wheel_lanes(int L) { return L == 8 || L == 16 || L == 24 || L == 32 ? 4 : 1; }
-// Launch groups of the four-lanes-per-wheel kernels (+-J and glassy), beside
-// the model numbers 0..4 of the other sweep kernels.
-constexpr int LAUNCH_POTTS_QUAD = 5, LAUNCH_GPOTTS_QUAD = 6;
+// Lanes per wheel of the 3D Potts kernels (the wheel's outputs are formed S
+// at a time, lane l taking those with index = l mod S): four where L/2 is a
+// multiple of 4 and a copy's 4 NW lanes fit one workgroup (L = 8..32), two at
+// L = 40, 48 (2 NW = 400, 576 lanes), else one.
+SG_HD constexpr int potts_wheel_lanes(int L) {
+  return L == 8 || L == 16 || L == 24 || L == 32 ? 4 : (L == 40 || L == 48 ? 2 : 1);
+}
+// Workgroups of the two-lanes-per-wheel kernels hold up to 768 threads.
+constexpr int POTTS_PAIR_MAX_TPB = 768;
+// Launch groups of the several-lanes-per-wheel kernels (+-J and glassy),
+// beside the model numbers 0..4 of the other sweep kernels.
+constexpr int LAUNCH_POTTS_QUAD = 5, LAUNCH_GPOTTS_QUAD = 6, LAUNCH_POTTS_PAIR = 7,
+              LAUNCH_GPOTTS_PAIR = 8;
 constexpr int POTTS_TAB_STRIDE = 7;
 constexpr int POTTS_TAB_WORDS = 64 * POTTS_TAB_STRIDE;
 constexpr int POTTS_W_WORDS = 8;
