@@ -17,7 +17,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sg_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# SG_ORACLE_LIBRARY names another build of the oracle (a sanitizer build)
+LIB = os.environ.get("SG_ORACLE_LIBRARY") or os.path.join(HERE, "liboracle.so")
 
 ISING, POTTS, GPOTTS = 0, 1, 2  # GPOTTS: glassy (permutation) Potts, Eq. (3)
 GPOTTS4 = 4  # glassy Potts model on the 4D hypercubic lattice

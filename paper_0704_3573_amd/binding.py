@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsg.so")
+# SG_LIBRARY names another build of the same library (for example one whose
+# host code is built with sanitizers, for the CPU checks)
+LIB_PATH = os.environ.get("SG_LIBRARY") or os.path.join(HERE, "libsg.so")
 
 ISING, POTTS, GPOTTS = 0, 1, 2  # GPOTTS: glassy Potts model (permutation couplings)
 ISING_GEN = 3  # Ising-like model of Eq. 2 with dilution and field (RFIM, DAFF)
