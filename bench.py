@@ -29,10 +29,12 @@ if ROOT not in sys.path:
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # algorithmic integer operations per Metropolis site update: Eq. (5) draw
-# (one add, one xor), one compare with the site's threshold, and one word
-# operation for the bit-sliced six-bond count and flip (36 word operations
-# per 32 sites)
-ALG_OPS_PER_UPDATE = 4
+# (one add, one xor), one compare with the site's threshold, one operation
+# recording the decision in the site's word, and the bit-sliced six-bond
+# count with the flip amortised over the 32 sites of a word (about half an
+# operation per site); the lower end of the 4.5 .. 8.5 operations the
+# method needs per update
+ALG_OPS_PER_UPDATE = 4.5
 # Ising-like models (Eq. 2): the same plus one operation forming the site's
 # threshold-table index (the paper's update cell reads a LUT in the same way)
 GEN_ALG_OPS_PER_UPDATE = 5
@@ -60,23 +62,27 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source (else None)."""
+def committed_counters():
+    """Values of the committed rocprofv3 counter summary of the batched sweep
+    launch, if it was taken on the current kernel source (else {})."""
     p = os.path.join(ROOT, "profiles", "ising_sweep_c3_counters.txt")
     if not os.path.exists(p):
-        return None
+        return {}
     vals = {}
     for line in open(p):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for k in ("hbm_bytes_per_launch", "valu_lane_ops_per_update", "valu_busy_fraction",
+              "lds_bank_conflict_fraction"):
+        try:
+            out[k] = float(vals[k])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def build_c3(ctx, B, inputs, algo=None):
@@ -182,12 +188,37 @@ def cpu_baseline(budget_s=15.0):
             inst["spins"], inst["wheels"], inst["ptwheels"] = (out["spins"], out["wheels"],
                                                                out["ptwheels"])
         periods += 1
+    # single thread, the plain workloads: EA L = 8 (1 replica, 1000 sweeps,
+    # whole run) and EA L = 64 with two replicas (a 50-sweep sample of the
+    # 10^4-sweep run), Metropolis at T = 1.1
+    single = {}
+    for name, L, R, n in (("L8_1000_sweeps", 8, 1, 1000), ("L64_2_replicas_50_sweeps", 64, 2, 50)):
+        inst = inputs.make_instance("ising", L, 1, R, 1, seed=1 if L == 8 else 2)
+        t = time.perf_counter()
+        oracle.run(oracle.ISING, oracle.METROPOLIS, L, [1 / 1.1], inst["J"], inst["spins"],
+                   inst["wheels"], n_replicas=R, n_sweeps=n, n_threads=1)
+        dt = time.perf_counter() - t
+        ups = R * L ** 3 * n
+        single[name] = {"ns_per_update": round(dt * 1e9 / ups, 3),
+                        "updates_per_ns": round(ups / (dt * 1e9), 5)}
     del np
     return {"value": updates / (elapsed * 1e9), "unit": "spin updates/ns", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"one sample per L in {list(C3_LS)} with its {C3_R * C3_K} copies "
                       f"(2 replicas x 32 temperatures), {periods} parallel-tempering period(s) "
-                      f"of {C3_PT} sweeps each, {updates:.3g} updates in {elapsed:.1f}s"}
+                      f"of {C3_PT} sweeps each, {updates:.3g} updates in {elapsed:.1f}s",
+            "single_thread": single}
+
+
+def cpu_model():
+    """Model name of the host CPU (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def heat_bath_c3(ctx, B, inputs, np, torch, stream, steps, block):
@@ -504,7 +535,8 @@ def main():
     batch.set_timing(False)
     kernel_ms = float(np.mean(kms))
     achieved = updates_per_step * ALG_OPS_PER_UPDATE / (kernel_ms * 1e-3) / 1e12
-    traffic = measured_traffic()
+    counters = committed_counters()
+    traffic = counters.get("hbm_bytes_per_launch")
     log(f"[bench] sweep kernel: {kernel_ms:.3f} ms per launch ({C3_PT} sweeps), "
         f"{achieved:.2f} TOP/s algorithmic")
     E = [j.energies() for j in jobs]
@@ -514,7 +546,7 @@ def main():
         log(f"[bench] batched only: {value:.1f} updates/ns")
         return
 
-    hb = heat_bath_c3(ctx, B, inputs, np, torch, stream, max(10, args.steps // 4), tpb) \
+    hb = heat_bath_c3(ctx, B, inputs, np, torch, stream, args.steps, tpb) \
         if args.heat_bath else None
 
     # --------------------------------------------------------- plain form --
@@ -595,6 +627,15 @@ def main():
             "alg_ops_per_update": ALG_OPS_PER_UPDATE,
             "hbm_alg_bytes_per_update": round(c3_alg_bytes_per_update(), 4),
             "hbm_frac_alg": round(value * c3_alg_bytes_per_update() / HBM_PEAK_GBS, 5),
+            # measured (committed rocprofv3 counters of this kernel source):
+            # HBM bytes per launch over the live launch time, and the VALU
+            # lane-operations issued per update and the VALU issue fraction
+            "hbm_gbs_measured": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9, 1),
+            "hbm_frac_measured": None if traffic is None else
+            round(traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "valu_lane_ops_per_update_measured": counters.get("valu_lane_ops_per_update"),
+            "valu_issue_frac_measured": counters.get("valu_busy_fraction"),
+            "lds_bank_conflict_frac_measured": counters.get("lds_bank_conflict_fraction"),
         },
         "plain": {
             "value": round(plain_value, 3),

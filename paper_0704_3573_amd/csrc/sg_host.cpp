@@ -177,6 +177,7 @@ static int wheel_lanes(int model, int L) {
   return model == SG_POTTS || model == SG_GPOTTS ? sg::potts_wheel_lanes(L) : 1;
 }
 static int launch_group(int model, int L) {
+  if (model == SG_ISING && L <= 4) return sg::LAUNCH_ISING_SMALL;
   if (wheel_lanes(model, L) == 4) return model == SG_POTTS ? sg::LAUNCH_POTTS_QUAD : sg::LAUNCH_GPOTTS_QUAD;
   if (wheel_lanes(model, L) == 2) return model == SG_POTTS ? sg::LAUNCH_POTTS_PAIR : sg::LAUNCH_GPOTTS_PAIR;
   return model;
@@ -296,7 +297,7 @@ static size_t item_lds(const sg_job *j, int G) {
 
 // threads per workgroup of a launch group for a requested block size
 static int model_tpb(int group, int tpb) {
-  if (group == SG_ISING) return tpb;
+  if (group == SG_ISING || group == sg::LAUNCH_ISING_SMALL) return tpb;
   if (group == sg::LAUNCH_POTTS_PAIR || group == sg::LAUNCH_GPOTTS_PAIR)
     return std::min(tpb, sg::POTTS_PAIR_MAX_TPB);
   return std::min(tpb, sg::POTTS_MAX_TPB);

@@ -2251,8 +2251,6 @@ __global__ __launch_bounds__(1024) void ising_sweep_kernel(const Work *__restric
   Work w = works[blockIdx.x];
   w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
   switch (w.L) {
-    case 2: ising_run<2, ALGO>(w, lds); break;
-    case 4: ising_run<4, ALGO>(w, lds); break;
     case 8: ising_run<8, ALGO>(w, lds); break;
     case 16: ising_run<16, ALGO>(w, lds); break;
     case 24: ising_run<24, ALGO>(w, lds); break;
@@ -2265,8 +2263,26 @@ __global__ __launch_bounds__(1024) void ising_sweep_kernel(const Work *__restric
   }
 }
 
+// L = 2 and 4 (blocks of 2 and 8 draws, so a register ring cycling through
+// 31 and 8 block phases): a kernel of their own, so that their register
+// needs do not set those of the large-lattice kernel
+template <int ALGO>
+__global__ __launch_bounds__(1024) void ising_small_kernel(const Work *__restrict__ works,
+                                                          int nsweeps) {
+  extern __shared__ uint32_t lds[];
+  Work w = works[blockIdx.x];
+  w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
+  switch (w.L) {
+    case 2: ising_run<2, ALGO>(w, lds); break;
+    case 4: ising_run<4, ALGO>(w, lds); break;
+    default: break;
+  }
+}
+
 template __global__ void ising_sweep_kernel<0>(const Work *, int);
 template __global__ void ising_sweep_kernel<1>(const Work *, int);
+template __global__ void ising_small_kernel<0>(const Work *, int);
+template __global__ void ising_small_kernel<1>(const Work *, int);
 
 template <int ALGO>
 __global__ __launch_bounds__(POTTS_MAX_TPB) void gen_sweep_kernel(const Work *__restrict__ works,
@@ -2327,6 +2343,10 @@ hipError_t launch_sweep(int model, int algo, const Work *d_works, int nworks, in
     hipLaunchKernelGGL(potts_pair_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == LAUNCH_GPOTTS_PAIR)
     hipLaunchKernelGGL(gpotts_pair_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == LAUNCH_ISING_SMALL && algo == 0)
+    hipLaunchKernelGGL(ising_small_kernel<0>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
+  else if (model == LAUNCH_ISING_SMALL)
+    hipLaunchKernelGGL(ising_small_kernel<1>, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == 4)
     hipLaunchKernelGGL(gpotts4_sweep_kernel, dim3(nworks), dim3(tpb), lds, st, d_works, nsweeps);
   else if (model == 3 && algo == 0)
@@ -2370,6 +2390,12 @@ hipError_t set_max_lds(int bytes) {
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)gen_sweep_kernel<1>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)ising_small_kernel<0>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)ising_small_kernel<1>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)ising_sweep_kernel<0>,

@@ -178,6 +178,8 @@ constexpr int POTTS_PAIR_MAX_TPB = 768;
 // beside the model numbers 0..4 of the other sweep kernels.
 constexpr int LAUNCH_POTTS_QUAD = 5, LAUNCH_GPOTTS_QUAD = 6, LAUNCH_POTTS_PAIR = 7,
               LAUNCH_GPOTTS_PAIR = 8;
+// Launch group of the EA kernel at L = 2, 4 (a kernel of its own).
+constexpr int LAUNCH_ISING_SMALL = 9;
 constexpr int POTTS_TAB_STRIDE = 7;
 constexpr int POTTS_TAB_WORDS = 64 * POTTS_TAB_STRIDE;
 constexpr int POTTS_W_WORDS = 8;
