@@ -275,13 +275,15 @@ struct sg_job {
 
 // lanes and LDS bytes of a work item of G copies
 static size_t item_lds(const sg_job *j, int G) {
-  // Ising: copies, per-copy counters, one scratch copy for lanes without a
-  // wheel and the per-copy Metropolis threshold tables; Potts: the
+  // Ising: copies, per-copy counters (an even count of words, so that the
+  // tables are 8-byte aligned), one scratch copy for lanes without a wheel
+  // and the per-copy threshold tables; Potts: the
   // rotation-base table, copies, per-copy weight tables and counters, and
   // (when a wave can hold lanes without a wheel) the region those lanes
   // store into
   if (j->sp.model == SG_ISING)
-    return (size_t)(G + 1) * j->g.CS * 4 + (size_t)G * 4 + (size_t)G * sg::ISING_TAB_STRIDE * 4;
+    return (size_t)(G + 1) * j->g.CS * 4 + (size_t)((G + 1) & ~1) * 4 +
+           (size_t)G * sg::ISING_TAB_STRIDE * 4;
   // Ising-like: copies, per-copy threshold tables and two counters, scratch copy
   if (j->sp.model == SG_ISING_GEN)
     return (size_t)(G + 1) * j->g.CS * 4 + (size_t)G * (sg::GEN_TAB_STRIDE + 2) * 4;

@@ -534,20 +534,23 @@ DEV void drive(K &k, Drive &d) {
 
 // Metropolis with a per-copy threshold table (the LUT of the paper's update
 // cell).  The number n of unsatisfied bonds of every site of the block is
-// counted bit-sliced before the draws; each draw is compared with T[n mod 4]
-// read from the copy's LDS table (entry v at words v, 4 v and 16 v, addressed
-// by the two low count planes interleaved into bytes, one byte-select add
-// per site), and
-// the flips that are certain in advance (n >= 3, dE <= 0; or n >= m when the
-// thresholds from m on equal 2^32, beta ~ 0) are one bit-sliced compare per
-// block.  Per draw: add, xor, compare, insert and the address add.  The
-// block's couplings are loaded one block ahead.
+// counted bit-sliced before the draws; the two sites of a pair (2 p + 1, 2 p)
+// read their thresholds T[n mod 4] together, one 64-bit LDS read of the
+// copy's pair table addressed by the four low count bits of the two sites
+// (gathered into bytes, one byte-select add per pair), and the flips that
+// are certain in advance (n >= 3, dE <= 0; or n >= m when the thresholds from
+// m on equal 2^32, beta ~ 0) are one bit-sliced compare per block.  Per
+// draw: add, xor, compare, insert and half an address add.  The block's
+// couplings are loaded one block ahead.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) const u32x2 lds_u64;
+
 template <int L>
 struct IsingMetK {
   using G = IC<L>;
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK;
   IsingLane ln;
-  const uint32_t *tab;  // LDS table of the lane's copy: T[v] at words v, 4 v, 16 v (T[3] = 0)
+  const uint32_t *tab;  // LDS pair table of the lane's copy (8-byte aligned)
   uint32_t mlo, mhi;    // limit m in 0..3 of the certain flips, bits as lane masks
   uint32_t nextJ[6];    // coupling words of the next block
 
@@ -576,53 +579,69 @@ struct IsingMetK {
     // n >= m  <=>  n2 or (n1, n0) >= (mhi, mlo)
     const uint32_t below = bfi(n1 ^ mhi, mhi, ~n0 & mlo);
     const uint32_t cert = n2 | ~below;
-    // byte j of word w (= 2 t + e) is the byte offset into the table of
-    // the site at bit w + 8 j: after the bit-pair interleave its count pair
-    // (n mod 4) sits at bits 2t, 2t + 1 of byte j of z[e]; masked in place
-    // it is the offset of entry v at word v (t = 1), 4 v (t = 2) or 16 v
-    // (t = 3); pairs at t = 0 are moved up by two bits first
-    uint32_t Kw[8], z[2];
-    pair_planes(n0, n1, z[0], z[1]);
-#pragma unroll
-    for (int w = 0; w < 8; w++) {
-      const int t = w >> 1;
-      Kw[w] = t == 0 ? (z[w & 1] << 2) & 0x0C0C0C0Cu : z[w & 1] & (0x03030303u << (2 * t));
+    // pair p = 4 j + w (sites 8 j + 2 w + 1 and 8 j + 2 w): its table entry
+    // e = n0[s] + 2 n0[s+1] + 4 n1[s] + 8 n1[s+1] (s = 8 j + 2 w) times 8,
+    // the byte offset, sits in byte j of Kw[w].  X holds the nibbles of the
+    // pairs w = 0 (bits 0..3 of each byte) and w = 2 (bits 4..7), Y those of
+    // w = 1 and w = 3.
+    uint32_t Kw[4];
+    {
+      const uint32_t X = bfi(0x33333333u, n0, n1 << 2);
+      const uint32_t Y = bfi(0x33333333u, n0 >> 2, n1);
+      Kw[0] = (X << 3) & 0x78787878u;
+      Kw[1] = (Y << 3) & 0x78787878u;
+      Kw[2] = (X >> 1) & 0x78787878u;
+      Kw[3] = (Y >> 1) & 0x78787878u;
     }
     const uint32_t tbase = lds_offset(tab);
-    uint32_t T[B];
-    // threshold of draw i (site at bit B - 1 - i), read PF draws ahead
-    auto load = [&](int i) {
-      const int q = B - 1 - i;
-      T[i] = *(const lds_u32 *)(uintptr_t)add_byte(q >> 3, tbase, Kw[q & 7]);
+    constexpr int NP = B / 2;
+    // thresholds of pair P in draw order (draws 2 P and 2 P + 1: sites
+    // B - 1 - 2 P, odd, in .x and B - 2 - 2 P in .y), read PF pairs ahead
+    u32x2 T[NP];
+    uint32_t A[NP];
+    auto addr = [&](int P) {
+      const int pp = NP - 1 - P;
+      A[P] = add_byte(pp >> 2, tbase, Kw[pp & 3]);
     };
-    constexpr int PF = B < 8 ? B : 8;
+    auto read = [&](int P) { T[P] = *(lds_u64 *)(uintptr_t)A[P]; };
+    constexpr int PF = NP < 4 ? NP : 4;
 #pragma unroll
-    for (int i = 0; i < PF; i++) load(i);
+    for (int P = 0; P < PF; P++) {
+      addr(P);
+      read(P);
+    }
     __builtin_amdgcn_sched_barrier(0);
 
-    static_assert(B >= 2, "the draw pipeline needs two draws per block");
+    static_assert(B >= 2 && B % 2 == 0, "the draw pipeline needs pairs of draws");
     uint32_t acc = 0, r = 0;
     uint64_t co = 0;
     uint64_t m[B];
-    // per step: add, xor and compare of draw i + 1; the address add and
-    // read of draw i + PF; the insert of draw i (an insert directly before an
-    // SDWA address add would cost a wait state)
+    // per step: add, xor and compare of draw i + 1; the address add (i
+    // even) or the read (i odd) of the pair PF - 1 pairs past the one that
+    // draw i + 1 belongs to; the insert of draw i (an insert directly after
+    // the compare that precedes it would cost a wait state).  The compiler
+    // waits for each pair's read before its first compare.
     auto s1 = [&](int i) {
       const int k = VI * B + i;  // static after unrolling
+      const uint32_t Ti = (i & 1) ? T[i >> 1].y : T[i >> 1].x;
       met_s1(ring[k % M], ring[(k + M - 24) % M], ring[(k + M - 55) % M], ring[(k + M - 61) % M],
-             T[i], r, m[i]);
+             Ti, r, m[i]);
     };
-    // one LDS wait per two draws (group_wait)
     s1(0);
     static_for<0, B>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       if constexpr (i + 1 < B) {
-        group_wait<2, PF, B, i + 1>();
         s1(i + 1);
       } else {
         asm volatile("s_nop 1");
       }
-      if constexpr (i + PF < B) load(i + PF);
+      constexpr int Pn = i / 2 + PF;
+      if constexpr (Pn < NP) {
+        if constexpr (i % 2 == 0)
+          addr(Pn);
+        else
+          read(Pn);
+      }
       ins1(i == 0, m[i], acc, co);
     });
     __builtin_amdgcn_sched_barrier(0);
@@ -734,17 +753,20 @@ DEV void ising_run(const Work &w, uint32_t *lds) {
   const int lanes = w.ncopies * G::NW;
   const bool active = t < lanes;
   int *Ucnt = (int *)(lds + w.ncopies * G::CS);
-  uint32_t *scratch_copy = lds + w.ncopies * G::CS + w.ncopies;  // CS words
+  // CS words; the counters take an even number of words, so the tables that
+  // follow the scratch copy are 8-byte aligned (CS is even)
+  uint32_t *scratch_copy = lds + w.ncopies * G::CS + ((w.ncopies + 1) & ~1);
   uint32_t *tabs = scratch_copy + G::CS;  // [ncopies][ISING_TAB_STRIDE] thresholds
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
 
   // stage the threshold tables and the copies in LDS
   const uint32_t sbase = (uint32_t)w.copy0 * G::CS * 4u;
   for (int i = t; i < w.ncopies; i += nthr) Ucnt[i] = 0;
-  if constexpr (ALGO == 0)  // T[v] at words v, 4 v, 16 v (word 0 written thrice, same value)
-    for (int i = t; i < w.ncopies * 12; i += nthr) {
-      const int c = i / 12, k = (i % 12) >> 2, v = i & 3;
-      tabs[c * ISING_TAB_STRIDE + (v << (2 * k))] =
+  if constexpr (ALGO == 0)  // pair entry e: T[v1], T[v0] at words 2 e, 2 e + 1
+    for (int i = t; i < w.ncopies * 32; i += nthr) {
+      const int c = i >> 5, e = (i & 31) >> 1;
+      const int v = (i & 1) ? (e & 1) | ((e >> 1) & 2) : ((e >> 1) & 1) | ((e >> 2) & 2);
+      tabs[c * ISING_TAB_STRIDE + (i & 31)] =
           v < 3 ? w.thr[w.temp_of_slot[w.copy0 + c] * THR_WORDS + v] : 0u;
     }
   else  // heat bath: entry m holds T_HB[6 - m]
@@ -2247,7 +2269,7 @@ __global__ void debug_rng_kernel(const uint32_t *__restrict__ wheels, uint32_t *
 template <int ALGO>
 __global__ __launch_bounds__(1024) void ising_sweep_kernel(const Work *__restrict__ works,
                                                           int nsweeps) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   Work w = works[blockIdx.x];
   w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
   switch (w.L) {
@@ -2269,7 +2291,7 @@ __global__ __launch_bounds__(1024) void ising_sweep_kernel(const Work *__restric
 template <int ALGO>
 __global__ __launch_bounds__(1024) void ising_small_kernel(const Work *__restrict__ works,
                                                           int nsweeps) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   Work w = works[blockIdx.x];
   w.nsweeps_cap = min(w.nsweeps_cap, nsweeps);
   switch (w.L) {

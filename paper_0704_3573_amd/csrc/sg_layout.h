@@ -200,12 +200,14 @@ SG_HD constexpr int gen_js(int L) { return gen_block_js(L) + igeom(L).CS; }
 // LDS threshold table of a copy: 32 words at an odd stride (bank spread).
 constexpr int GEN_TAB_STRIDE = 33;
 
-// Ising: LDS threshold table of a copy at an odd stride of 49 words.
-// Metropolis: T[v] (v = n mod 4 of the unsatisfied-bond count n, T[3] = 0)
-// at words v, 4 v and 16 v (the count pair read at byte offsets 4 v, 16 v
-// or 64 v, by its position in the byte); heat bath: T_HB[6 - m] at words
-// m = 0..6, then 0.
-constexpr int ISING_TAB_STRIDE = 49;
+// Ising: LDS threshold table of a copy at a stride of 40 words (8-byte
+// aligned; copies sharing a wave start on different banks).  Metropolis:
+// thresholds of site pairs, with T[v] for v = n mod 4 of a site's
+// unsatisfied-bond count n (T[3] = 0): entry e = 0..15 at words 2 e, 2 e + 1
+// holds T[v1], T[v0] for the odd site (v1 = bit 1 of e + 2 * bit 3) and the
+// even site (v0 = bit 0 of e + 2 * bit 2) of a pair of consecutive sites;
+// heat bath: T_HB[6 - m] at words m = 0..6, then 0.
+constexpr int ISING_TAB_STRIDE = 40;
 
 // Per-temperature threshold row: 32 words.  Ising Metropolis uses [0..2],
 // heat bath [0..6], Potts [0..12]; a threshold equal to 2^32 is stored as
