@@ -292,7 +292,7 @@ static size_t item_lds(const sg_job *j, int G) {
     return (size_t)48 * 4 + (size_t)G * sg::potts4_lds_copy(j->L) + (size_t)G * sg::POTTS4_W_WORDS * 4 +
            (size_t)G * 4 + dummy4;
   }
-  const size_t dummy = j->lanes() % 64 ? (size_t)j->g.RHO * j->L * j->L : 0;
+  const size_t dummy = j->lanes() % 64 ? (size_t)j->g.RHO * j->L * sg::potts_xs(j->L) : 0;
   return (size_t)sg::POTTS_TAB_WORDS * 4 + (size_t)G * sg::potts_lds_copy(j->L) +
          (size_t)G * sg::POTTS_W_WORDS * 4 + (size_t)G * 4 + dummy;
 }

@@ -1119,6 +1119,7 @@ DEV void gen_run(const Work &w, uint32_t *lds) {
 template <int L, bool GLASSY>
 struct PottsK {
   using G = GC<L>;
+  static_assert(potts_xs(L) == L, "the one-lane kernel uses an x stride of L bytes");
   static constexpr int M = G::M, B = G::B, V = G::V, NBLK = G::NBLK, H = G::H, RPB = G::RPB,
                        RHO = G::RHO, NW = G::NW, BQ = GLASSY ? G::B : potts_bq(L);
   uint8_t *sp;          // LDS bytes of the lane's copy, [y][x][z] (rows at row(y)), 8 sigma
@@ -1434,6 +1435,7 @@ struct PottsMK {
   static constexpr int NBLK = G::NBLK, H = G::H, RPB = G::RPB, RHO = G::RHO, NW = G::NW;
   static constexpr int MS = G::M;                    // HBM ring slots of a wheel
   static constexpr int BQ = GLASSY ? B : potts_bq(L);  // coupling words per block and lane
+  static constexpr int XS = potts_xs(L);             // LDS byte stride of x
   uint8_t *sp;          // LDS bytes of the lane's copy, [y][x][z] (rows at row(y)), 8 sigma
   uint8_t *wp;          // where the lane stores its new spins: sp, or the dummy region
   const uint32_t *tab;  // LDS table: rotation bases (+-J) or vote words (glassy)
@@ -1448,7 +1450,7 @@ struct PottsMK {
   int kmod0, kmod1;       // first draw of the launch (and of the next one) mod MS
   uint32_t nextpat[BQ];
 
-  static DEV int row(int y) { return y * L * L + (y / RHO) * 2 * L; }
+  static DEV int row(int y) { return y * L * XS + (y / RHO) * 2 * L; }
 
   DEV void init_lane(int t) {
     sub = t % S;
@@ -1522,11 +1524,11 @@ struct PottsMK {
       const int y = y0 + rr;
       const int e = (p + y + z) & 1;
       const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
-      const int lane = 2 * sub * L;
-      base[rr] = row(y) + e * L + z + lane;
-      bxw[rr] = row(y) + z + (e ? 0 : (L - 1) * L);
-      byp[rr] = row(yp) + e * L + z + lane;
-      bym[rr] = row(ym) + e * L + z + lane;
+      const int lane = 2 * sub * XS;
+      base[rr] = row(y) + e * XS + z + lane;
+      bxw[rr] = row(y) + z + (e ? 0 : (L - 1) * XS);
+      byp[rr] = row(yp) + e * XS + z + lane;
+      bym[rr] = row(ym) + e * XS + z + lane;
     }
     const int dzp = zp - z, dzm = zm - z;
     uint32_t nb[B][6], rb[B][6], w[B][4];
@@ -1534,20 +1536,22 @@ struct PottsMK {
     // step i: draw S i + sub of the block, row rr = S i / H, in-row index
     // j = S i mod H + sub (H is a multiple of S)
     auto request_site = [&](int i) {
-      const int rr = S * i / H, jb = S * i - rr * H, o = 2 * jb * L;
+      const int rr = S * i / H, jb = S * i - rr * H, o = 2 * jb * XS;
       if constexpr (GLASSY) {
 #pragma unroll
         for (int d = 0; d < 6; d++) rb[i][d] = tb[(d & 1) * 24 + ((pat[i] >> (5 * d)) & 31u)];
       } else {
-        // word (S i) / 4, byte (S i) mod 4 + sub
-        const uint32_t *r6 =
-            tb + POTTS_TAB_STRIDE * ((pat[(S * i) >> 2] >> (sh + 8 * ((S * i) & 3))) & 0xFFu);
+        // word (S i) / 4, byte (S i) mod 4 + sub; the entry of the
+        // pattern's bits 0..4 gives directions 0..4, bit 5 the sixth word
+        const uint32_t pb = pat[(S * i) >> 2] >> (sh + 8 * ((S * i) & 3));
+        const uint32_t *r5 = tb + POTTS_TAB_STRIDE * (pb & 31u);
 #pragma unroll
-        for (int d = 0; d < 6; d++) rb[i][d] = r6[d];
+        for (int d = 0; d < 5; d++) rb[i][d] = r5[d];
+        rb[i][5] = bfi((uint32_t)((int32_t)(pb << 26) >> 31), 0x04040400u, 4u);
       }
       const int c = base[rr] + o;
-      const int xp = jb == H - S ? (int)bfi(mlast, (uint32_t)bxw[rr], (uint32_t)(c + L)) : c + L;
-      const int xm = jb == 0 ? (int)bfi(m0, (uint32_t)bxw[rr], (uint32_t)(c - L)) : c - L;
+      const int xp = jb == H - S ? (int)bfi(mlast, (uint32_t)bxw[rr], (uint32_t)(c + XS)) : c + XS;
+      const int xm = jb == 0 ? (int)bfi(m0, (uint32_t)bxw[rr], (uint32_t)(c - XS)) : c - XS;
       nb[i][0] = rd[xp];
       nb[i][1] = rd[xm];
       nb[i][2] = rd[byp[rr] + o];
@@ -1587,7 +1591,7 @@ struct PottsMK {
       const uint32_t t = __umulhi(r, C2 + w[i][3]);
       const uint32_t nt = ~t;
       const uint32_t v = (((w[i][0] + nt) >> 31) + ((C1 + nt) >> 31) + ((C2 + nt) >> 31)) << 3;
-      wr[base[rr] + 2 * jb * L] = (uint8_t)v;
+      wr[base[rr] + 2 * jb * XS] = (uint8_t)v;
     };
 
     request_site(0);
@@ -1616,10 +1620,10 @@ struct PottsMK {
         const int y = y0 + rr;
         const int e = (y + z) & 1;
         const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
-        const int c = row(y) + (2 * j + e) * L + z;
+        const int c = row(y) + (2 * j + e) * XS + z;
         const int xpi = (2 * j + e + 1) % L, xmi = (2 * j + e + L - 1) % L;
-        const int nb[6] = {row(y) + xpi * L + z, row(y) + xmi * L + z,
-                           row(yp) + (2 * j + e) * L + z, row(ym) + (2 * j + e) * L + z,
+        const int nb[6] = {row(y) + xpi * XS + z, row(y) + xmi * XS + z,
+                           row(yp) + (2 * j + e) * XS + z, row(ym) + (2 * j + e) * XS + z,
                            c - z + zp, c - z + zm};
         const uint32_t si = sp[c];
         if constexpr (GLASSY) {
@@ -1646,8 +1650,13 @@ DEV void potts_multi_run(const Work &w, uint32_t *lds) {
   using K = PottsMK<L, GLASSY, S>;
   constexpr int N3 = L * L * L;
   constexpr int CW = potts_lds_copy(L) / 4;  // LDS words per copy
-  constexpr int GW = G::RHO * L * L / 4;     // HBM words per row group
+  constexpr int XW = potts_xs(L) / 4;        // LDS words per x step
   constexpr int LPC = S * G::NW;             // lanes per copy
+  // LDS word of HBM word u of a copy (u = (y L + x) L / 4 + z / 4)
+  auto lds_word = [](int u) {
+    const int y = u / (L * L / 4), x = (u / (L / 4)) % L;
+    return (y * L * potts_xs(L) + (y / G::RHO) * 2 * L) / 4 + x * XW + u % (L / 4);
+  };
   const int t = threadIdx.x;
   const int nthr = blockDim.x;
   const bool active = t < w.ncopies * LPC;
@@ -1655,7 +1664,7 @@ DEV void potts_multi_run(const Work &w, uint32_t *lds) {
   uint32_t *cp = lds + POTTS_TAB_WORDS;
   uint32_t *Wt = cp + w.ncopies * CW;
   int *Hcnt = (int *)(Wt + w.ncopies * POTTS_W_WORDS);
-  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);  // RHO L^2 bytes if LPC % 64 != 0
+  uint8_t *dummy = (uint8_t *)(Hcnt + w.ncopies);  // RHO L XS bytes if LPC % 64 != 0
   const rsrc_t rsp = make_rsrc(w.spins, w.spins_bytes);
   const uint32_t sbase = (uint32_t)w.copy0 * N3;
   potts_tables<GLASSY>(tab);
@@ -1667,7 +1676,7 @@ DEV void potts_multi_run(const Work &w, uint32_t *lds) {
       w.ncopies * (N3 / 4), [&](int i) { return bload(rsp, i * 4, sbase); },
       [&](int i, uint32_t v) {
         const int c = i / (N3 / 4), u = i - c * (N3 / 4);
-        cp[c * CW + u + (u / GW) * L / 2] = v;
+        cp[c * CW + lds_word(u)] = v;
       });
   for (int i = t; i < w.ncopies; i += nthr) Hcnt[i] = 0;
 
@@ -1713,7 +1722,7 @@ DEV void potts_multi_run(const Work &w, uint32_t *lds) {
   if (w.nsweeps_cap > 0)
     for (int i = t; i < w.ncopies * (N3 / 4); i += nthr) {
       const int c = i / (N3 / 4), u = i - c * (N3 / 4);
-      bstore(rsp, cp[c * CW + u + (u / GW) * L / 2], i * 4, sbase);
+      bstore(rsp, cp[c * CW + lds_word(u)], i * 4, sbase);
     }
   for (int i = t; i < w.ncopies; i += nthr) w.E[w.copy0 + i] = -(int64_t)Hcnt[i];
 }

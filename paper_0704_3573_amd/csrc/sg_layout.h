@@ -155,15 +155,16 @@ constexpr int POTTS4_W_WORDS = 12;
 
 // Potts work items: at most 512 lanes per workgroup (the kernel keeps up to
 // 256 VGPRs per lane).  LDS = the 64-entry rotation-base table (6 words per
-// coupling pattern at an odd stride of 7 words, so that lanes reading
-// different entries hit different banks), then the copies, then per copy 8
-// weight words and 1 counter.  In LDS a copy's row y starts at byte
-// y L^2 + (y / RHO) 2L (each row group is skewed by 2L bytes) and copies are
-// potts_lds_copy(L) bytes apart (= N + 2 NG L, 0 mod 4).  The lanes of one
-// row group (consecutive z, sites x = 2j + e with e alternating in z) touch
-// a 2L-byte window of a row; with these offsets the windows of the row
-// groups and copies of a wave are consecutive modulo 256 bytes, i.e. they
-// fall on distinct LDS banks.
+// coupling pattern at an odd stride of 7 words; the kernels with several
+// lanes per wheel index it by the pattern's bits 0..4 only, so the 32
+// entries a read can touch lie on 32 distinct banks, and form the sixth
+// word from bit 5), then the copies, then per copy 8 weight words and 1
+// counter.  In LDS a copy's row y starts at byte y L XS + (y / RHO) 2L (XS =
+// potts_xs(L), the x stride; each row group is skewed by 2L bytes) and
+// copies are potts_lds_copy(L) bytes apart (0 mod 4).  The lanes of one row
+// group (consecutive z, sites x = 2j + e with e alternating in z) touch a
+// 2 XS-byte window of a row; with these offsets the windows of the row
+// groups and copies of a wave fall on distinct LDS banks.
 constexpr int POTTS_MAX_TPB = 512;
 // Lanes per wheel of the 3D Potts kernels (the wheel's outputs are formed S
 // at a time, lane l taking those with index = l mod S): four where L/2 is a
@@ -183,7 +184,16 @@ constexpr int LAUNCH_ISING_SMALL = 9;
 constexpr int POTTS_TAB_STRIDE = 7;
 constexpr int POTTS_TAB_WORDS = 64 * POTTS_TAB_STRIDE;
 constexpr int POTTS_W_WORDS = 8;
-SG_HD constexpr int potts_lds_copy(int L) { return (L * L * L + 2 * geom(L).NG * L + 3) / 4 * 4; }
+// Byte stride of x in a copy's LDS rows (z fastest, then x, then y).  At
+// L = 32 the four lanes of a wheel read sites 2 x-steps apart, 64 bytes with
+// an x stride of L: 16 words, so lanes 0 and 2 of every wheel would share a
+// bank.  The 64 lanes of a wave (16 wheels of consecutive z, four lanes
+// each; even and odd z planes one x-step apart) read 32 distinct words;
+// with a stride of 48 bytes they lie on 32 distinct banks.
+SG_HD constexpr int potts_xs(int L) { return L == 32 ? 48 : L; }
+SG_HD constexpr int potts_lds_copy(int L) {
+  return (L * L * potts_xs(L) + 2 * geom(L).NG * L + 3) / 4 * 4;
+}
 
 // Ising-like models of Eq. (2) of the paper (dilution x_i, field h_i =
 // |h| f_i): spins as for the EA glass.  Per (colour p, block word wb, plane z)
