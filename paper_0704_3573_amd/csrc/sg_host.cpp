@@ -1376,7 +1376,7 @@ struct sg_batch {
   std::vector<void *> graph_bufs;  // device buffers referenced by captured graphs
   std::map<std::vector<int>, PtTable> pt_cache;
   hipStream_t cap_stream = nullptr;
-  std::vector<hipStream_t> side;  // parallel branches while capturing
+  std::vector<hipStream_t> side;  // streams of the concurrent launches
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   bool timing = false;
@@ -1480,11 +1480,14 @@ static int plan(sg_batch *b) {
   if (rc) return rc;
   size_t total = 0;
   for (auto &l : b->launches) total += l.items.size();
+  // device tables grow geometrically: a serving loop adds jobs one by one,
+  // and every hipFree waits for the whole device
   if (total > b->d_items_cap) {
+    const size_t cap = std::max<size_t>({total, 2 * b->d_items_cap, 256});
     if (b->d_items) HIPCHK(hipFree(b->d_items));
     b->d_items = nullptr;
-    HIPCHK(hipMalloc(&b->d_items, std::max<size_t>(total, 1) * sizeof(Work)));
-    b->d_items_cap = total;
+    HIPCHK(hipMalloc(&b->d_items, cap * sizeof(Work)));
+    b->d_items_cap = cap;
   }
   size_t off = 0;
   for (auto &l : b->launches) {
@@ -1502,11 +1505,14 @@ static int plan(sg_batch *b) {
     b->join.push_back(ev);
   }
   if (b->jobs.size() > b->d_jobs_cap) {
+    const size_t cap = std::max<size_t>({b->jobs.size(), 2 * b->d_jobs_cap, 64});
     if (b->d_done) HIPCHK(hipFree(b->d_done));
     if (b->d_cap) HIPCHK(hipFree(b->d_cap));
-    HIPCHK(hipMalloc(&b->d_done, b->jobs.size() * sizeof(uint64_t *)));
-    HIPCHK(hipMalloc(&b->d_cap, b->jobs.size() * sizeof(int32_t)));
-    b->d_jobs_cap = b->jobs.size();
+    b->d_done = nullptr;
+    b->d_cap = nullptr;
+    HIPCHK(hipMalloc(&b->d_done, cap * sizeof(uint64_t *)));
+    HIPCHK(hipMalloc(&b->d_cap, cap * sizeof(int32_t)));
+    b->d_jobs_cap = cap;
   }
   std::vector<uint64_t *> done;
   std::vector<int32_t> cap;
@@ -1569,9 +1575,12 @@ static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs,
   const bool capturing = st == b->cap_stream;
   const bool timed = b->timing && !capturing;
   if (timed) HIPCHK(hipEventRecord(b->ev0, st));
-  // the fused launches; while capturing, they become parallel branches of
-  // the graph
-  const bool fork = capturing && b->launches.size() > 1;
+  // the fused launches run concurrently: side streams forked from and joined
+  // back to the caller's stream (while capturing, parallel branches of the
+  // graph).  A batch whose membership changes often (serving) launches its
+  // periods directly, and one launch after another would last as long as the
+  // sum of the launches' durations rather than the longest.
+  const bool fork = b->launches.size() > 1;
   if (fork) HIPCHK(hipEventRecord(b->fork, st));
   for (size_t g = 0; g < b->launches.size(); g++) {
     const Launch &l = b->launches[g];
