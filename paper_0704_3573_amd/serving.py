@@ -31,7 +31,9 @@ from __future__ import annotations
 import concurrent.futures as cf
 import dataclasses
 import hashlib
+import threading
 import time
+import collections
 from collections import deque
 from typing import Optional
 
@@ -110,14 +112,20 @@ class DeviceBackend:
     """Jobs and batches of libsg on one GPU (arenas are torch tensors).
 
     Periods run on `stream` (a new non-blocking torch stream by default);
-    jobs are created by one worker thread on a creation stream of its own."""
+    jobs are created by `workers` threads, each on a creation stream of its
+    own (a job's instance is generated on the host from its seed, then
+    uploaded)."""
 
-    def __init__(self, ctx, stream=None):
+    def __init__(self, ctx, stream=None, workers=2):
         import torch
         self.ctx = ctx
         self.stream = stream if stream is not None else torch.cuda.Stream()
-        self.create_stream = torch.cuda.Stream()
-        self.pool = cf.ThreadPoolExecutor(max_workers=1)
+        # creation streams made here, on the caller's thread; each worker
+        # thread takes one the first time it creates a job
+        self._streams = [torch.cuda.Stream() for _ in range(workers)]
+        self._local = threading.local()
+        self._lock = threading.Lock()
+        self.pool = cf.ThreadPoolExecutor(max_workers=workers)
         self.busy = []  # timing events around each period
 
     def new_batch(self):
@@ -128,9 +136,13 @@ class DeviceBackend:
 
     def _create(self, req):
         import torch
-        with torch.cuda.stream(self.create_stream):
+        st = getattr(self._local, "stream", None)
+        if st is None:
+            with self._lock:
+                st = self._local.stream = self._streams.pop()
+        with torch.cuda.stream(st):
             arena = torch.empty(job_bytes(req), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
-            return make_job(self.ctx, req, arena, self.create_stream)
+            return make_job(self.ctx, req, arena, st)
 
     def create_async(self, req):
         return self.pool.submit(self._create, req)
@@ -197,6 +209,8 @@ class Server:
         self.inflight = deque()     # events of enqueued periods
         self.done = []
         self.periods = 0
+        self.changes = 0            # membership changes (each re-plans the batch)
+        self.host_s = collections.Counter()  # host seconds per loop step
         self.n = 1                  # sweeps per run (the largest per-run cap)
 
     def _admit(self):
@@ -265,6 +279,20 @@ class Server:
         self.inflight.append(self.be.launch(self.batch, self.n))
         self.periods += 1
 
+    def release(self):
+        """Release every job the server still holds (after serve() stopped at
+        its wall-clock cap): the periods in flight are waited for and the
+        jobs still being created are taken and closed."""
+        self._drain()
+        for req, h, nb in list(self.creating):
+            self.be.take(h).close()
+        self.creating.clear()
+        for job, req, nb in list(self.active.values()):
+            self.batch.remove(job)
+            job.close()
+        self.active.clear()
+        self.used = 0
+
     def updates_done(self) -> int:
         """Site updates enqueued so far (finished jobs and the resident ones)."""
         return sum(r.updates() for r in self.done) + sum(
@@ -291,19 +319,31 @@ class Server:
             if finished or ready:
                 # membership changes at a period boundary: let the enqueued
                 # periods end, release finished jobs, add the new ones
+                ta = clock()
                 self._drain()
-                now = clock() - t0
+                tb = clock()
+                now = tb - t0
                 self._harvest(finished, now)
                 self._join(ready, now)
                 self._set_caps()
                 self._admit()
+                self.changes += 1
+                self.host_s["drain"] += tb - ta
+                self.host_s["change"] += clock() - tb
             if self.active and len(self.inflight) < self.depth:
+                ta = clock()
                 self._launch()
+                self.host_s["launch"] += clock() - ta
             elif self.inflight:
+                ta = clock()
                 self.be.wait(self.inflight[0])
+                self.host_s["wait"] += clock() - ta
             elif i < len(reqs) or self.creating:
-                nxt = reqs[i].arrival - (clock() - t0) if i < len(reqs) else 0.0
-                sleep(max(0.0, min(0.002, nxt)))
+                # nothing on the device: wait for the next arrival or for a
+                # job being created (never a zero-length sleep, which would
+                # keep the interpreter lock from the creating threads)
+                nxt = reqs[i].arrival - (clock() - t0) if i < len(reqs) else 0.002
+                sleep(max(0.0005, min(0.002, nxt)))
         self._drain()
         return self.done
 

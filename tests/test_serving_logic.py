@@ -172,3 +172,16 @@ def test_wall_clock_cap_stops_with_work_left():
     done = srv.serve(reqs, clock=clock, sleep=clock.sleep, cap_s=0.01)
     assert [r.rid for r in done] == [1] and reqs[0].t_done is None
     assert srv.updates_done() > reqs[1].updates()
+
+
+def test_release_after_the_cap_closes_every_job():
+    reqs = [Request(i, "ising", 8, 1.0, 10 ** 6, i) for i in range(6)]
+    clock = Clock()
+    be = FakeBackend(clock)
+    srv = Server(be, hbm_budget=10 ** 9, max_slots=4, period=100)
+    srv.serve(reqs, clock=clock, sleep=clock.sleep, cap_s=0.001)
+    held = [job for job, _, _ in srv.active.values()]
+    assert held and not srv.done
+    srv.release()
+    assert all(j.closed for j in held) and not srv.active and not srv.creating
+    assert srv.used == 0 and srv.batch.jobs == []
