@@ -88,11 +88,14 @@ def make_job(ctx, req: Request, arena=None, stream=None) -> B.Job:
 def sweep_cost(req: Request) -> float:
     """Relative device time of one sweep of a request's job: draws per lane
     per sweep (min(8, L) rows of L sites per wheel, shared by the lanes of
-    the wheel: four for the Potts model at L = 8..32) times the cost of a
-    draw per lane (a Potts heat-bath update about eight Ising Metropolis
-    ones, from the measured per-lane rates of the two kernels).  Only a
-    scheduling estimate: it sets how many sweeps each job runs in a period."""
-    lanes = 4 if req.model == "potts" and req.L in (8, 16, 24, 32) else 1
+    the wheel: four for the Potts model at L = 8..32, two at L = 40, 48)
+    times the cost of a draw per lane (a Potts heat-bath update about eight
+    Ising Metropolis ones, from the measured per-lane rates of the two
+    kernels).  Only a scheduling estimate: it sets how many sweeps each job
+    runs in a period."""
+    lanes = 1
+    if req.model == "potts":
+        lanes = 4 if req.L in (8, 16, 24, 32) else 2 if req.L in (40, 48) else 1
     return min(8, req.L) * req.L / lanes * (8.0 if req.model == "potts" else 1.0)
 
 

@@ -154,11 +154,12 @@ def test_periods_give_every_job_the_same_device_time():
     from paper_0704_3573_amd.serving import sweep_cost
     reqs = [Request(0, "ising", 8, 1.0, 700, 0), Request(1, "ising", 16, 1.0, 2000, 1),
             Request(2, "potts", 48, 1.0, 90, 2)]
-    assert sweep_cost(reqs[2]) == 8 * 48 * 8 and sweep_cost(reqs[1]) == 2 * sweep_cost(reqs[0])
+    # an L = 48 Potts wheel is served by two lanes
+    assert sweep_cost(reqs[2]) == 8 * 48 * 8 / 2 and sweep_cost(reqs[1]) == 2 * sweep_cost(reqs[0])
     srv, be, done = run(reqs, budget=10 ** 9, slots=8, period=30)
-    # period 1: the L = 48 Potts job runs 30 sweeps; the L = 16 job 30 * 3072
-    # / 128 = 720, the L = 8 one 1440, capped at its 700
-    assert srv.batch.runs[0] == (720, 3)
+    # period 1: the L = 48 Potts job runs 30 sweeps; the L = 16 job 30 * 1536
+    # / 128 = 360, the L = 8 one 720, capped at its 700
+    assert srv.batch.runs[0] == (700, 3)
     assert [r.rid for r in done][0] == 0
     assert all(r.E == [r.sweeps, -r.sweeps] for r in done) and len(done) == 3
     assert srv.updates_done() == sum(r.updates() for r in done)
