@@ -149,6 +149,12 @@ static void threshold_row(int model, int algo, double beta, uint32_t row[sg::THR
 }
 
 // ------------------------------------------------------------------- ctx --
+// chains per fused PT work item: the decisions of a chain are sequential,
+// so a launch's time is one chain's decisions plus the staging of its
+// workgroup's wheels, energies and permutations; small items keep the
+// staging short and spread it over many CUs
+static const int PT_CHAINS_PER_ITEM = 16;
+
 struct sg_ctx {
   int device;
   int max_lds;
@@ -245,7 +251,7 @@ static Layout layout(const sg_job_spec *sp) {
   l.Mf = o; o = al(o + C * 8);
   l.dbg = o; o = al(o + 4096 * 4);
   l.works = o; o = al(o + C * sizeof(Work));
-  l.ptworks = o; o = al(o + ((S * R + 63) / 64) * sizeof(PtWork));
+  l.ptworks = o; o = al(o + ((S * R + PT_CHAINS_PER_ITEM - 1) / PT_CHAINS_PER_ITEM) * sizeof(PtWork));
   l.total = o;
   return l;
 }
@@ -371,7 +377,7 @@ static void xcd_order(std::vector<Work> &v) {
 static const int PT_FUSED_KMAX = 64;
 
 static void make_pt_works(const sg_job *j, std::vector<PtWork> &out) {
-  for (int c0 = 0; c0 < j->chains; c0 += 64) {
+  for (int c0 = 0; c0 < j->chains; c0 += PT_CHAINS_PER_ITEM) {
     PtWork w{};
     w.E = j->at<int64_t>(j->lay.E);
     w.slot_of_temp = j->at<int32_t>(j->lay.sot);
@@ -381,7 +387,7 @@ static void make_pt_works(const sg_job *j, std::vector<PtWork> &out) {
     w.sgn = j->at<int32_t>(j->lay.sgn);
     w.accepts = j->at<uint64_t>(j->lay.acc);
     w.chain0 = c0;
-    w.nchains = std::min(64, j->chains - c0);
+    w.nchains = std::min(PT_CHAINS_PER_ITEM, j->chains - c0);
     w.K = j->K;
     out.push_back(w);
   }
@@ -954,7 +960,8 @@ int sg_job_set_betas(sg_job *job, const double *betas, void *stream) {
 
 static int run_pt(sg_job *j, hipStream_t st) {
   if (j->K <= PT_FUSED_KMAX) {
-    HIPCHK(sg::launch_pt_fused(j->at<PtWork>(j->lay.ptworks), (j->chains + 63) / 64, j->K, st));
+    HIPCHK(sg::launch_pt_fused(j->at<PtWork>(j->lay.ptworks),
+                               (j->chains + PT_CHAINS_PER_ITEM - 1) / PT_CHAINS_PER_ITEM, j->K, st));
     return SG_OK;
   }
   HIPCHK(sg::launch_pt(j->at<int64_t>(j->lay.E), j->at<int32_t>(j->lay.sot), j->at<int32_t>(j->lay.tos),

@@ -14,12 +14,15 @@
 //  * the B sites served by those draws are one 32-bit word of the bit-packed
 //    lattice; the six-neighbour bond count is computed bit-sliced on whole
 //    words (32 sites per operation) from LDS-resident neighbour words, and
-//    each site's threshold is read from the copy's small LDS table indexed by
-//    its count (the LUT of the paper's update cell);
+//    the thresholds are read from the copy's small LDS table indexed by the
+//    counts (the LUT of the paper's update cell; Metropolis reads the two
+//    sites of a pair at once);
 //  * each draw is compared with its site's threshold and the compare result
 //    (a 64-lane mask) is shifted into a per-lane accumulator word with
-//    add-with-carry, so the per-site work is draw + address + compare +
-//    insert;
+//    add-with-carry, so the per-site work is draw + compare + insert + the
+//    table address (half of one for Metropolis);
+//  * the 3D Potts kernels share each wheel between four or two lanes (the
+//    multi-output wheel of sec. 3.3, see PottsMK);
 //  * the copies' spins stay in LDS for the whole launch; a workgroup barrier
 //    separates the two colours (sec. 3.1: same-colour sites never interact).
 #include <hip/hip_runtime.h>
@@ -2218,9 +2221,16 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
   if (t >= nch) return;
   const int ch = w.chain0 + t;
   uint64_t accepted = 0;  // bit i: the swap of temperatures i, i + 1 was accepted
+  // the configuration at temperature i is carried upward: after step i it is
+  // at i + 1 if the swap was accepted, else the one read from i + 1 is; so
+  // the slot and energy read at i + 1 never depend on earlier decisions and
+  // only (Sc, Ec) does
+  int Sc = so[0];
+  int32_t Ec = Es[Sc];
   for (int i = 0; i + 1 < K; i++) {
-    const int a = so[i], b = so[i + 1];
-    const int32_t D = Es[b] - Es[a];
+    const int a = Sc, b = so[i + 1];
+    const int32_t Eb = Es[b];
+    const int32_t D = Eb - Ec;
     const uint32_t r = ptw_next(ring);
     const int sd = D > 0 ? 1 : (D < 0 ? -1 : 0);
     bool accept;
@@ -2242,10 +2252,14 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
     }
     if (accept) {
       so[i] = b;
-      so[i + 1] = a;
       accepted |= 1ull << i;
+    } else {
+      so[i] = a;
+      Sc = b;
+      Ec = Eb;
     }
   }
+  so[K - 1] = Sc;
   // each counter belongs to this thread alone; atomics whose result is not
   // used leave the thread without a dependent load per accepted swap
   if (w.accepts)
