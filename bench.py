@@ -504,10 +504,11 @@ def main():
         batch.set_block(args.block)
     elif not args.no_tune:
         from paper_0704_3573_amd import autotune
-        tpb, tune_times = autotune.tune(batch, C3_PT, periods=2, stream=stream, use_cache=False)
+        tpb, tune_times = autotune.tune(batch, C3_PT, periods=5, stream=stream, use_cache=False)
         # keep the block the committed counter summary was taken on unless
-        # another one is clearly faster (within 1 % they tie in timing noise)
-        if tpb != PROFILED_BLOCK and tune_times.get(PROFILED_BLOCK, float("inf")) <= 1.01 * tune_times[tpb]:
+        # another one is clearly faster (within 3 % they tie: 512 and 1024
+        # differ by about 1 %, and run-to-run noise reaches 1.5 %)
+        if tpb != PROFILED_BLOCK and tune_times.get(PROFILED_BLOCK, float("inf")) <= 1.03 * tune_times[tpb]:
             tpb = PROFILED_BLOCK
             batch.set_block(tpb)
         log(f"[bench] autotuned block: {tpb} threads "
