@@ -34,6 +34,10 @@
  * of the last error on the calling thread is returned by sg_last_error().  No
  * C++ exception crosses this boundary.  Device errors raised asynchronously
  * surface at the next call that synchronises.
+ * Test hook: when the environment variable SG_TEST_INJECT_HIP_ERROR holds
+ * the name of sg_job_create, sg_job_sweep, sg_job_measure, sg_job_restore,
+ * sg_batch_run, sg_batch_run_static or sg_threshold_row, that call returns
+ * SG_E_HIP at entry, before it changes any state (fault-path tests).
  *
  * Ownership: handles are created and released by the library.  Device memory
  * of a job (its "arena") is owned by the caller: ask sg_job_bytes(), allocate

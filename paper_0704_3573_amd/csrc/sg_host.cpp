@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -60,6 +61,17 @@ static int fail(int code, const char *fmt, ...) {
     hipError_t e_ = (x);                                                             \
     if (e_ != hipSuccess) return fail(SG_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
+
+// Test hook: when the environment variable SG_TEST_INJECT_HIP_ERROR names
+// an entry point that checks it, that call fails with SG_E_HIP before it
+// touches any state, as if the device had reported an error.
+static bool injected(const char *fn) {
+  const char *e = std::getenv("SG_TEST_INJECT_HIP_ERROR");
+  return e && std::strcmp(e, fn) == 0;
+}
+#define INJECTION_POINT()                                                               \
+  if (injected(__func__))                                                               \
+    return fail(SG_E_HIP, "%s: injected device error (SG_TEST_INJECT_HIP_ERROR)", __func__)
 
 #define GUARD_BEGIN try {
 #define GUARD_END                                     \
@@ -708,6 +720,7 @@ int32_t sg_model_wheels_per_copy(int32_t model, int32_t L) {
 
 int sg_threshold_row(int32_t model, int32_t algo, double beta, double field, uint32_t row[32]) {
   GUARD_BEGIN
+  INJECTION_POINT();
   if (!row) return fail(SG_E_INVALID, "row is NULL");
   if (model < SG_ISING || model > SG_GPOTTS4) return fail(SG_E_INVALID, "bad model %d", model);
   if (algo != SG_METROPOLIS && algo != SG_HEATBATH) return fail(SG_E_INVALID, "bad algo %d", algo);
@@ -776,6 +789,7 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
                   const int32_t *slot_of_temp, uint64_t sweeps_done, void *d_arena,
                   uint64_t arena_bytes, void *stream, sg_job **out) {
   GUARD_BEGIN
+  INJECTION_POINT();
   if (!ctx || !out) return fail(SG_E_INVALID, "ctx or out is NULL");
   int rc = check_spec(spec);
   if (rc) return rc;
@@ -979,6 +993,7 @@ static int launch_own(sg_job *j, int n, hipStream_t st) {
 
 int sg_job_sweep(sg_job *job, uint64_t n_sweeps, void *stream) {
   GUARD_BEGIN
+  INJECTION_POINT();
   if (!job) return fail(SG_E_INVALID, "job is NULL");
   hipStream_t st = S_(stream);
   uint64_t left = n_sweeps;
@@ -1014,6 +1029,7 @@ int sg_job_sweep_beta(sg_job *job, double beta, uint64_t n_sweeps, void *stream)
 
 int sg_job_measure(sg_job *job, int64_t *E, int64_t *Q, void *stream) {
   GUARD_BEGIN
+  INJECTION_POINT();
   if (!job) return fail(SG_E_INVALID, "job is NULL");
   hipStream_t st = S_(stream);
   int rc = launch_own(job, 0, st);  // energy only
@@ -1223,6 +1239,7 @@ int sg_job_checkpoint(sg_job *job, void *host_buf, uint64_t bytes, void *stream)
 
 int sg_job_restore(sg_job *j, const void *host_buf, uint64_t bytes, void *stream) {
   GUARD_BEGIN
+  INJECTION_POINT();
   if (!j || !host_buf) return fail(SG_E_INVALID, "NULL argument");
   CkHeader h;
   if (bytes < sizeof h) return fail(SG_E_INVALID, "not a checkpoint (too short)");
@@ -1742,6 +1759,7 @@ int sg_batch_block(sg_batch *b, int32_t *threads) {
 
 int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
   GUARD_BEGIN
+  INJECTION_POINT();
   if (!b) return fail(SG_E_INVALID, "batch is NULL");
   if (b->jobs.empty() || n_sweeps == 0) return SG_OK;
   hipStream_t st = S_(stream);
@@ -1815,6 +1833,7 @@ int sg_batch_run(sg_batch *b, uint64_t n_sweeps, void *stream) {
 // work], each part 256-byte aligned; periods are enqueued directly (no graph).
 int sg_batch_run_static(sg_batch *b, uint64_t n_sweeps, void *stream) {
   GUARD_BEGIN
+  INJECTION_POINT();
   if (!b) return fail(SG_E_INVALID, "batch is NULL");
   if (b->jobs.empty() || n_sweeps == 0) return SG_OK;
   if (!b->ctx->scratch) return fail(SG_E_STATE, "the context has no scratch address");

@@ -21,6 +21,10 @@ against an L = 8 Ising one), so in each period every job runs about the same
 device time rather than the same number of sweeps: a period would otherwise
 last as long as its slowest job while the others' compute units idle.
 
+A request can be cancelled (Server.cancel) while it waits, while its job
+is being created or while it is resident; a resident job leaves the batch at
+the next period boundary, and the others continue unchanged.
+
 The loop runs in wall-clock time and records, per request, the arrival,
 admission and completion times; latency = completion - arrival.  An optional
 wall-clock cap stops it with work still in flight (for streams far longer
@@ -64,6 +68,7 @@ class Request:
     E: Optional[np.ndarray] = None  # energy of replica 0 and 1
     Q: Optional[int] = None         # overlap of the two replicas
     spins_hash: Optional[int] = None
+    cancelled: bool = False
 
     @property
     def latency(self):
@@ -213,6 +218,9 @@ class Server:
         self.done = []
         self.periods = 0
         self.changes = 0            # membership changes (each re-plans the batch)
+        self.cancelled = []         # requests cancelled before completion
+        self._cancel = set()        # rids to cancel once arrived, created or resident
+        self._cancelled_updates = 0
         self.host_s = collections.Counter()  # host seconds per loop step
         self.n = 1                  # sweeps per run (the largest per-run cap)
 
@@ -234,11 +242,46 @@ class Server:
     def _ready(self):
         return [c for c in self.creating if self.be.ready(c[1])]
 
+    def cancel(self, rid) -> bool:
+        """Cancel request rid: a waiting request is dropped, a job being
+        created is released once created, a resident job leaves the batch at
+        the next period boundary; none of them completes.  False if the
+        request has already completed."""
+        if any(r.rid == rid for r in self.done):
+            return False
+        for r in self.pending:
+            if r.rid == rid:
+                self.pending.remove(r)
+                self._mark_cancelled(r)
+                return True
+        self._cancel.add(rid)
+        return True
+
+    def _mark_cancelled(self, req):
+        req.cancelled = True
+        self._cancel.discard(req.rid)
+        self.cancelled.append(req)
+
+    def _drop_cancelled(self):
+        """Resident jobs cancelled since the last period boundary leave."""
+        for rid in [r for r in self._cancel if r in self.active]:
+            job, req, nb = self.active.pop(rid)
+            self._cancelled_updates += 2 * req.L ** 3 * job.sweeps_done()
+            self.batch.remove(job)
+            job.close()
+            self.used -= nb
+            self._mark_cancelled(req)
+
     def _join(self, ready, now):
         for c in ready:
             self.creating.remove(c)
             req, h, nb = c
             job = self.be.take(h)
+            if req.rid in self._cancel:
+                job.close()
+                self.used -= nb
+                self._mark_cancelled(req)
+                continue
             self.batch.add(job)
             self.batch.set_budget(job, req.sweeps)
             req.t_admit = now
@@ -257,6 +300,7 @@ class Server:
             job.close()
             self.used -= nb
             self.done.append(req)
+            self._cancel.discard(rid)  # completed before its cancellation took effect
 
     def _drain(self):
         if self.inflight:
@@ -298,7 +342,7 @@ class Server:
 
     def updates_done(self) -> int:
         """Site updates enqueued so far (finished jobs and the resident ones)."""
-        return sum(r.updates() for r in self.done) + sum(
+        return sum(r.updates() for r in self.done) + self._cancelled_updates + sum(
             2 * req.L ** 3 * job.sweeps_done() for job, req, _ in self.active.values())
 
     def serve(self, requests, clock=time.perf_counter, sleep=time.sleep, cap_s=None):
@@ -313,13 +357,17 @@ class Server:
             if cap_s is not None and now >= cap_s:
                 break
             while i < len(reqs) and reqs[i].arrival <= now:
-                self.pending.append(reqs[i])
+                if reqs[i].rid in self._cancel:
+                    self._mark_cancelled(reqs[i])
+                else:
+                    self.pending.append(reqs[i])
                 i += 1
             self._admit()
             while self.inflight and self.be.done(self.inflight[0]):
                 self.inflight.popleft()
             finished, ready = self._finished(), self._ready()
-            if finished or ready:
+            leaving = any(r in self.active for r in self._cancel)
+            if finished or ready or leaving:
                 # membership changes at a period boundary: let the enqueued
                 # periods end, release finished jobs, add the new ones
                 ta = clock()
@@ -327,6 +375,7 @@ class Server:
                 tb = clock()
                 now = tb - t0
                 self._harvest(finished, now)
+                self._drop_cancelled()
                 self._join(ready, now)
                 self._set_caps()
                 self._admit()

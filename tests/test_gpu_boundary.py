@@ -162,3 +162,30 @@ def test_membership_changes_on_a_nonblocking_stream_without_host_sync(ctx):
         inst = inputs.make_instance(name, L, S, R, K, 60 + k)
         ref = run_oracle(name, algo, L, betas, inst, S=S, R=R, n=n, pt_every=pe)
         assert_same_state(job, ref, f"{name} L={L}")
+
+
+def test_injected_device_errors_leave_jobs_and_batches_intact(ctx, monkeypatch):
+    """A device error reported at entry (test hook) changes no state: the
+    job's sweep counter, budgets and trajectory continue as if the failing
+    calls had not been made."""
+    from paper_0704_3573_amd import binding as B
+    L, seed = 16, 91
+    job = B.Job(ctx, B.ISING, B.METROPOLIS, L, [1.0], n_replicas=2, seed=seed)
+    job.sweep(5)
+    batch = B.Batch(ctx, [job])
+    for fn, call in (("sg_job_sweep", lambda: job.sweep(5)), ("sg_batch_run", lambda: batch.run(4)),
+                     ("sg_batch_run_static", lambda: batch.run_static(4)),
+                     ("sg_job_measure", lambda: job.measure())):
+        monkeypatch.setenv("SG_TEST_INJECT_HIP_ERROR", fn)
+        with pytest.raises(B.SgError) as e:
+            call()
+        assert e.value.code == B.SG_E_HIP, fn
+        assert job.sweeps_done() == 5, fn
+    monkeypatch.delenv("SG_TEST_INJECT_HIP_ERROR")
+    batch.run(4)
+    job.sweep(3)
+    assert job.sweeps_done() == 12
+    inst = inputs.make_instance("ising", L, 1, 2, 1, seed)
+    ref = run_oracle("ising", oracle.METROPOLIS, L, [1.0], inst, R=2, n=12)
+    assert np.array_equal(job.spins(), ref["spins"])
+    assert np.array_equal(job.wheels()[0], ref["wheels"])

@@ -59,3 +59,38 @@ def test_served_results_equal_alone_and_oracle(ctx):
         assert np.array_equal(ref["E_log"][0].reshape(-1), r.E)
         assert int(ref["Q_log"][0, 0, 0]) == r.Q
         assert serving.spins_fingerprint(ref["spins"]) == r.spins_hash
+
+
+def test_cancelling_resident_jobs_leaves_the_others_exact(ctx):
+    """Two resident jobs are cancelled mid-run; every other request still
+    ends exactly where it ends alone, and the cancelled jobs' memory and
+    slots are released."""
+
+    class Cancelling(serving.DeviceBackend):
+        def __init__(self, ctx):
+            super().__init__(ctx)
+            self.srv, self.n = None, 0
+
+        def launch(self, batch, n):
+            tok = super().launch(batch, n)
+            self.n += 1
+            if self.n == 3:
+                for rid in (0, 1):
+                    self.srv.cancel(rid)
+            return tok
+
+    reqs = serving.poisson_stream(8, rate=0.0, seed=13, sweeps_lo=1.5, sweeps_hi=2.2, sizes=(8, 16))
+    reqs[0].sweeps = reqs[1].sweeps = 100000    # still running when cancelled
+    be = Cancelling(ctx)
+    srv = serving.Server(be, hbm_budget=8 << 20, max_slots=8, period=20)
+    be.srv = srv
+    done = srv.serve(reqs)
+    be.close()
+    assert sorted(r.rid for r in srv.cancelled) == [0, 1] and len(done) == 6
+    assert srv.used == 0 and not srv.active
+    for r in done:
+        alone = serving.Request(r.rid, r.model, r.L, r.T, r.sweeps, r.seed)
+        job = serving.make_job(ctx, alone)
+        job.sweep(r.sweeps)
+        serving.finish(job, alone)
+        assert np.array_equal(alone.E, r.E) and alone.Q == r.Q and alone.spins_hash == r.spins_hash, r

@@ -118,3 +118,17 @@ def test_library_generates_the_seeded_instances(name):
 def test_generate_rejects_bad_specs():
     with pytest.raises(B.SgError):
         B.generate(B.Spec(B.ISING, B.METROPOLIS, 4, 12, 1, 1, 1, 0))
+
+
+def test_injected_device_error_is_reported_and_leaves_the_library_usable(monkeypatch):
+    """The test hook makes a named entry point fail with SG_E_HIP at entry;
+    the binding raises with that code and the thread's message, and the
+    next call without the hook succeeds."""
+    monkeypatch.setenv("SG_TEST_INJECT_HIP_ERROR", "sg_threshold_row")
+    with pytest.raises(B.SgError) as e:
+        B.threshold_row(B.ISING, B.METROPOLIS, 1.0)
+    assert e.value.code == B.SG_E_HIP and "injected" in str(e.value)
+    monkeypatch.setenv("SG_TEST_INJECT_HIP_ERROR", "sg_job_sweep")  # another entry point
+    assert B.threshold_row(B.ISING, B.METROPOLIS, 1.0)[0] > 0
+    monkeypatch.delenv("SG_TEST_INJECT_HIP_ERROR")
+    assert B.threshold_row(B.ISING, B.METROPOLIS, 1.0)[0] > 0

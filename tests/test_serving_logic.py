@@ -186,3 +186,40 @@ def test_release_after_the_cap_closes_every_job():
     srv.release()
     assert all(j.closed for j in held) and not srv.active and not srv.creating
     assert srv.used == 0 and srv.batch.jobs == []
+
+
+class CancellingBackend(FakeBackend):
+    """Cancels requests after given numbers of period launches."""
+
+    def __init__(self, clock, plan):
+        super().__init__(clock)
+        self.plan = plan          # launches -> rids to cancel then
+        self.srv = None
+        self.launches = 0
+
+    def launch(self, batch, n):
+        tok = super().launch(batch, n)
+        self.launches += 1
+        for rid in self.plan.get(self.launches, ()):
+            self.srv.cancel(rid)
+        return tok
+
+
+def test_cancelled_requests_leave_and_the_others_run_exactly():
+    reqs = [Request(0, "ising", 8, 1.0, 10 ** 6, 0, arrival=0.0),     # resident, cancelled
+            Request(1, "ising", 16, 1.0, 3000, 1, arrival=0.0),        # runs to completion
+            Request(2, "ising", 8, 1.0, 500, 2, arrival=0.0),          # waits for a slot, cancelled
+            Request(3, "potts", 8, 1.0, 400, 3, arrival=10.0)]         # cancelled before arrival
+    clock = Clock()
+    be = CancellingBackend(clock, {3: [0, 2, 3]})
+    srv = Server(be, hbm_budget=10 ** 9, max_slots=2, period=50)
+    be.srv = srv
+    done = srv.serve(reqs, clock=clock, sleep=clock.sleep)
+    assert [r.rid for r in done] == [1] and done[0].E == [3000, -3000]
+    assert sorted(r.rid for r in srv.cancelled) == [0, 2, 3]
+    assert all(r.cancelled and r.t_done is None for r in srv.cancelled)
+    assert 2 not in be.created and 3 not in be.created   # never created
+    assert srv.used == 0 and not srv.active and srv.batch.jobs == []
+    # the cancelled resident job's sweeps count as performed work
+    assert srv.updates_done() > done[0].updates()
+    assert srv.cancel(1) is False                         # already completed
