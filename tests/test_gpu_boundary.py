@@ -189,3 +189,26 @@ def test_injected_device_errors_leave_jobs_and_batches_intact(ctx, monkeypatch):
     ref = run_oracle("ising", oracle.METROPOLIS, L, [1.0], inst, R=2, n=12)
     assert np.array_equal(job.spins(), ref["spins"])
     assert np.array_equal(job.wheels()[0], ref["wheels"])
+
+
+def test_results_do_not_depend_on_the_arena_offset(ctx):
+    """A job placed at a 256-byte aligned offset inside a larger buffer
+    runs exactly as one in an arena of its own; a misaligned arena is
+    rejected."""
+    import torch
+    from paper_0704_3573_amd import binding as B
+    L, seed = 16, 333
+    spec = B.Spec(B.POTTS, B.HEATBATH, 4, L, 1, 2, 1, 0)
+    n = B.job_bytes(spec)
+    big = torch.empty(n + 8192, dtype=torch.uint8, device="cuda")
+    kw = dict(n_replicas=2, seed=seed)
+    a = B.Job(ctx, B.POTTS, B.HEATBATH, L, [1.1], **kw)
+    b = B.Job(ctx, B.POTTS, B.HEATBATH, L, [1.1], arena=big[4096 + 256:4096 + 256 + n], **kw)
+    for j in (a, b):
+        j.sweep(7)
+    assert np.array_equal(a.spins(), b.spins())
+    assert np.array_equal(a.wheels()[0], b.wheels()[0])
+    assert np.array_equal(a.measure()[0], b.measure()[0])
+    with pytest.raises(B.SgError) as e:
+        B.Job(ctx, B.POTTS, B.HEATBATH, L, [1.1], arena=big[128:128 + n], **kw)
+    assert e.value.code == B.SG_E_INVALID
