@@ -221,6 +221,7 @@ class Server:
         self.cancelled = []         # requests cancelled before completion
         self._cancel = set()        # rids to cancel once arrived, created or resident
         self._cancelled_updates = 0
+        self._caps = {}             # per-run cap last set, by rid
         self.host_s = collections.Counter()  # host seconds per loop step
         self.n = 1                  # sweeps per run (the largest per-run cap)
 
@@ -266,6 +267,7 @@ class Server:
         """Resident jobs cancelled since the last period boundary leave."""
         for rid in [r for r in self._cancel if r in self.active]:
             job, req, nb = self.active.pop(rid)
+            self._caps.pop(rid, None)
             self._cancelled_updates += 2 * req.L ** 3 * job.sweeps_done()
             self.batch.remove(job)
             job.close()
@@ -300,6 +302,7 @@ class Server:
             job.close()
             self.used -= nb
             self.done.append(req)
+            self._caps.pop(rid, None)
             self._cancel.discard(rid)  # completed before its cancellation took effect
 
     def _drain(self):
@@ -317,9 +320,11 @@ class Server:
             return
         slow = max(sweep_cost(req) for _, req, _ in self.active.values())
         self.n = 1
-        for job, req, _ in self.active.values():
+        for rid, (job, req, _) in self.active.items():
             cap = max(1, int(self.period * slow / sweep_cost(req)))
-            self.batch.set_period_cap(job, cap)
+            if self._caps.get(rid) != cap:  # a library call only when it changes
+                self.batch.set_period_cap(job, cap)
+                self._caps[rid] = cap
             self.n = max(self.n, min(cap, req.sweeps))
 
     def _launch(self):
@@ -338,6 +343,7 @@ class Server:
             self.batch.remove(job)
             job.close()
         self.active.clear()
+        self._caps.clear()
         self.used = 0
 
     def updates_done(self) -> int:
