@@ -277,3 +277,50 @@ def test_l2_parallel_tempering_marginals_are_boltzmann():
         levels, probs = exact_energy_law(inst["J"][0], b)
         ok, chi2, dof = chi2_ok(out["E_log"][:, k], levels, probs, n_eff=n // 3)
         assert ok, (k, chi2, dof)
+
+
+@pytest.mark.parametrize("model", ["ising_met", "ising_hb", "potts", "gpotts"])
+@pytest.mark.parametrize("L", [4, 8])
+def test_same_colour_updates_commute(model, L):
+    """The checkerboard's race freedom (sec. 3.1), on the oracle's own site
+    update: with every site of one colour given its own number, updating
+    them in any order gives the same configuration, because no two sites
+    of one colour are neighbours.  Updating sites of both colours in a
+    different order does change the result (the test can see an order
+    dependence when there is one)."""
+    rng = np.random.default_rng(100 + L)
+    N = L ** 3
+    beta = 0.9
+    J = rng.choice(np.array([-1, 1], np.int8), size=(3, N)).astype(np.int8)
+    if model.startswith("ising"):
+        s0 = rng.choice(np.array([-1, 1], np.int8), size=N).astype(np.int8)
+        algo = oracle.METROPOLIS if model == "ising_met" else oracle.HEATBATH
+        T = oracle.tables_metropolis(beta) if algo == oracle.METROPOLIS else oracle.tables_heatbath(beta)
+        upd = lambda s, i, r: oracle.ising_update_site(L, algo, s, J, i, r, T)
+    elif model == "potts":
+        s0 = rng.integers(0, 4, N).astype(np.uint8)
+        W = oracle.tables_potts(beta)
+        upd = lambda s, i, r: oracle.potts_update_site(L, s, J, i, r, W)
+    else:
+        s0 = rng.integers(0, 4, N).astype(np.uint8)
+        P = rng.integers(0, 24, (3, N)).astype(np.uint8)
+        W = oracle.tables_potts(beta)
+        upd = lambda s, i, r: oracle.gpotts_update_site(L, s, P, i, r, W)
+    r = rng.integers(0, TWO32, N, dtype=np.uint64)
+    x, y, z = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    colour = ((x + y + z) % 2).transpose(2, 1, 0).reshape(-1)  # site i = x + L (y + L z)
+    for p in (0, 1):
+        sites = np.flatnonzero(colour == p)
+        a, b = s0.copy(), s0.copy()
+        for i in sites:
+            upd(a, int(i), int(r[i]))
+        for i in rng.permutation(sites):
+            upd(b, int(i), int(r[i]))
+        assert np.array_equal(a, b), (model, L, p)
+    # both colours: the order matters
+    a, b = s0.copy(), s0.copy()
+    for i in range(N):
+        upd(a, i, int(r[i]))
+    for i in rng.permutation(N):
+        upd(b, int(i), int(r[i]))
+    assert not np.array_equal(a, b)
