@@ -35,7 +35,11 @@ hipError_t launch_debug_rng(const uint32_t *wheels, uint32_t *out, uint64_t wstr
 hipError_t launch_advance(uint64_t *const *done, const int32_t *cap, int n, int nsweeps,
                           hipStream_t st);
 hipError_t launch_add(uint64_t *p, uint64_t v, hipStream_t st);
-hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st);
+// with done != nullptr the launch also performs launch_advance(done, cap,
+// ncnt, nsweeps)
+hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st,
+                           uint64_t *const *done = nullptr, const int32_t *cap = nullptr, int ncnt = 0,
+                           int nsweeps = 0);
 hipError_t scratch_address(int device, void **out);
 }  // namespace sg
 
@@ -366,10 +370,13 @@ static void make_items(const sg_job *j, int G, std::vector<Work> &out) {
 // index, and each XCD has its own L2.  Items reading the same sample's
 // couplings (consecutive in the list) are put on one XCD so that its L2
 // serves the second reader: within each run of equal-size items (the list
-// stays sorted by size), the run is cut into 8 contiguous parts and part x
+// keeps its order), the run is cut into 8 contiguous parts and part x
 // fills the run's positions p with p mod 8 = x.  Results do not depend on
 // the order of the items.
 static uint64_t work_size(const Work &w) { return (uint64_t)w.ncopies * w.L * w.L * w.L; }
+// sites one lane of the item visits per sweep (its wheel's min(8, L) rows of
+// L sites): the item's duration grows with it, whatever the item's copies
+static uint64_t lane_work(const Work &w) { return (uint64_t)std::min(8, w.L) * w.L; }
 
 static void xcd_order(std::vector<Work> &v) {
   const size_t NX = 8;
@@ -1484,9 +1491,11 @@ static int plan_items(const sg_batch *b, int &tpb_out, std::vector<Launch> &laun
   launches.clear();
   for (auto &kv : by_key) {
     Launch &l = kv.second;
-    // longest items first: the launch tail is then made of short items
-    std::stable_sort(l.items.begin(), l.items.end(),
-                     [](const Work &x, const Work &y) { return work_size(x) > work_size(y); });
+    // longest items first (most sites per lane, then most sites): the launch
+    // tail is then made of short items
+    std::stable_sort(l.items.begin(), l.items.end(), [](const Work &x, const Work &y) {
+      return lane_work(x) != lane_work(y) ? lane_work(x) > lane_work(y) : work_size(x) > work_size(y);
+    });
     xcd_order(l.items);
     launches.push_back(std::move(l));
   }
@@ -1621,17 +1630,20 @@ static int enqueue_period(sg_batch *b, int nsw, const std::vector<int> &pt_jobs,
     off += l.items.size();
   }
   if (timed) HIPCHK(hipEventRecord(b->ev1, st));
-  HIPCHK(sg::launch_advance(b->d_done, b->d_cap, (int)b->jobs.size(), nsw, st));
   // parallel tempering of every due job in one fused launch (buffers prepared
-  // before any capture starts)
+  // before any capture starts), which also advances the sweep counters; a
+  // period without it advances them in a launch of their own
+  auto it = b->pt_cache.find(pt_jobs);
+  const bool fused_pt = it != b->pt_cache.end() && it->second.n > 0;
+  if (!fused_pt) HIPCHK(sg::launch_advance(b->d_done, b->d_cap, (int)b->jobs.size(), nsw, st));
   for (int ji : pt_jobs)
     if (b->jobs[ji]->K > PT_FUSED_KMAX) {
       int rc = run_pt(b->jobs[ji], st);
       if (rc) return rc;
     }
-  auto it = b->pt_cache.find(pt_jobs);
-  if (it != b->pt_cache.end() && it->second.n > 0)
-    HIPCHK(sg::launch_pt_fused(it->second.d, it->second.n, it->second.kmax, st));
+  if (fused_pt)
+    HIPCHK(sg::launch_pt_fused(it->second.d, it->second.n, it->second.kmax, st, b->d_done, b->d_cap,
+                               (int)b->jobs.size(), nsw));
   return SG_OK;
 }
 

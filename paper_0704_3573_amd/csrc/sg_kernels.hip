@@ -2180,10 +2180,18 @@ __global__ __launch_bounds__(64) void pt_kernel(const int64_t *__restrict__ E,
 // batch in one launch.  Wheels, energies, permutations and the factor table
 // are staged in LDS, so the 31 sequential swap decisions of a chain run on
 // LDS latency instead of global memory latency.  Same decisions as pt_kernel.
-__global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__ works, int kmax) {
+// Workgroup 0 also adds min(cap[i], nsweeps) to the ncnt sweep counters
+// *done[i] (the counter update of a period that ends in parallel tempering;
+// nothing in the launch reads the counters).
+__global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__ works, int kmax,
+                                                      uint64_t *const *__restrict__ done,
+                                                      const int32_t *__restrict__ cap, int ncnt,
+                                                      int nsweeps) {
   extern __shared__ uint32_t lds[];
   const PtWork w = works[blockIdx.x];
   const int t = threadIdx.x;
+  if (blockIdx.x == 0)
+    for (int i = t; i < ncnt; i += 64) *done[i] += (uint64_t)min(cap[i], nsweeps);
   const int K = w.K;
   uint32_t *ring = lds + t * 62;                                 // 61 words + position
   int32_t *Es = (int32_t *)(lds + 64 * 62) + t * kmax;           // energy by slot
@@ -2468,10 +2476,12 @@ hipError_t launch_pt(const int64_t *E, int32_t *slot_of_temp, int32_t *temp_of_s
   return hipGetLastError();
 }
 
-hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st) {
+hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st,
+                           uint64_t *const *done, const int32_t *cap, int ncnt, int nsweeps) {
   if (nworks <= 0) return hipSuccess;
   const size_t lds = (size_t)(64 * 62 + 128 * kmax) * 4 + (size_t)(kmax > 1 ? kmax - 1 : 1) * 24 * 8;
-  hipLaunchKernelGGL(pt_fused_kernel, dim3(nworks), dim3(64), lds, st, works, kmax);
+  hipLaunchKernelGGL(pt_fused_kernel, dim3(nworks), dim3(64), lds, st, works, kmax, done, cap, ncnt,
+                     nsweeps);
   return hipGetLastError();
 }
 
