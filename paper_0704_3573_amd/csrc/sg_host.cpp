@@ -194,13 +194,13 @@ static Geom geom_of(int model, int L) {
   return model == SG_ISING || model == SG_ISING_GEN ? sg::igeom(L) : sg::geom(L);
 }
 // Lanes serving one copy, and the fused launch (sweep kernel) of a job: the
-// 3D Potts models run four lanes per wheel where the layout allows it.
+// 3D Potts models run several lanes per wheel where the layout allows it.
 static int wheel_lanes(int model, int L) {
   return model == SG_POTTS || model == SG_GPOTTS ? sg::potts_wheel_lanes(L) : 1;
 }
 static int launch_group(int model, int L) {
   if (model == SG_ISING && L <= 4) return sg::LAUNCH_ISING_SMALL;
-  if (wheel_lanes(model, L) == 4) return model == SG_POTTS ? sg::LAUNCH_POTTS_QUAD : sg::LAUNCH_GPOTTS_QUAD;
+  if (wheel_lanes(model, L) >= 4) return model == SG_POTTS ? sg::LAUNCH_POTTS_QUAD : sg::LAUNCH_GPOTTS_QUAD;
   if (wheel_lanes(model, L) == 2) return model == SG_POTTS ? sg::LAUNCH_POTTS_PAIR : sg::LAUNCH_GPOTTS_PAIR;
   return model;
 }

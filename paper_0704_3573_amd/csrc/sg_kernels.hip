@@ -1395,24 +1395,26 @@ DEV void potts_run(const Work &w, uint32_t *lds) {
 }
 
 // ---------------------------------------------------------------------------
-// q = 4 Potts heat bath (+-J glass and glassy model) with S = 4 or 2 lanes
-// per wheel.  Sec. 3.3 lets one wheel emit many numbers per clock, because
-// the recurrence I(k) = I(k-24) + I(k-55) reaches back at least 24 outputs:
-// any 24 consecutive outputs can be formed at once.  Here the S lanes of a
-// group share a wheel: lane l forms the outputs k = k0 + S s + l (step s),
-// so the numbers, their order and every site's number are those of the
-// one-lane kernel.  For a lag m = q S + r (0 <= r < S), I(k - m) is the
+// q = 4 Potts heat bath (+-J glass and glassy model) with S = 8, 4 or 2
+// lanes per wheel.  Sec. 3.3 lets one wheel emit many numbers per clock,
+// because the recurrence I(k) = I(k-24) + I(k-55) reaches back at least 24
+// outputs: any 24 consecutive outputs can be formed at once.  Here the S
+// lanes of a group share a wheel: lane l forms the outputs k = k0 + S s + l
+// (step s), so the numbers, their order and every site's number are those of
+// the one-lane kernel.  For a lag m = q S + r (0 <= r < S), I(k - m) is the
 // output of step s - q of lane l - r if l >= r, else of step s - q - 1 of
 // lane l - r + S: each lane exposes the word its reader needs (step s - q - 1
 // in lanes l >= S - r, else s - q: one bit-select on lane-constant masks)
-// and the reader takes it with a DPP quad permutation; lag 24 (r = 0) stays
-// in the lane.  Each lane keeps its outputs of the last D steps in registers
-// (D = 16 for S = 4, 31 for S = 2; a ring of RL >= D words, static indices),
-// and within a block of B draws (as in the one-lane kernel) lane l updates
-// draws l, l + S, l + 2S, ...  Everything else (fields, weights, multiply,
-// selection, the LDS layout and the HBM state) is the one-lane kernel's.
-// potts_wheel_lanes gives S: four at L = 8..32, two at L = 40, 48 (four
-// lanes per wheel would not fit one workgroup there).
+// and the reader takes it across lanes (a DPP quad permutation for S <= 4,
+// two DPP row rotations and a select for S = 8); lag 24 (r = 0) stays in the
+// lane.  Each lane keeps its outputs of the last D steps in registers (D = 8
+// for S = 8, 16 for S = 4, 31 for S = 2; a ring of RL >= D words, static
+// indices), and within a block of B draws (as in the one-lane kernel) lane l
+// updates draws l, l + S, l + 2S, ...  Everything else (fields, weights,
+// multiply, selection, the LDS layout and the HBM state) is the one-lane
+// kernel's.  potts_wheel_lanes gives S: eight at L = 16, four at L = 8, 24,
+// 32, two at L = 40, 48 (more lanes per wheel would not fit one workgroup
+// there, or would not divide L/2).
 // ---------------------------------------------------------------------------
 
 // DPP quad-permutation control: lane i of a group of S (S | 4) reads lane
@@ -1427,7 +1429,7 @@ template <int L, bool GLASSY, int S>
 struct PottsMK {
   using G = GC<L>;
   static constexpr bool QUAD = true;  // loads and stores its own ring
-  static_assert(S == 2 || S == 4, "two or four lanes per wheel");
+  static_assert(S == 2 || S == 4 || S == 8, "two, four or eight lanes per wheel");
   static_assert(G::B % S == 0 && G::H % S == 0, "S lanes per wheel need B, L/2 multiples of S");
   static constexpr int B = G::B / S;                 // steps per block (draws per lane)
   static constexpr int Q24 = 24 / S, Q55 = 55 / S, R55 = 55 % S, Q61 = 61 / S, R61 = 61 % S;
@@ -1437,7 +1439,10 @@ struct PottsMK {
   static constexpr int M = RL, V = RL / B;           // as the drive expects them
   static constexpr int NBLK = G::NBLK, H = G::H, RPB = G::RPB, RHO = G::RHO, NW = G::NW;
   static constexpr int MS = G::M;                    // HBM ring slots of a wheel
-  static constexpr int BQ = GLASSY ? B : potts_bq(L);  // coupling words per block and lane
+  // +-J patterns hold four draws per word: with S <= 4 every lane loads all
+  // words of the block, with S = 8 each lane the word of each of its draws
+  static constexpr bool OWNW = !GLASSY && S > 4;
+  static constexpr int BQ = GLASSY || OWNW ? B : potts_bq(L);  // coupling words per block and lane
   static constexpr int XS = potts_xs(L);             // LDS byte stride of x
   uint8_t *sp;          // LDS bytes of the lane's copy, [y][x][z] (rows at row(y)), 8 sigma
   uint8_t *wp;          // where the lane stores its new spins: sp, or the dummy region
@@ -1449,7 +1454,8 @@ struct PottsMK {
   int z, zp, zm, g, sub;  // wheel plane, row group and the lane's place in its group
   uint32_t m0, mlast;     // all ones in lanes with sub == 0 (== S - 1)
   uint32_t x55, x61;      // all ones in lanes exposing the older word for lag 55 (61)
-  uint32_t sh;            // 8 sub: the lane's byte of a +-J pattern word
+  uint32_t lo55, lo61;    // S = 8: all ones in lanes reading a lane below them (sub >= r)
+  uint32_t sh;            // 8 (sub mod 4): the lane's byte of a +-J pattern word
   int kmod0, kmod1;       // first draw of the launch (and of the next one) mod MS
   uint32_t nextpat[BQ];
 
@@ -1461,7 +1467,25 @@ struct PottsMK {
     mlast = sub == S - 1 ? ~0u : 0u;
     x55 = sub >= S - R55 ? ~0u : 0u;
     x61 = sub >= S - R61 ? ~0u : 0u;
-    sh = 8u * (uint32_t)sub;
+    lo55 = sub >= R55 ? ~0u : 0u;
+    lo61 = sub >= R61 ? ~0u : 0u;
+    sh = 8u * (uint32_t)(sub & 3);
+  }
+
+  // x of lane (sub - R) mod S of the lane's group.  S <= 4: one quad
+  // permutation.  S = 8: the groups are the halves of the 16-lane DPP rows;
+  // rotating the row by R serves the lanes with sub >= R, rotating it by
+  // R + 8 the others.
+  template <int R>
+  DEV uint32_t from_lane(uint32_t x, uint32_t lo) const {
+    if constexpr (S <= 4) {
+      (void)lo;
+      return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, qp_ctrl(S, R), 0xF, 0xF, false);
+    } else {
+      const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x120 + R, 0xF, 0xF, false);
+      const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x120 + R + 8, 0xF, 0xF, false);
+      return bfi(lo, a, b);
+    }
   }
 
   DEV void fetch(int p, int blk) {
@@ -1470,6 +1494,12 @@ struct PottsMK {
       const uint32_t s0 = __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * G::B) * NW * 4u);
 #pragma unroll
       for (int i = 0; i < B; i++) nextpat[i] = bload(rJ, voff, s0 + (uint32_t)(S * i) * NW * 4u);
+    } else if constexpr (OWNW) {
+      // draw S i + sub is in word S i / 4 + sub / 4 (sub / 4 is in voff)
+      const uint32_t s0 =
+          __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * potts_bq(L)) * NW * 4u);
+#pragma unroll
+      for (int i = 0; i < B; i++) nextpat[i] = bload(rJ, voff, s0 + (uint32_t)(S / 4 * i) * NW * 4u);
     } else {
       // four draws per word
       const uint32_t s0 = __builtin_amdgcn_readfirstlane((uint32_t)((p * NBLK + blk) * BQ) * NW * 4u);
@@ -1544,9 +1574,9 @@ struct PottsMK {
 #pragma unroll
         for (int d = 0; d < 6; d++) rb[i][d] = tb[(d & 1) * 24 + ((pat[i] >> (5 * d)) & 31u)];
       } else {
-        // word (S i) / 4, byte (S i) mod 4 + sub; the entry of the
+        // word (S i + sub) / 4, byte (S i + sub) mod 4; the entry of the
         // pattern's bits 0..4 gives directions 0..4, bit 5 the sixth word
-        const uint32_t pb = pat[(S * i) >> 2] >> (sh + 8 * ((S * i) & 3));
+        const uint32_t pb = OWNW ? pat[i] >> sh : pat[(S * i) >> 2] >> (sh + 8 * ((S * i) & 3));
         const uint32_t *r5 = tb + POTTS_TAB_STRIDE * (pb & 31u);
 #pragma unroll
         for (int d = 0; d < 5; d++) rb[i][d] = r5[d];
@@ -1586,8 +1616,8 @@ struct PottsMK {
       const int st = VI * B + i;  // register of this step (static)
       const uint32_t e55 = bfi(x55, ring[(st + RL - Q55 - 1) % RL], ring[(st + RL - Q55) % RL]);
       const uint32_t e61 = bfi(x61, ring[(st + RL - Q61 - 1) % RL], ring[(st + RL - Q61) % RL]);
-      const uint32_t y55 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e55, qp_ctrl(S, R55), 0xF, 0xF, false);
-      const uint32_t y61 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e61, qp_ctrl(S, R61), 0xF, 0xF, false);
+      const uint32_t y55 = from_lane<R55>(e55, lo55);
+      const uint32_t y61 = from_lane<R61>(e61, lo61);
       ring[st % RL] = ring[(st + RL - Q24) % RL] + y55;
       const uint32_t r = ring[st % RL] ^ y61;
       const uint32_t C1 = w[i][0] + w[i][1], C2 = C1 + w[i][2];
@@ -1636,7 +1666,9 @@ struct PottsMK {
             hsum += ((vote >> sp[nb[d]]) & 31u) == si;
           }
         } else {
-          const uint32_t pw = bload(rJ, voff + (uint32_t)((blk * BQ + (kb >> 2)) * NW) * 4u);
+          // word kb / 4 of the block (voff holds sub / 4 when S = 8)
+          const uint32_t v0 = OWNW ? voff - (uint32_t)((sub >> 2) * NW) * 4u : voff;
+          const uint32_t pw = bload(rJ, v0 + (uint32_t)((blk * potts_bq(L) + (kb >> 2)) * NW) * 4u);
           const uint32_t pt = (pw >> (8 * (kb & 3))) & 0xFFu;
           for (int d = 0; d < 6; d++)
             if (sp[nb[d]] == si) hsum += ((pt >> d) & 1u) ? -1 : 1;
@@ -1703,6 +1735,7 @@ DEV void potts_multi_run(const Work &w, uint32_t *lds) {
   k.rJ = make_rsrc(w.J, w.J_bytes);
   k.voff = ((uint32_t)(copy / w.RK) * (GLASSY ? gpotts_js(L) : potts_js(L)) + wl) * 4u;
   if constexpr (GLASSY) k.voff += (uint32_t)(k.sub * G::NW) * 4u;
+  if constexpr (K::OWNW) k.voff += (uint32_t)((k.sub >> 2) * G::NW) * 4u;
   const uint64_t per_sweep = (uint64_t)G::RHO * L;
   const uint64_t done = *w.done;
   k.kmod0 = (int)__builtin_amdgcn_readfirstlane((uint32_t)((done * per_sweep) % G::M));
@@ -1734,7 +1767,7 @@ template <bool GLASSY>
 DEV void potts_quad_dispatch(const Work &w, uint32_t *lds) {
   switch (w.L) {
     case 8: potts_multi_run<8, GLASSY, 4>(w, lds); break;
-    case 16: potts_multi_run<16, GLASSY, 4>(w, lds); break;
+    case 16: potts_multi_run<16, GLASSY, 8>(w, lds); break;
     case 24: potts_multi_run<24, GLASSY, 4>(w, lds); break;
     case 32: potts_multi_run<32, GLASSY, 4>(w, lds); break;
     default: break;

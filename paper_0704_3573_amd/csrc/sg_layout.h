@@ -167,11 +167,12 @@ constexpr int POTTS4_W_WORDS = 12;
 // groups and copies of a wave fall on distinct LDS banks.
 constexpr int POTTS_MAX_TPB = 512;
 // Lanes per wheel of the 3D Potts kernels (the wheel's outputs are formed S
-// at a time, lane l taking those with index = l mod S): four where L/2 is a
-// multiple of 4 and a copy's 4 NW lanes fit one workgroup (L = 8..32), two at
-// L = 40, 48 (2 NW = 400, 576 lanes), else one.
+// at a time, lane l taking those with index = l mod S): eight at L = 16
+// (8 NW = 256 lanes per copy), four where L/2 is a multiple of 4 and a
+// copy's 4 NW lanes fit one workgroup (L = 8, 24, 32), two at L = 40, 48
+// (2 NW = 400, 576 lanes), else one.  S divides L/2 and 24.
 SG_HD constexpr int potts_wheel_lanes(int L) {
-  return L == 8 || L == 16 || L == 24 || L == 32 ? 4 : (L == 40 || L == 48 ? 2 : 1);
+  return L == 16 ? 8 : (L == 8 || L == 24 || L == 32 ? 4 : (L == 40 || L == 48 ? 2 : 1));
 }
 // Workgroups of the two-lanes-per-wheel kernels hold up to 768 threads.
 constexpr int POTTS_PAIR_MAX_TPB = 768;
@@ -189,8 +190,12 @@ constexpr int POTTS_W_WORDS = 8;
 // an x stride of L: 16 words, so lanes 0 and 2 of every wheel would share a
 // bank.  The 64 lanes of a wave (16 wheels of consecutive z, four lanes
 // each; even and odd z planes one x-step apart) read 32 distinct words;
-// with a stride of 48 bytes they lie on 32 distinct banks.
-SG_HD constexpr int potts_xs(int L) { return L == 32 ? 48 : L; }
+// with a stride of 48 bytes they lie on 32 distinct banks.  At L = 16 the
+// eight lanes of a wheel read sites 32 bytes apart with a stride of L, and
+// lanes 0 and 4 share a bank; with a stride of 24 bytes the 32 words a wave
+// reads lie on 32 distinct banks (the reads of the z neighbours, where one
+// wheel of the wave wraps around in z, excepted).
+SG_HD constexpr int potts_xs(int L) { return L == 32 ? 48 : (L == 16 ? 24 : L); }
 SG_HD constexpr int potts_lds_copy(int L) {
   return (L * L * potts_xs(L) + 2 * geom(L).NG * L + 3) / 4 * 4;
 }

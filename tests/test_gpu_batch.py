@@ -79,6 +79,30 @@ def test_continuous_batching_join_and_leave(ctx):
         assert_same_state(job, ref, f"continuous {model} L={L}")
 
 
+
+def test_fused_and_unfused_parallel_tempering_in_one_batch(ctx):
+    """A K = 70 job takes the unfused parallel-tempering kernel and is due
+    every sweep; a K = 3 job is due every second sweep, and its fused PT
+    launch then also advances every job's sweep counter; in the other
+    periods the counters advance in a launch of their own.  A job without PT
+    rides along.  Every job must match the oracle."""
+    from paper_0704_3573_amd import binding as B
+    specs = [("ising", oracle.METROPOLIS, 4, 1, 1, 70, 1), ("ising", oracle.METROPOLIS, 8, 1, 2, 3, 2),
+             ("ising", oracle.HEATBATH, 8, 1, 1, 1, 0)]
+    jobs = []
+    for n, (model, algo, L, S, R, K, pe) in enumerate(specs):
+        betas = 1.0 / np.linspace(0.5, 3.0, K) if K > 1 else [1.0 / 1.1]
+        inst = instance(model, L, S, R, K, seed=980 + n)
+        jobs.append((model, algo, L, S, R, K, pe, betas, inst,
+                     make_job(ctx, model, algo, L, betas, inst, S=S, R=R, pt_every=pe)))
+    batch = B.Batch(ctx, [j[-1] for j in jobs])
+    batch.run(3)
+    batch.run(4)
+    for model, algo, L, S, R, K, pe, betas, inst, job in jobs:
+        assert job.sweeps_done() == 7
+        ref = run_oracle(model, algo, L, betas, inst, S=S, R=R, n=7, pt_every=pe)
+        assert_same_state(job, ref, f"{model} L={L} K={K}")
+
 def test_full_size_batched_pt_workload_sampled_chains(ctx):
     """The benchmark's batched workload at full size (256 samples at L = 16,
     24, 32, 48, 2 replicas x 32 temperatures, PT every 10 sweeps) in the
