@@ -46,6 +46,8 @@ hipError_t scratch_address(int device, void **out);
 using sg::Geom;
 using sg::PtWork;
 using sg::Work;
+using sg::PT_CHAINS_PER_ITEM;
+using sg::PT_FUSED_KMAX;
 
 // ---------------------------------------------------------------- errors --
 static thread_local std::string g_err;
@@ -169,7 +171,6 @@ static void threshold_row(int model, int algo, double beta, uint32_t row[sg::THR
 // so a launch's time is one chain's decisions plus the staging of its
 // workgroup's wheels, energies and permutations; small items keep the
 // staging short and spread it over many CUs
-static const int PT_CHAINS_PER_ITEM = 16;
 
 struct sg_ctx {
   int device;
@@ -393,7 +394,6 @@ static void xcd_order(std::vector<Work> &v) {
   }
 }
 
-static const int PT_FUSED_KMAX = 64;
 
 static void make_pt_works(const sg_job *j, std::vector<PtWork> &out) {
   for (int c0 = 0; c0 < j->chains; c0 += PT_CHAINS_PER_ITEM) {

@@ -71,6 +71,25 @@ DEV void stage_words(int n, Load load, Put put) {
   }
 }
 
+// Staging in two phases, for a workgroup of NT threads: load_words issues
+// all U loads of a thread (word i = t + NT u of n, 1 <= n <= NT U; an index
+// past the end re-reads the last word, so every load is valid and none is
+// behind a branch), put_words stores the words that exist.  Loads of several
+// arrays issued before any put wait for global memory together.
+template <int NT, int U, class Load>
+DEV void load_words(int n, Load load, uint32_t (&v)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; u++) v[u] = load(min((int)threadIdx.x + NT * u, n - 1));
+}
+template <int NT, int U, class Put>
+DEV void put_words(int n, const uint32_t (&v)[U], Put put) {
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int i = (int)threadIdx.x + NT * u;
+    if (i < n) put(i, v[u]);
+  }
+}
+
 // Compile-time geometry of the Potts kernels (row-aligned blocks of draws).
 template <int L>
 struct GC {
@@ -2165,6 +2184,43 @@ DEV uint32_t ptw_next(uint32_t *w) {
   return out;
 }
 
+// The threshold of |D| = m (0 < m < 2^24): from T = 2^32, for each set bit
+// b of m, lowest first, T <- floor(T Fi[b] / 2^32).  With T = Th 2^32 + Tl
+// and Fi[b] = fh 2^32 + fl, both at most 2^32 (so Th = 1 forces Tl = 0 and
+// fh = 1 forces fl = 0), the step is exact as: T = 2^32 if Th = fh = 1, fl
+// if only Th = 1, T if only fh = 1, else the high word of Tl fl (one 32-bit
+// multiply).  The factors of the next two set bits are read while one
+// multiplies.
+DEV uint64_t pt_threshold(const uint64_t *Fi, uint32_t m) {
+  uint32_t Th = 1, Tl = 0;
+  uint32_t m1 = m & (m - 1);  // the bits after the lowest
+  uint64_t f0 = Fi[m ? __ffs(m) - 1 : 0];
+  uint64_t f1 = Fi[m1 ? __ffs(m1) - 1 : 0];
+  while (m) {
+    const uint32_t m2 = m1 & (m1 - 1);
+    const uint64_t f2 = Fi[m2 ? __ffs(m2) - 1 : 0];
+    const uint32_t fl = (uint32_t)f0, fh = (uint32_t)(f0 >> 32);
+    const uint32_t p = __umulhi(Tl, fl);
+    Tl = Th ? fl : (fh ? Tl : p);
+    Th &= fh;
+    f0 = f1;
+    f1 = f2;
+    m = m1;
+    m1 = m2;
+  }
+  return (uint64_t)Th << 32 | Tl;
+}
+
+// ptw_next with the position held by the caller (in a register)
+DEV uint32_t ptw_draw(uint32_t *w, int &pos) {
+  auto back = [&](int m) { int j = pos - m; return w[j < 0 ? j + 61 : j]; };
+  const uint32_t ik = back(24) + back(55);
+  const uint32_t out = ik ^ w[pos];
+  w[pos] = ik;
+  pos = pos == 60 ? 0 : pos + 1;
+  return out;
+}
+
 __global__ __launch_bounds__(64) void pt_kernel(const int64_t *__restrict__ E,
                                                 int32_t *__restrict__ slot_of_temp,
                                                 int32_t *__restrict__ temp_of_slot,
@@ -2209,10 +2265,11 @@ __global__ __launch_bounds__(64) void pt_kernel(const int64_t *__restrict__ E,
   for (int i = 0; i < K; i++) temp_of_slot[(size_t)ch * K + so[i]] = i;
 }
 
-// Fused variant: one workgroup per 64 chains of one job, every job of a
-// batch in one launch.  Wheels, energies, permutations and the factor table
-// are staged in LDS, so the 31 sequential swap decisions of a chain run on
-// LDS latency instead of global memory latency.  Same decisions as pt_kernel.
+// Fused variant: one workgroup per PT_CHAINS_PER_ITEM (at most) chains of
+// one job, every job of a batch in one launch.  Wheels, energies,
+// permutations, the factor table and the signs are staged in LDS, so the 31
+// sequential swap decisions of a chain run on LDS latency instead of global
+// memory latency.  Same decisions as pt_kernel.
 // Workgroup 0 also adds min(cap[i], nsweeps) to the ncnt sweep counters
 // *done[i] (the counter update of a period that ends in parallel tempering;
 // nothing in the launch reads the counters).
@@ -2230,34 +2287,42 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
   int32_t *Es = (int32_t *)(lds + 64 * 62) + t * kmax;           // energy by slot
   int32_t *so = (int32_t *)(lds + 64 * 62 + 64 * kmax) + t * kmax;  // slot by temperature
   uint64_t *Fl = (uint64_t *)(lds + 64 * 62 + 128 * kmax);       // [K-1][24]
-  for (int i = t; i < (K - 1) * 24; i += 64) Fl[i] = w.F[i];
-  // the workgroup's chains are consecutive: stage their wheels (64 words per
-  // chain in memory, 62 used), energies and permutations cooperatively,
-  // coalesced and with several loads in flight per thread
+  int32_t *sgl = (int32_t *)(Fl + (kmax - 1) * 24);              // [K-1] sign of dbeta
+  // one staging pass: every load of the factor table (as 32-bit halves),
+  // the signs and the wheels (64 words per chain in memory, 62 used),
+  // energies (|E| <= 3 L^3: the low word of each int64) and permutations of
+  // the workgroup's consecutive chains is issued before any is stored, so
+  // the thread waits for global memory about once (not once per array and
+  // chunk); each decision then reads LDS only
   const int nch = w.nchains;
+  const int nF = (K - 1) * 48, nW = nch * 64, nE = nch * K;
+  const uint32_t *F32 = (const uint32_t *)w.F;
   const uint32_t *gw0 = w.ptw + (size_t)w.chain0 * 64;
-  stage_words<8>(
-      nch * 64, [&](int i) { return gw0[i]; },
-      [&](int i, uint32_t v) {
-        if ((i & 63) < 62) lds[(i >> 6) * 62 + (i & 63)] = v;
-      });
-  // |E| <= 3 L^3 fits 32 bits: the low word of each int64 energy
   const uint32_t *E0 = (const uint32_t *)(w.E + (size_t)w.chain0 * K);
   const uint32_t *S0 = (const uint32_t *)(w.slot_of_temp + (size_t)w.chain0 * K);
+  constexpr int UF = (PT_FUSED_KMAX - 1) * 48 / 64 + 1, UW = PT_CHAINS_PER_ITEM,
+                UE = (PT_CHAINS_PER_ITEM * PT_FUSED_KMAX + 63) / 64;
+  uint32_t vF[UF], vW[UW], vE[UE], vS[UE];
+  load_words<64>(nF, [&](int i) { return F32[i]; }, vF);
+  const int32_t sg_t = t < K - 1 ? w.sgn[t] : 0;
+  load_words<64>(nW, [&](int i) { return gw0[i]; }, vW);
+  load_words<64>(nE, [&](int i) { return E0[2 * i]; }, vE);
+  load_words<64>(nE, [&](int i) { return S0[i]; }, vS);
+  put_words<64>(nF, vF, [&](int i, uint32_t v) { ((uint32_t *)Fl)[i] = v; });
+  if (t < K - 1) sgl[t] = sg_t;
+  put_words<64>(nW, vW, [&](int i, uint32_t v) {
+    if ((i & 63) < 62) lds[(i >> 6) * 62 + (i & 63)] = v;
+  });
   int32_t *EsAll = (int32_t *)(lds + 64 * 62);
   int32_t *soAll = (int32_t *)(lds + 64 * 62 + 64 * kmax);
-  stage_words<8>(
-      nch * K, [&](int i) { return E0[2 * i]; },
-      [&](int i, uint32_t v) {
-        const int c = i / K;
-        EsAll[c * kmax + (i - c * K)] = (int32_t)v;
-      });
-  stage_words<8>(
-      nch * K, [&](int i) { return S0[i]; },
-      [&](int i, uint32_t v) {
-        const int c = i / K;
-        soAll[c * kmax + (i - c * K)] = (int32_t)v;
-      });
+  put_words<64>(nE, vE, [&](int i, uint32_t v) {
+    const int c = i / K;
+    EsAll[c * kmax + (i - c * K)] = (int32_t)v;
+  });
+  put_words<64>(nE, vS, [&](int i, uint32_t v) {
+    const int c = i / K;
+    soAll[c * kmax + (i - c * K)] = (int32_t)v;
+  });
   __syncthreads();
   if (t >= nch) return;
   const int ch = w.chain0 + t;
@@ -2268,26 +2333,21 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
   // only (Sc, Ec) does
   int Sc = so[0];
   int32_t Ec = Es[Sc];
+  int pos = (int)ring[61];
   for (int i = 0; i + 1 < K; i++) {
     const int a = Sc, b = so[i + 1];
     const int32_t Eb = Es[b];
     const int32_t D = Eb - Ec;
-    const uint32_t r = ptw_next(ring);
+    const uint32_t r = ptw_draw(ring, pos);
     const int sd = D > 0 ? 1 : (D < 0 ? -1 : 0);
     bool accept;
-    if (w.sgn[i] * sd <= 0) {
+    if (sgl[i] * sd <= 0) {
       accept = true;
     } else {
       const uint32_t aD = (uint32_t)(D < 0 ? -D : D);
       uint64_t T = 0;
       if (aD < (1u << 24)) {
-        T = 1ull << 32;
-        const uint64_t *Fi = Fl + i * 24;
-        for (uint32_t m = aD; m; m &= m - 1) {
-          const int bb = __ffs(m) - 1;
-          const uint64_t f = Fi[bb];
-          T = __umul64hi(T, f) << 32 | ((T * f) >> 32);
-        }
+        T = pt_threshold(Fl + i * 24, aD);
       }
       accept = (uint64_t)r < T;
     }
@@ -2301,6 +2361,7 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
     }
   }
   so[K - 1] = Sc;
+  ring[61] = (uint32_t)pos;
   // each counter belongs to this thread alone; atomics whose result is not
   // used leave the thread without a dependent load per accepted swap
   if (w.accepts)
@@ -2512,7 +2573,7 @@ hipError_t launch_pt(const int64_t *E, int32_t *slot_of_temp, int32_t *temp_of_s
 hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st,
                            uint64_t *const *done, const int32_t *cap, int ncnt, int nsweeps) {
   if (nworks <= 0) return hipSuccess;
-  const size_t lds = (size_t)(64 * 62 + 128 * kmax) * 4 + (size_t)(kmax > 1 ? kmax - 1 : 1) * 24 * 8;
+  const size_t lds = (size_t)(64 * 62 + 128 * kmax) * 4 + (size_t)(kmax > 1 ? kmax - 1 : 1) * (24 * 8 + 4);
   hipLaunchKernelGGL(pt_fused_kernel, dim3(nworks), dim3(64), lds, st, works, kmax, done, cap, ncnt,
                      nsweeps);
   return hipGetLastError();

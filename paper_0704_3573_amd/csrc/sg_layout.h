@@ -256,7 +256,12 @@ struct Work {
 constexpr uint64_t STATIC_SCRATCH_BYTES = 2u << 20;
 constexpr int MAX_DEVICES = 64;
 
-// Parallel-tempering work of one workgroup: up to 64 chains of one job.
+// Fused parallel tempering: chains per workgroup, and the largest number of
+// temperatures it serves (more take the unfused kernel).
+constexpr int PT_CHAINS_PER_ITEM = 16;
+constexpr int PT_FUSED_KMAX = 64;
+
+// Parallel-tempering work of one workgroup: up to PT_CHAINS_PER_ITEM chains of one job.
 struct PtWork {
   const int64_t *E;          // [C] energy per slot
   int32_t *slot_of_temp;     // [chains][K]
