@@ -251,8 +251,9 @@ struct Work {
 };
 
 // Size of the static device scratch of the no-allocation batch run (launch
-// tables only: about 112 bytes per work item, 12 per job, 72 per 64 chains),
-// and the number of devices whose scratch address the library keeps.
+// tables only: about 112 bytes per work item, 12 per job, 72 per
+// parallel-tempering work item of up to PT_CHAINS_PER_ITEM chains), and the
+// number of devices whose scratch address the library keeps.
 constexpr uint64_t STATIC_SCRATCH_BYTES = 2u << 20;
 constexpr int MAX_DEVICES = 64;
 
