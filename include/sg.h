@@ -187,6 +187,19 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
  * of sec. 2.2 / Eq. 4 on the host and uploads them. (sync) */
 int sg_job_set_betas(sg_job *job, const double *betas, void *stream);
 
+/* Lanes serving one Parisi-Rapuano wheel in the 3D Potts kernels: sec. 3.3
+ * lets one wheel emit many numbers at once (its lags reach back at least 24
+ * outputs), so S lanes may form its outputs k = k0 + S s + l together.  The
+ * numbers, their order and every result are the same for every S; only the
+ * launch shape changes (S NW lanes per copy).  Defaults: 8 at L = 16, 4 at
+ * L = 8, 24, 32, 2 at L = 40, 48, 1 otherwise and for the other models.
+ * Alternative: 4 at L = 16 (fewer instructions per update, half the lanes).
+ * Any other value: SG_E_INVALID.  The job's own launch plan is rebuilt and
+ * uploaded on `stream` (no sweep of the job may be in flight on another
+ * stream); batches holding the job re-plan at their next run. (sync) */
+int sg_job_set_wheel_lanes(sg_job *job, int32_t lanes, void *stream);
+int sg_job_wheel_lanes(sg_job *job, int32_t *lanes);
+
 /* Run n sweeps of every copy: checkerboard half-sweeps (sec. 3.1), each site
  * update drawing one Parisi-Rapuano number (sec. 3.3, Eq. 5) and accepting
  * by the integer rule of sec. 2.2 / Eq. 4; parallel-tempering steps (sec.

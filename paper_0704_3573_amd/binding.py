@@ -34,7 +34,7 @@ EXPORTS = (
     "sg_batch_set_timing", "sg_batch_sweep_ms", "sg_batch_set_budget", "sg_batch_get_budget",
     "sg_batch_destroy", "sg_generate", "sg_threshold_row", "sg_pt_factors", "sg_job_sweep_beta",
     "sg_job_checkpoint_bytes", "sg_job_checkpoint", "sg_job_restore", "sg_batch_run_static",
-    "sg_batch_set_period_cap",
+    "sg_batch_set_period_cap", "sg_job_set_wheel_lanes", "sg_job_wheel_lanes",
 )
 
 
@@ -72,6 +72,8 @@ def lib():
         L.sg_job_create.argtypes = [vp, C.POINTER(Spec), vp, vp, vp, vp, vp, vp, u64, vp, u64, vp,
                                     C.POINTER(vp)]
         L.sg_job_set_betas.argtypes = [vp, vp, vp]
+        L.sg_job_set_wheel_lanes.argtypes = [vp, C.c_int32, vp]
+        L.sg_job_wheel_lanes.argtypes = [vp, C.POINTER(C.c_int32)]
         L.sg_job_sweep.argtypes = [vp, u64, vp]
         L.sg_job_measure.argtypes = [vp, vp, vp, vp]
         L.sg_job_energies.argtypes = [vp, vp, vp]
@@ -256,6 +258,14 @@ class Job:
 
     def sweep(self, n: int, stream=None):
         _chk(lib().sg_job_sweep(self.h, n, _stream(stream)))
+
+    def set_wheel_lanes(self, lanes: int, stream=None):
+        _chk(lib().sg_job_set_wheel_lanes(self.h, int(lanes), _stream(stream)))
+
+    def wheel_lanes(self) -> int:
+        n = C.c_int32()
+        _chk(lib().sg_job_wheel_lanes(self.h, C.byref(n)))
+        return n.value
 
     def sweep_beta(self, beta: float, n: int, stream=None):
         _chk(lib().sg_job_sweep_beta(self.h, float(beta), n, _stream(stream)))

@@ -199,10 +199,10 @@ static Geom geom_of(int model, int L) {
 static int wheel_lanes(int model, int L) {
   return model == SG_POTTS || model == SG_GPOTTS ? sg::potts_wheel_lanes(L) : 1;
 }
-static int launch_group(int model, int L) {
+static int launch_group(int model, int L, int wl) {
   if (model == SG_ISING && L <= 4) return sg::LAUNCH_ISING_SMALL;
-  if (wheel_lanes(model, L) >= 4) return model == SG_POTTS ? sg::LAUNCH_POTTS_QUAD : sg::LAUNCH_GPOTTS_QUAD;
-  if (wheel_lanes(model, L) == 2) return model == SG_POTTS ? sg::LAUNCH_POTTS_PAIR : sg::LAUNCH_GPOTTS_PAIR;
+  if (wl >= 4) return model == SG_POTTS ? sg::LAUNCH_POTTS_QUAD : sg::LAUNCH_GPOTTS_QUAD;
+  if (wl == 2) return model == SG_POTTS ? sg::LAUNCH_POTTS_PAIR : sg::LAUNCH_GPOTTS_PAIR;
   return model;
 }
 
@@ -286,14 +286,16 @@ struct sg_job {
   int tpb;
   size_t lds;
   uint64_t sweeps_done;
+  int wl = 1;         // lanes per wheel
+  uint64_t gen = 0;   // changes of the job's launch shape (lanes per wheel)
 
   template <class T>
   T *at(uint64_t off) const {
     return (T *)(arena + off);
   }
   uint64_t *done_ptr() const { return at<uint64_t>(lay.done); }
-  int lanes() const { return g.NW * wheel_lanes(sp.model, L); }  // lanes per copy
-  int group() const { return launch_group(sp.model, L); }       // fused launch of the job
+  int lanes() const { return g.NW * wl; }                  // lanes per copy
+  int group() const { return launch_group(sp.model, L, wl); }  // fused launch of the job
 };
 
 // lanes and LDS bytes of a work item of G copies
@@ -361,6 +363,7 @@ static void make_items(const sg_job *j, int G, std::vector<Work> &out) {
     w.spins_bytes = (uint32_t)j->lay.spins_bytes;
     w.J_bytes = (uint32_t)j->lay.J_bytes;
     w.wheels_bytes = (uint32_t)j->lay.wheels_bytes;
+    w.wl = j->wl;
     w.done = j->done_ptr();
     w.M = j->sp.model == SG_ISING_GEN ? j->at<int64_t>(j->lay.Mf) : nullptr;
     out.push_back(w);
@@ -394,6 +397,23 @@ static void xcd_order(std::vector<Work> &v) {
   }
 }
 
+
+// the job's own launch plan (job sweeps outside batches), uploaded on st
+static int own_plan(sg_job *j, hipStream_t st) {
+  int tpb = 512;
+  if (j->lanes() > tpb) tpb = j->lanes();
+  const int G = copies_per_item(j, tpb);
+  if (G < 1 || item_lds(j, 1) > (size_t)j->ctx->max_lds)
+    return fail(SG_E_UNSUPPORTED, "one copy of L = %d needs more LDS than the device offers", j->L);
+  j->works.clear();
+  make_items(j, G, j->works);
+  xcd_order(j->works);
+  j->tpb = ((G * j->lanes() + 63) / 64) * 64;
+  j->lds = item_lds(j, G);
+  HIPCHK(hipMemcpyAsync(j->at<void>(j->lay.works), j->works.data(), j->works.size() * sizeof(Work),
+                        hipMemcpyHostToDevice, st));
+  return SG_OK;
+}
 
 static void make_pt_works(const sg_job *j, std::vector<PtWork> &out) {
   for (int c0 = 0; c0 < j->chains; c0 += PT_CHAINS_PER_ITEM) {
@@ -946,18 +966,9 @@ int sg_job_create(sg_ctx *ctx, const sg_job_spec *spec, const double *betas, con
   HIPCHK(hipMemcpyAsync(j->at<void>(lay.done), &j->sweeps_done, 8, hipMemcpyHostToDevice, st));
   std::vector<uint8_t> zero((size_t)(lay.done - lay.E), 0);  // E, Q, accepts
   HIPCHK(hipMemcpyAsync(j->at<void>(lay.E), zero.data(), zero.size(), hipMemcpyHostToDevice, st));
-  // own launch plan
-  int tpb = 512;
-  if (j->lanes() > tpb) tpb = j->lanes();
-  int G = copies_per_item(j, tpb);
-  if (G < 1 || item_lds(j, 1) > (size_t)ctx->max_lds)
-    return fail(SG_E_UNSUPPORTED, "one copy of L = %d needs more LDS than the device offers", spec->L);
-  make_items(j, G, j->works);
-  xcd_order(j->works);
-  j->tpb = ((G * j->lanes() + 63) / 64) * 64;
-  j->lds = item_lds(j, G);
-  HIPCHK(hipMemcpyAsync(j->at<void>(lay.works), j->works.data(), j->works.size() * sizeof(Work),
-                        hipMemcpyHostToDevice, st));
+  j->wl = wheel_lanes(spec->model, spec->L);
+  rc = own_plan(j, st);
+  if (rc) return rc;
   std::vector<PtWork> ptw;
   make_pt_works(j, ptw);
   HIPCHK(hipMemcpyAsync(j->at<void>(lay.ptworks), ptw.data(), ptw.size() * sizeof(PtWork),
@@ -1358,6 +1369,34 @@ int sg_job_destroy(sg_job *job) {
   return SG_OK;
 }
 
+int sg_job_set_wheel_lanes(sg_job *job, int32_t lanes, void *stream) {
+  GUARD_BEGIN
+  if (!job) return fail(SG_E_INVALID, "job is NULL");
+  const bool potts3 = job->sp.model == SG_POTTS || job->sp.model == SG_GPOTTS;
+  if (!(potts3 ? sg::potts_lanes_ok(job->L, lanes) : lanes == 1))
+    return fail(SG_E_INVALID, "%d lanes per wheel are not built for model %d at L = %d", (int)lanes,
+                (int)job->sp.model, job->L);
+  if (lanes == job->wl) return SG_OK;
+  hipStream_t st = S_(stream);
+  const int old = job->wl;
+  job->wl = lanes;
+  int rc = own_plan(job, st);
+  if (rc) {
+    job->wl = old;
+    return rc;
+  }
+  job->gen++;
+  HIPCHK(hipStreamSynchronize(st));
+  return SG_OK;
+  GUARD_END
+}
+
+int sg_job_wheel_lanes(sg_job *job, int32_t *lanes) {
+  if (!job || !lanes) return fail(SG_E_INVALID, "NULL argument");
+  *lanes = job->wl;
+  return SG_OK;
+}
+
 }  // extern "C"
 
 // ----------------------------------------------------------------- batch --
@@ -1395,6 +1434,7 @@ struct sg_batch {
   int block_req = 0;  // 0 = automatic
   // plan
   bool dirty = true;
+  std::vector<uint64_t> gens;     // the jobs' launch shapes the plan was made for
   int tpb = 0;                    // the batch's block size
   std::vector<Launch> launches;   // fused launches of a period
   Work *d_items = nullptr;
@@ -1444,7 +1484,7 @@ static double idle_fraction(const sg_batch *b, int tpb) {
     const int G = copies_per_item(j, tpb);
     if (G < 1) return 2.0;
     const double items = std::ceil((double)j->C / G);
-    const double per_lane = (double)j->g.RHO / wheel_lanes(j->sp.model, j->L);  // draws per lane, in L/2
+    const double per_lane = (double)j->g.RHO / j->wl;  // draws per lane, in L/2
     used += (double)j->C * j->lanes() * per_lane;
     total += items * item_tpb(j, tpb) * per_lane;
   }
@@ -1503,8 +1543,16 @@ static int plan_items(const sg_batch *b, int &tpb_out, std::vector<Launch> &laun
   return SG_OK;
 }
 
+// a job of the batch changed its launch shape since the plan was made
+static bool shapes_changed(const sg_batch *b) {
+  if (b->gens.size() != b->jobs.size()) return true;
+  for (size_t i = 0; i < b->jobs.size(); i++)
+    if (b->jobs[i]->gen != b->gens[i]) return true;
+  return false;
+}
+
 static int plan(sg_batch *b) {
-  if (!b->dirty) return SG_OK;
+  if (!b->dirty && !shapes_changed(b)) return SG_OK;
   int rc = wait_enqueued(b);
   if (rc) return rc;
   drop_graphs(b);
@@ -1559,6 +1607,8 @@ static int plan(sg_batch *b) {
   }
   b->run_cap.assign(b->jobs.size(), 0x7FFFFFFF);
   b->tpb = tpb;
+  b->gens.clear();
+  for (sg_job *j : b->jobs) b->gens.push_back(j->gen);
   b->dirty = false;
   return SG_OK;
 }

@@ -1786,7 +1786,12 @@ template <bool GLASSY>
 DEV void potts_quad_dispatch(const Work &w, uint32_t *lds) {
   switch (w.L) {
     case 8: potts_multi_run<8, GLASSY, 4>(w, lds); break;
-    case 16: potts_multi_run<16, GLASSY, 8>(w, lds); break;
+    case 16:
+      if (w.wl == 4)
+        potts_multi_run<16, GLASSY, 4>(w, lds);
+      else
+        potts_multi_run<16, GLASSY, 8>(w, lds);
+      break;
     case 24: potts_multi_run<24, GLASSY, 4>(w, lds); break;
     case 32: potts_multi_run<32, GLASSY, 4>(w, lds); break;
     default: break;

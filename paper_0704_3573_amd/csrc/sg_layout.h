@@ -174,6 +174,11 @@ constexpr int POTTS_MAX_TPB = 512;
 SG_HD constexpr int potts_wheel_lanes(int L) {
   return L == 16 ? 8 : (L == 8 || L == 24 || L == 32 ? 4 : (L == 40 || L == 48 ? 2 : 1));
 }
+// Lanes per wheel a 3D Potts job may choose instead (the numbers drawn and
+// every result stay the same): four at L = 16, where eight is the default
+// (eight lanes fill more SIMDs when the batch is small, four spend fewer
+// instructions per update when the device is full).
+SG_HD constexpr bool potts_lanes_ok(int L, int S) { return S == potts_wheel_lanes(L) || (L == 16 && S == 4); }
 // Workgroups of the two-lanes-per-wheel kernels hold up to 768 threads.
 constexpr int POTTS_PAIR_MAX_TPB = 768;
 // Launch groups of the several-lanes-per-wheel kernels (+-J and glassy),
@@ -245,7 +250,7 @@ struct Work {
   int32_t L, algo, model, copy0, ncopies, C, RK;
   int32_t nsweeps_cap;           // the item runs min(launch sweeps, cap) sweeps
   uint32_t spins_bytes, J_bytes, wheels_bytes;  // extents (buffer range checks)
-  uint32_t pad;
+  int32_t wl;                    // lanes per wheel (3D Potts kernels)
   const uint64_t *done;          // sweeps already performed by the job (device)
   int64_t *M;                    // [C] field sum per slot (Ising-like models), else null
 };
