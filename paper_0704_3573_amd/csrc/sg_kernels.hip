@@ -2189,31 +2189,16 @@ DEV uint32_t ptw_next(uint32_t *w) {
   return out;
 }
 
-// The threshold of |D| = m (0 < m < 2^24): from T = 2^32, for each set bit
-// b of m, lowest first, T <- floor(T Fi[b] / 2^32).  With T = Th 2^32 + Tl
-// and Fi[b] = fh 2^32 + fl, both at most 2^32 (so Th = 1 forces Tl = 0 and
-// fh = 1 forces fl = 0), the step is exact as: T = 2^32 if Th = fh = 1, fl
-// if only Th = 1, T if only fh = 1, else the high word of Tl fl (one 32-bit
-// multiply).  The factors of the next two set bits are read while one
-// multiplies.
-DEV uint64_t pt_threshold(const uint64_t *Fi, uint32_t m) {
-  uint32_t Th = 1, Tl = 0;
-  uint32_t m1 = m & (m - 1);  // the bits after the lowest
-  uint64_t f0 = Fi[m ? __ffs(m) - 1 : 0];
-  uint64_t f1 = Fi[m1 ? __ffs(m1) - 1 : 0];
-  while (m) {
-    const uint32_t m2 = m1 & (m1 - 1);
-    const uint64_t f2 = Fi[m2 ? __ffs(m2) - 1 : 0];
-    const uint32_t fl = (uint32_t)f0, fh = (uint32_t)(f0 >> 32);
-    const uint32_t p = __umulhi(Tl, fl);
-    Tl = Th ? fl : (fh ? Tl : p);
-    Th &= fh;
-    f0 = f1;
-    f1 = f2;
-    m = m1;
-    m1 = m2;
-  }
-  return (uint64_t)Th << 32 | Tl;
+// The threshold of |D| (0 < |D| < 2^24): from T = 2^32, for each set bit b
+// of |D|, lowest first, T <- floor(T Fi[b] / 2^32).  No factor exceeds
+// 2^32 and one equal to 2^32 leaves T as it is, so with m = the set bits
+// whose factor is below 2^32 (m != 0) the first step sets T to that factor
+// and every later one is the high word of a 32 x 32-bit product; m = 0
+// leaves T = 2^32.  F2: the pair's factors as (low, high) word pairs.
+DEV uint32_t pt_threshold(const uint32_t *F2, uint32_t m) {
+  uint32_t T = F2[2 * (__ffs(m) - 1)];
+  for (m &= m - 1; m; m &= m - 1) T = __umulhi(T, F2[2 * (__ffs(m) - 1)]);
+  return T;
 }
 
 // ptw_next with the position held by the caller (in a register)
@@ -2293,6 +2278,7 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
   int32_t *so = (int32_t *)(lds + 64 * 62 + 64 * kmax) + t * kmax;  // slot by temperature
   uint64_t *Fl = (uint64_t *)(lds + 64 * 62 + 128 * kmax);       // [K-1][24]
   int32_t *sgl = (int32_t *)(Fl + (kmax - 1) * 24);              // [K-1] sign of dbeta
+  uint32_t *onem = (uint32_t *)(sgl + (kmax - 1));               // [K-1] bits whose factor is 2^32
   // one staging pass: every load of the factor table (as 32-bit halves),
   // the signs and the wheels (64 words per chain in memory, 62 used),
   // energies (|E| <= 3 L^3: the low word of each int64) and permutations of
@@ -2329,6 +2315,13 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
     soAll[c * kmax + (i - c * K)] = (int32_t)v;
   });
   __syncthreads();
+  if (t < K - 1) {
+    const uint32_t *Fh = (const uint32_t *)(Fl + t * 24) + 1;
+    uint32_t m = 0;
+    for (int bb = 0; bb < 24; bb++) m |= (Fh[2 * bb] != 0u ? 1u : 0u) << bb;
+    onem[t] = m;
+  }
+  __syncthreads();
   if (t >= nch) return;
   const int ch = w.chain0 + t;
   uint64_t accepted = 0;  // bit i: the swap of temperatures i, i + 1 was accepted
@@ -2350,11 +2343,9 @@ __global__ __launch_bounds__(64) void pt_fused_kernel(const PtWork *__restrict__
       accept = true;
     } else {
       const uint32_t aD = (uint32_t)(D < 0 ? -D : D);
-      uint64_t T = 0;
-      if (aD < (1u << 24)) {
-        T = pt_threshold(Fl + i * 24, aD);
-      }
-      accept = (uint64_t)r < T;
+      const uint32_t m = aD & ~onem[i];
+      // |D| >= 2^24 gives T = 0
+      accept = aD < (1u << 24) && (m == 0 || r < pt_threshold((const uint32_t *)(Fl + i * 24), m));
     }
     if (accept) {
       so[i] = b;
@@ -2578,7 +2569,7 @@ hipError_t launch_pt(const int64_t *E, int32_t *slot_of_temp, int32_t *temp_of_s
 hipError_t launch_pt_fused(const PtWork *works, int nworks, int kmax, hipStream_t st,
                            uint64_t *const *done, const int32_t *cap, int ncnt, int nsweeps) {
   if (nworks <= 0) return hipSuccess;
-  const size_t lds = (size_t)(64 * 62 + 128 * kmax) * 4 + (size_t)(kmax > 1 ? kmax - 1 : 1) * (24 * 8 + 4);
+  const size_t lds = (size_t)(64 * 62 + 128 * kmax) * 4 + (size_t)(kmax > 1 ? kmax - 1 : 1) * (24 * 8 + 8);
   hipLaunchKernelGGL(pt_fused_kernel, dim3(nworks), dim3(64), lds, st, works, kmax, done, cap, ncnt,
                      nsweeps);
   return hipGetLastError();
